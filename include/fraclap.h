@@ -1,0 +1,179 @@
+/*
+ * fraclap -- MI355X (gfx950) library for the spectral fractional Poisson
+ * problem by eigenfunction expansion (Carlson, Kirby, Sundar, "A Scalable
+ * Framework for Solving Fractional Diffusion Equations").
+ *
+ * The method (Section "Method"): with the Galerkin pencil
+ *     K_ij = <grad e_i, grad e_j>,   M_ij = <e_i, e_j>      (eq. discrete_laplace)
+ * compute ALL n generalized eigenpairs K phi_k = theta_k M phi_k with
+ * phi_j^T M phi_k = delta_jk (orthonormality: Section "Post-processing"), then
+ * for any forcing f and fractional order alpha
+ *     v = sum_k theta_k^(-alpha/2) <f, phi_k> phi_k,   <f, phi_k> = phi_k^T M f
+ * (the equations for g and v in Section "Method"; the basis is computed once
+ * and reused for every forcing, same section).
+ *
+ * Conventions
+ *  - Dense matrices are column-major; element (i, j) of an array with leading
+ *    dimension ld is at X[i + j*ld].  All floating point is IEEE double unless
+ *    a function says otherwise.
+ *  - "device" pointers are HIP device memory (e.g. the data pointer of a torch
+ *    tensor on cuda:N); "host" pointers are ordinary process memory.  Device
+ *    pointers are borrowed for the duration of the stream-ordered work; host
+ *    inputs are copied before the call returns.  Output buffers are always
+ *    allocated by the caller.  The library owns K, M, theta, V and its
+ *    workspace until fl_op_destroy.
+ *  - Every call returns FL_OK (0) or a negative status; the message of the
+ *    last failure is available from fl_last_error.  Argument validation runs
+ *    before any device work, so a rejected call leaves all buffers untouched.
+ *  - Synchrony: fl_assemble, fl_op_from_dense, fl_eigensolve and the fl_d*
+ *    stage calls return after their device work has completed;
+ *    fl_apply_fractional and fl_grad_apply are asynchronous on the context
+ *    stream.
+ *  - Threading: one context per host thread.
+ */
+#ifndef FRACLAP_H
+#define FRACLAP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fl_ctx fl_ctx; /* device, borrowed stream, last error */
+typedef struct fl_op fl_op;   /* one discretised domain: K, M; after eigensolve theta, V */
+
+enum {
+    FL_OK = 0,
+    FL_EINVAL = -1,   /* bad argument (sizes, NaN/Inf input, bad mesh, alpha with theta_1 <= 0) */
+    FL_ENOMEM = -2,   /* device allocation failed */
+    FL_EHIP = -3,     /* HIP runtime error */
+    FL_ENOTSPD = -4,  /* M (or a matrix to factor) is not positive definite; info->index = pivot */
+    FL_ENOCONV = -5,  /* an iterative stage did not converge; info->index = stage */
+    FL_ESTATE = -6    /* call out of order (apply before eigensolve) */
+};
+enum { FL_ELEM_P1 = 3, FL_ELEM_Q1 = 4 };
+enum { FL_FP64 = 0, FL_MIXED = 1 };
+
+/* Eigensolve stages, in order (indices into fl_eig_info.stage_ms). */
+enum {
+    FL_STAGE_POTRF = 0, /* M = L L^T */
+    FL_STAGE_SYGST = 1, /* C = L^-1 K L^-T */
+    FL_STAGE_SY2SB = 2, /* C -> symmetric band (Householder panels, MFMA updates) */
+    FL_STAGE_SB2ST = 3, /* band -> tridiagonal (bulge chasing) */
+    FL_STAGE_STEDC = 4, /* tridiagonal divide and conquer */
+    FL_STAGE_Q2 = 5,    /* back-transform by the bulge-chasing reflectors */
+    FL_STAGE_Q1 = 6,    /* back-transform by the band-reduction reflectors */
+    FL_STAGE_TRSM = 7,  /* V = L^-T Z */
+    FL_STAGE_REFINE = 8,/* mixed mode: eigenpair refinement */
+    FL_NSTAGES = 9
+};
+
+typedef struct fl_eig_opts {
+    int32_t band;             /* band width of the two-stage reduction (0 = default 64) */
+    int32_t leaf;             /* divide-and-conquer leaf size (0 = default 32) */
+    int32_t refine_max_iters; /* mixed mode: refinement sweeps (-1 = default 2) */
+    double refine_tol;        /* mixed mode: stop when max |r_ij| below this (0 = default 1e-13) */
+} fl_eig_opts;
+
+typedef struct fl_eig_info {
+    int32_t status;           /* FL_OK or the failing status */
+    int64_t index;            /* FL_ENOTSPD: 1-based pivot; FL_ENOCONV: stage */
+    int32_t refine_iters;     /* mixed mode: sweeps done */
+    double refine_resid;      /* mixed mode: last max |I - X^T M X| entry */
+    double stage_ms[FL_NSTAGES]; /* per-stage device time (HIP events) */
+    double total_ms;
+    double flops_nominal;     /* 9 n^3 */
+} fl_eig_info;
+
+/* ---- context ------------------------------------------------------------ */
+/* device: HIP ordinal.  hip_stream: a hipStream_t to borrow (NULL = the
+ * legacy default stream).  *out receives the context. */
+int fl_ctx_create(int device, void *hip_stream, fl_ctx **out);
+int fl_ctx_set_stream(fl_ctx *ctx, void *hip_stream);
+void fl_ctx_destroy(fl_ctx *ctx);
+/* Message for the last non-OK status on this context ("" if none). */
+const char *fl_last_error(const fl_ctx *ctx);
+
+/* ---- input stage: the discretised pencil (eq. discrete_laplace) ----------
+ * Assemble K and M for a mesh with homogeneous Dirichlet data (Section
+ * "Accuracy"): Dirichlet nodes are eliminated, interior nodes become DOFs in
+ * node order.  elem = FL_ELEM_Q1 (4 nodes, counter-clockwise, axis-aligned
+ * rectangles) or FL_ELEM_P1 (3 nodes, counter-clockwise).  Exact element
+ * integrals (consistent mass).  xy: host, n_nodes x 2 row-major (x, y);
+ * conn: host, n_elem x elem row-major; dirichlet: host, n_nodes flags.
+ * *n_dof receives n; dof_of_node (host, n_nodes, may be NULL) receives the
+ * DOF index of each node or -1.  FL_EINVAL for NaN/Inf coordinates, node
+ * indices out of range, clockwise or degenerate elements, non-rectangular Q1
+ * elements, or no interior node. */
+int fl_assemble(fl_ctx *ctx, int elem, int64_t n_nodes, const double *xy, int64_t n_elem,
+                const int32_t *conn, const uint8_t *dirichlet, fl_op **out, int64_t *n_dof,
+                int64_t *dof_of_node);
+/* Wrap an existing symmetric pencil.  K, M: n x n, leading dimension ld,
+ * host (on_device = 0) or device (1).  FL_EINVAL for NaN/Inf entries. */
+int fl_op_from_dense(fl_ctx *ctx, int64_t n, const double *K, const double *M, int64_t ld, int on_device,
+                     fl_op **out);
+int64_t fl_op_n(const fl_op *op);
+/* Copy K and/or M (either may be NULL) out to host or device memory. */
+int fl_op_matrices(const fl_op *op, double *K, double *M, int64_t ld, int on_device);
+void fl_op_destroy(fl_op *op);
+
+/* ---- the eigensolve ------------------------------------------------------
+ * All n pairs of K phi = theta M phi, theta ascending, V^T M V = I
+ * (eq. discrete_laplace, Section "Post-processing").  Stages: FL_STAGE_*.
+ * precision = FL_FP64 runs every stage in FP64; FL_MIXED runs the band
+ * reduction and both back-transforms in FP32 on the matrix cores and restores
+ * FP64 accuracy by eigenpair refinement.  opts/info may be NULL.
+ * FL_ENOTSPD if M is not positive definite (info->index = pivot). */
+int fl_eigensolve(fl_op *op, int precision, const fl_eig_opts *opts, fl_eig_info *info);
+/* Copy theta (n) and V (n x n, ld ldv; V may be NULL) out. */
+int fl_eigenpairs(const fl_op *op, double *theta, double *V, int64_t ldv, int on_device);
+/* Install eigenpairs computed elsewhere (resume, or testing the apply path
+ * alone).  theta must be positive. */
+int fl_op_set_eigenpairs(fl_op *op, const double *theta, const double *V, int64_t ldv, int on_device);
+
+/* ---- spectral application (the equation for v, Section "Method") ---------
+ * F: device, n x nf (ld ldf).  alpha: host, na orders in [0, 2].
+ * paired = 0: U (device, n x nf*na, ld ldu) column j + i*nf = v(alpha_i, f_j).
+ * paired = 1: requires na == nf; column b = v(alpha_b, f_b).
+ * Computes G = M F, C = V^T G, W_ki = theta_k^(-alpha_i/2) (alpha = 0 gives
+ * exactly 1), U = V (W o C) with the scaling fused into the GEMM's operand
+ * staging.  FL_ESTATE before an eigensolve; FL_EINVAL for alpha outside
+ * [0, 2] or non-finite. */
+int fl_apply_fractional(fl_op *op, int64_t nf, const double *F, int64_t ldf, int64_t na, const double *alpha,
+                        int paired, double *U, int64_t ldu);
+/* Adjoint of the paired map (f_b, alpha_b) -> u_b, b < nb.  GU = dL/du
+ * (device n x nb).  With c = V^T M f, w = theta^(-alpha/2), p = V^T GU:
+ *   GF = dL/df = M V (w o p)            (device n x nb, ld ldgf; may be NULL)
+ *   galpha_b = dL/dalpha_b = sum_k p_k c_k w_k (-ln(theta_k)/2)
+ *                                      (galpha: host nb; may be NULL).
+ * Synchronises the stream when galpha is requested. */
+int fl_grad_apply(fl_op *op, int64_t nb, const double *F, int64_t ldf, const double *alpha, const double *GU,
+                  int64_t ldgu, double *GF, int64_t ldgf, double *galpha);
+
+/* ---- stage entry points (device pointers; synchronous) -------------------
+ * Exposed so that each stage can be checked on its own. */
+/* C = alpha op(A) op(B) + beta C, FP64 on the matrix cores.  ta/tb: 0 = N, 1 = T. */
+int fl_dgemm(fl_ctx *ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha, const double *A,
+             int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc);
+/* In-place Cholesky A = L L^T of the lower triangle; the strict upper
+ * triangle is left undefined.  *info = 0 or the 1-based failing pivot. */
+int fl_dpotrf(fl_ctx *ctx, int64_t n, double *A, int64_t lda, int64_t *info);
+/* K := L^-1 K L^-T (full symmetric storage in and out); L lower from fl_dpotrf. */
+int fl_dsygst(fl_ctx *ctx, int64_t n, const double *L, int64_t ldl, double *K, int64_t ldk);
+/* All eigenpairs of the symmetric tridiagonal (d: n diagonal, e: n-1
+ * off-diagonal; both device, overwritten): d := eigenvalues ascending,
+ * Z (n x n, ld ldz) := orthonormal eigenvectors.  Divide and conquer. */
+int fl_dstedc(fl_ctx *ctx, int64_t n, double *d, double *e, double *Z, int64_t ldz);
+/* Two-stage tridiagonalisation of the symmetric A (full storage, destroyed):
+ * d (n), e (n-1) receive T; if Q is non-NULL it receives the orthogonal
+ * n x n Q with A = Q T Q^T. */
+int fl_dsytrd_2stage(fl_ctx *ctx, int64_t n, double *A, int64_t lda, int band, double *d, double *e, double *Q,
+                     int64_t ldq);
+/* All eigenpairs of the symmetric A (full storage, destroyed): w ascending,
+ * Z orthonormal (n x n, ld ldz). */
+int fl_dsyevd(fl_ctx *ctx, int64_t n, double *A, int64_t lda, int band, double *w, double *Z, int64_t ldz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRACLAP_H */

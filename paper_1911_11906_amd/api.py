@@ -1,0 +1,273 @@
+"""Python front end of the fraclap HIP library.
+
+PyTorch supplies device memory and the stream; every computation happens in
+the HIP kernels behind the C ABI (include/fraclap.h).  Dense matrices are
+column-major: a torch tensor X of shape (n, m) is accepted when
+X.stride(0) == 1 (e.g. ``torch.empty(m, n).t()``); helpers below produce that
+layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import sys
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FlEigInfo, FlEigOpts, FraclapError
+
+P = ctypes.c_void_p
+
+
+def colmajor(x, device=None) -> torch.Tensor:
+    """float64 CUDA tensor with column-major storage (stride(0) == 1)."""
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float64).T)).t()
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("expected a numpy array or a torch tensor")
+    if x.dim() == 1:
+        x = x[:, None]
+    dev = device if device is not None else (x.device if x.is_cuda else torch.device("cuda", 0))
+    x = x.to(device=dev, dtype=torch.float64)
+    if x.stride(0) != 1 or (x.shape[1] > 1 and x.stride(1) < x.shape[0]):
+        x = x.t().contiguous().t()
+    return x
+
+
+def empty_colmajor(n: int, m: int, device) -> torch.Tensor:
+    return torch.empty((m, n), dtype=torch.float64, device=device).t()
+
+
+def _ld(x: torch.Tensor) -> int:
+    return max(int(x.stride(1)) if x.shape[1] > 1 else int(x.shape[0]), 1)
+
+
+def _ptr(x: torch.Tensor):
+    return P(x.data_ptr())
+
+
+class Context:
+    """One device and the torch stream work is queued on."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        self.ptr = P()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = self.lib.fl_ctx_create(device, P(stream), ctypes.byref(self.ptr))
+        if rc != 0:
+            raise FraclapError(rc, "fl_ctx_create failed")
+
+    def _sync_stream(self):
+        self.lib.fl_ctx_set_stream(self.ptr, P(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self, rc: int):
+        if rc != 0:
+            raise FraclapError(rc, self.lib.fl_last_error(self.ptr).decode())
+
+    def close(self):
+        if self.ptr:
+            self.lib.fl_ctx_destroy(self.ptr)
+            self.ptr = P()
+
+    def __del__(self):
+        # no library calls while the interpreter (and the HIP runtime) shut down
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- stage calls
+    def dgemm(self, A, B, C=None, ta=False, tb=False, alpha=1.0, beta=0.0):
+        A, B = colmajor(A, self.device), colmajor(B, self.device)
+        m = A.shape[1] if ta else A.shape[0]
+        k = A.shape[0] if ta else A.shape[1]
+        n = B.shape[0] if tb else B.shape[1]
+        if C is None:
+            C = empty_colmajor(m, n, self.device)
+            beta = 0.0
+        self._sync_stream()
+        self.check(self.lib.fl_dgemm(self.ptr, int(ta), int(tb), m, n, k, alpha, _ptr(A), _ld(A), _ptr(B), _ld(B),
+                                     beta, _ptr(C), _ld(C)))
+        return C
+
+    def dpotrf(self, A):
+        """Lower Cholesky factor of A (returns a new column-major tensor)."""
+        A = colmajor(A, self.device).clone()
+        n = A.shape[0]
+        info = ctypes.c_int64(0)
+        self._sync_stream()
+        rc = self.lib.fl_dpotrf(self.ptr, n, _ptr(A), _ld(A), ctypes.byref(info))
+        if rc == _lib.FL_ENOTSPD:
+            raise FraclapError(rc, f"not positive definite at pivot {info.value}")
+        self.check(rc)
+        return torch.tril(A)
+
+    def dsygst(self, L, K):
+        L, K = colmajor(L, self.device), colmajor(K, self.device).clone()
+        self._sync_stream()
+        self.check(self.lib.fl_dsygst(self.ptr, K.shape[0], _ptr(L), _ld(L), _ptr(K), _ld(K)))
+        return K
+
+    def dstedc(self, d, e):
+        d = torch.as_tensor(d, dtype=torch.float64).to(self.device).clone()
+        e = torch.as_tensor(e, dtype=torch.float64).to(self.device).clone()
+        n = d.numel()
+        Z = empty_colmajor(n, n, self.device)
+        self._sync_stream()
+        self.check(self.lib.fl_dstedc(self.ptr, n, _ptr(d), _ptr(e), _ptr(Z), _ld(Z)))
+        return d, Z
+
+    def dsytrd_2stage(self, A, band=0, want_q=True):
+        A = colmajor(A, self.device).clone()
+        n = A.shape[0]
+        d = torch.empty(n, dtype=torch.float64, device=self.device)
+        e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=self.device)
+        Q = empty_colmajor(n, n, self.device) if want_q else None
+        self._sync_stream()
+        self.check(self.lib.fl_dsytrd_2stage(self.ptr, n, _ptr(A), _ld(A), band, _ptr(d), _ptr(e),
+                                             _ptr(Q) if want_q else None, _ld(Q) if want_q else n))
+        return d, e[: n - 1], Q
+
+    def dsyevd(self, A, band=0):
+        A = colmajor(A, self.device).clone()
+        n = A.shape[0]
+        w = torch.empty(n, dtype=torch.float64, device=self.device)
+        Z = empty_colmajor(n, n, self.device)
+        self._sync_stream()
+        self.check(self.lib.fl_dsyevd(self.ptr, n, _ptr(A), _ld(A), band, _ptr(w), _ptr(Z), _ld(Z)))
+        return w, Z
+
+
+class Operator:
+    """A discretised domain (K, M) and, after ``eigensolve``, its eigenbasis."""
+
+    def __init__(self, ctx: Context, ptr: P, dof_of_node=None):
+        self.ctx = ctx
+        self.ptr = ptr
+        self.dof_of_node = dof_of_node
+        self.n = int(ctx.lib.fl_op_n(ptr))
+        self.info = None
+
+    @classmethod
+    def assemble(cls, ctx: Context, mesh) -> "Operator":
+        xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+        conn = np.ascontiguousarray(mesh.conn, dtype=np.int32)
+        dirichlet = np.ascontiguousarray(mesh.dirichlet, dtype=np.uint8)
+        out = P()
+        n = ctypes.c_int64(0)
+        dof = np.zeros(xy.shape[0], dtype=np.int64)
+        ctx._sync_stream()
+        ctx.check(ctx.lib.fl_assemble(ctx.ptr, int(mesh.elem), xy.shape[0], xy.ctypes.data_as(P), conn.shape[0],
+                                      conn.ctypes.data_as(P), dirichlet.ctypes.data_as(P), ctypes.byref(out),
+                                      ctypes.byref(n), dof.ctypes.data_as(P)))
+        return cls(ctx, out, dof)
+
+    @classmethod
+    def from_dense(cls, ctx: Context, K, M) -> "Operator":
+        K = np.asfortranarray(K, dtype=np.float64)
+        M = np.asfortranarray(M, dtype=np.float64)
+        out = P()
+        ctx._sync_stream()
+        ctx.check(ctx.lib.fl_op_from_dense(ctx.ptr, K.shape[0], K.ctypes.data_as(P), M.ctypes.data_as(P),
+                                           K.shape[0], 0, ctypes.byref(out)))
+        return cls(ctx, out)
+
+    def close(self):
+        if self.ptr:
+            self.ctx.lib.fl_op_destroy(self.ptr)
+            self.ptr = P()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matrices(self):
+        K = empty_colmajor(self.n, self.n, self.ctx.device)
+        M = empty_colmajor(self.n, self.n, self.ctx.device)
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_op_matrices(self.ptr, _ptr(K), _ptr(M), _ld(K), 1))
+        return K, M
+
+    def eigensolve(self, precision: str = "fp64", band: int = 0, leaf: int = 0, refine_max_iters: int = -1,
+                   refine_tol: float = 0.0) -> dict:
+        prec = {"fp64": _lib.FL_FP64, "mixed": _lib.FL_MIXED}[precision]
+        opts = FlEigOpts(band, leaf, refine_max_iters, refine_tol)
+        info = FlEigInfo()
+        self.ctx._sync_stream()
+        rc = self.ctx.lib.fl_eigensolve(self.ptr, prec, ctypes.byref(opts), ctypes.byref(info))
+        self.info = info.as_dict()
+        if rc != 0:
+            raise FraclapError(rc, self.ctx.lib.fl_last_error(self.ctx.ptr).decode() + f" (index {info.index})")
+        return self.info
+
+    def eigenpairs(self, want_vectors: bool = True):
+        theta = torch.empty(self.n, dtype=torch.float64, device=self.ctx.device)
+        V = empty_colmajor(self.n, self.n, self.ctx.device) if want_vectors else None
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_eigenpairs(self.ptr, _ptr(theta), _ptr(V) if V is not None else None,
+                                                  _ld(V) if V is not None else self.n, 1))
+        return theta, V
+
+    def set_eigenpairs(self, theta, V):
+        theta = torch.as_tensor(np.asarray(theta) if isinstance(theta, np.ndarray) else theta,
+                                dtype=torch.float64).to(self.ctx.device).contiguous()
+        V = colmajor(V, self.ctx.device)
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_op_set_eigenpairs(self.ptr, _ptr(theta), _ptr(V), _ld(V), 1))
+
+    def apply(self, F, alpha, paired: bool = False, out=None) -> torch.Tensor:
+        """u = sum_k theta_k^(-alpha/2) (phi_k^T M f) phi_k.  Columns j + i*nf
+        (all pairs) or b (paired)."""
+        F = colmajor(F, self.ctx.device)
+        al = np.ascontiguousarray(np.atleast_1d(np.asarray(alpha, dtype=np.float64)))
+        nf, na = F.shape[1], al.size
+        ncol = nf if paired else nf * na
+        U = out if out is not None else empty_colmajor(self.n, ncol, self.ctx.device)
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_apply_fractional(self.ptr, nf, _ptr(F), _ld(F), na, al.ctypes.data_as(P),
+                                                        int(paired), _ptr(U), _ld(U)))
+        return U
+
+    def grad(self, F, alpha, GU, want_f: bool = True, want_alpha: bool = True):
+        F = colmajor(F, self.ctx.device)
+        GU = colmajor(GU, self.ctx.device)
+        al = np.ascontiguousarray(np.atleast_1d(np.asarray(alpha, dtype=np.float64)))
+        nb = GU.shape[1]
+        GF = empty_colmajor(self.n, nb, self.ctx.device) if want_f else None
+        ga = np.zeros(nb) if want_alpha else None
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_grad_apply(
+            self.ptr, nb, _ptr(F), _ld(F), al.ctypes.data_as(P), _ptr(GU), _ld(GU),
+            _ptr(GF) if want_f else None, _ld(GF) if want_f else self.n,
+            ga.ctypes.data_as(P) if want_alpha else None))
+        return GF, (torch.from_numpy(ga) if want_alpha else None)
+
+
+class FracApply(torch.autograd.Function):
+    """u_b = v(alpha_b, f_b) for paired columns; backward through the
+    hand-written adjoint (fl_grad_apply)."""
+
+    @staticmethod
+    def forward(ctx, op: Operator, F: torch.Tensor, alpha: torch.Tensor):
+        ctx.op = op
+        Fc = colmajor(F.detach(), op.ctx.device)
+        ctx.save_for_backward(Fc, alpha.detach())
+        U = op.apply(Fc, alpha.detach().cpu().numpy(), paired=True)
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        F, alpha = ctx.saved_tensors
+        op = ctx.op
+        GF, ga = op.grad(F, alpha.cpu().numpy(), gU, want_f=ctx.needs_input_grad[1],
+                         want_alpha=ctx.needs_input_grad[2])
+        ga_t = ga.to(alpha.device, alpha.dtype) if ga is not None else None
+        return None, GF, ga_t

@@ -1,0 +1,227 @@
+// Cholesky of the mass matrix (M = L L^T) and the triangular solves that
+// bring the pencil to standard form (C = L^-1 K L^-T) and map eigenvectors
+// back (V = L^-T Z), all in FP64.
+//
+// Recursive blocking on 128-aligned splits: every leaf is a 128 x 128
+// diagonal block, factored in LDS by one workgroup that also inverts it in
+// place.  Off-diagonal work is GEMM (matrix cores); a triangular solve at a
+// leaf is a GEMM with the stored leaf inverse.
+#include "internal.h"
+
+namespace {
+
+constexpr int LB = 128;  // leaf block
+constexpr int LT = 1024; // threads of the leaf kernel
+
+// In-place inverse of the lower-triangular LB x LB block S (column-major,
+// ld LB), last column first: X_jj = 1/L_jj, X(j+1:, j) = -X_jj X(j+1:, j+1:) L(j+1:, j).
+__device__ void invert_lower_lds(double* S, double* y, int t) {
+    for (int j = LB - 1; j >= 0; --j) {
+        double xjj = 1.0 / S[j + j * LB];
+        for (int i = j + 1 + t; i < LB; i += LT) {
+            double acc = 0.0;
+            for (int k = j + 1; k <= i; ++k) acc += S[i + k * LB] * S[k + j * LB];
+            y[i] = -xjj * acc;
+        }
+        __syncthreads();
+        for (int i = j + 1 + t; i < LB; i += LT) S[i + j * LB] = y[i];
+        if (t == 0) S[j + j * LB] = xjj;
+        __syncthreads();
+    }
+}
+
+// Factor the nb x nb (nb <= 128) diagonal block at A (ld lda) in LDS; write L
+// back (strict upper triangle of the block zeroed) and its inverse (128 x 128,
+// zero padded) to Linv.  info: first failing global pivot (1-based) if unset.
+__global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, int nb, int64_t goff,
+                                                        double* Linv, int64_t* info) {
+    __shared__ double S[LB * LB];  // column-major with ld LB (128 KB of the 160 KB LDS)
+    __shared__ double y[LB];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    for (int e = t; e < LB * LB; e += LT) {
+        int i = e % LB, j = e / LB;
+        double v;
+        if (i < nb && j < nb)
+            v = (i >= j) ? A[i + (int64_t)j * lda] : 0.0;
+        else
+            v = (i == j) ? 1.0 : 0.0;  // identity padding keeps the inverse well defined
+        S[i + j * LB] = v;
+    }
+    __syncthreads();
+    // right-looking unblocked Cholesky
+    for (int j = 0; j < nb; ++j) {
+        if (t == 0) {
+            double d = S[j + j * LB];
+            if (!(d > 0.0)) {
+                if (!bad) {
+                    bad = 1;
+                    if (*info == 0) *info = goff + j + 1;
+                }
+                d = 1.0;  // keep going with a harmless pivot; the status reports the failure
+            }
+            S[j + j * LB] = sqrt(d);
+        }
+        __syncthreads();
+        const double dj = S[j + j * LB];
+        for (int i = j + 1 + t; i < nb; i += LT) S[i + j * LB] /= dj;
+        __syncthreads();
+        const int w = nb - j - 1;
+        for (int e = t; e < w * w; e += LT) {
+            int r = e % w, c = e / w;
+            if (r >= c) {
+                int i = j + 1 + r, cc = j + 1 + c;
+                S[i + cc * LB] -= S[i + j * LB] * S[cc + j * LB];
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < nb * nb; e += LT) {
+        int i = e % nb, j = e / nb;
+        A[i + (int64_t)j * lda] = (i >= j) ? S[i + j * LB] : 0.0;
+    }
+    invert_lower_lds(S, y, t);
+    for (int e = t; e < LB * LB; e += LT) {
+        int i = e % LB, j = e / LB;
+        Linv[e] = (i >= j) ? S[i + j * LB] : 0.0;
+    }
+}
+
+// Inverses of the 128 x 128 diagonal blocks of an existing lower factor L
+// (one workgroup per block).
+__global__ __launch_bounds__(LT) void trtri_leaves_kernel(int64_t n, const double* L, int64_t ldl, double* Linv) {
+    __shared__ double S[LB * LB];
+    __shared__ double y[LB];
+    const int t = threadIdx.x;
+    const int64_t off = (int64_t)blockIdx.x * LB;
+    const int nb = (int)((n - off) < LB ? (n - off) : LB);
+    for (int e = t; e < LB * LB; e += LT) {
+        int i = e % LB, j = e / LB;
+        S[i + j * LB] = (i < nb && j < nb) ? ((i >= j) ? L[off + i + (off + j) * ldl] : 0.0) : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    invert_lower_lds(S, y, t);
+    double* out = Linv + (int64_t)blockIdx.x * LB * LB;
+    for (int e = t; e < LB * LB; e += LT) {
+        int i = e % LB, j = e / LB;
+        out[e] = (i >= j) ? S[i + j * LB] : 0.0;
+    }
+}
+
+__global__ void symmetrize_kernel(int64_t n, double* A, int64_t lda) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t j = blockIdx.y;
+    for (; j < n; j += gridDim.y) {
+        if (i < n && i > j) {
+            double v = 0.5 * (A[i + j * lda] + A[j + i * lda]);
+            A[i + j * lda] = v;
+            A[j + i * lda] = v;
+        }
+    }
+}
+
+inline int64_t split_point(int64_t k) {
+    int64_t leaves = FL_DIV_UP(k, LB);
+    return LB * ((leaves + 1) / 2);
+}
+
+}  // namespace
+
+int64_t fl_potrf_linv_elems(int64_t n) { return FL_DIV_UP(n, LB) * LB * LB; }
+int64_t fl_trsm_work_elems(int64_t n, int64_t other) { (void)n; return (int64_t)LB * (other > 0 ? other : 1); }
+
+hipError_t fl_potrf(hipStream_t s, int64_t n, double* A, int64_t lda, double* Linv, int64_t* info, double* work) {
+    if (n <= 0) return hipSuccess;
+    if (n <= LB) {
+        potrf_leaf_kernel<<<1, LT, 0, s>>>(A, lda, (int)n, 0, Linv, info);
+        return hipGetLastError();
+    }
+    // The global pivot offset of each leaf is needed in the status; recurse
+    // with an explicit offset through a small lambda.
+    struct Rec {
+        static hipError_t run(hipStream_t s, int64_t n, double* A, int64_t lda, double* Linv, int64_t* info,
+                              double* work, int64_t goff) {
+            if (n <= LB) {
+                potrf_leaf_kernel<<<1, LT, 0, s>>>(A, lda, (int)n, goff, Linv, info);
+                return hipGetLastError();
+            }
+            int64_t n1 = split_point(n), n2 = n - n1;
+            hipError_t e = run(s, n1, A, lda, Linv, info, work, goff);
+            if (e != hipSuccess) return e;
+            e = fl_trsm_rlt(s, n2, n1, A, lda, Linv, A + n1, lda, work);
+            if (e != hipSuccess) return e;
+            e = fl_dgemm(s, 0, 1, n2, n2, n1, -1.0, A + n1, lda, A + n1, lda, 1.0, A + n1 + n1 * lda, lda, 1);
+            if (e != hipSuccess) return e;
+            return run(s, n2, A + n1 + n1 * lda, lda, Linv + (n1 / LB) * LB * LB, info, work, goff + n1);
+        }
+    };
+    return Rec::run(s, n, A, lda, Linv, info, work, 0);
+}
+
+// X L^T = B, B is m x k.  work: >= m * 128 doubles.
+hipError_t fl_trsm_rlt(hipStream_t s, int64_t m, int64_t k, const double* L, int64_t ldl, const double* Linv,
+                       double* B, int64_t ldb, double* work) {
+    if (m <= 0 || k <= 0) return hipSuccess;
+    hipError_t e;
+    if (k <= LB) {
+        e = fl_copy_matrix(s, m, k, B, ldb, work, m);
+        if (e != hipSuccess) return e;
+        return fl_dgemm(s, 0, 1, m, k, k, 1.0, work, m, Linv, LB, 0.0, B, ldb);
+    }
+    int64_t k1 = split_point(k), k2 = k - k1;
+    e = fl_trsm_rlt(s, m, k1, L, ldl, Linv, B, ldb, work);
+    if (e != hipSuccess) return e;
+    e = fl_dgemm(s, 0, 1, m, k2, k1, -1.0, B, ldb, L + k1, ldl, 1.0, B + k1 * ldb, ldb);
+    if (e != hipSuccess) return e;
+    return fl_trsm_rlt(s, m, k2, L + k1 + k1 * ldl, ldl, Linv + (k1 / LB) * LB * LB, B + k1 * ldb, ldb, work);
+}
+
+// L X = B, B is k x m.  work: >= 128 * m doubles.
+hipError_t fl_trsm_lln(hipStream_t s, int64_t k, int64_t m, const double* L, int64_t ldl, const double* Linv,
+                       double* B, int64_t ldb, double* work) {
+    if (m <= 0 || k <= 0) return hipSuccess;
+    hipError_t e;
+    if (k <= LB) {
+        e = fl_copy_matrix(s, k, m, B, ldb, work, k);
+        if (e != hipSuccess) return e;
+        return fl_dgemm(s, 0, 0, k, m, k, 1.0, Linv, LB, work, k, 0.0, B, ldb);
+    }
+    int64_t k1 = split_point(k), k2 = k - k1;
+    e = fl_trsm_lln(s, k1, m, L, ldl, Linv, B, ldb, work);
+    if (e != hipSuccess) return e;
+    e = fl_dgemm(s, 0, 0, k2, m, k1, -1.0, L + k1, ldl, B, ldb, 1.0, B + k1, ldb);
+    if (e != hipSuccess) return e;
+    return fl_trsm_lln(s, k2, m, L + k1 + k1 * ldl, ldl, Linv + (k1 / LB) * LB * LB, B + k1, ldb, work);
+}
+
+// L^T X = B, B is k x m.  work: >= 128 * m doubles.
+hipError_t fl_trsm_llt(hipStream_t s, int64_t k, int64_t m, const double* L, int64_t ldl, const double* Linv,
+                       double* B, int64_t ldb, double* work) {
+    if (m <= 0 || k <= 0) return hipSuccess;
+    hipError_t e;
+    if (k <= LB) {
+        e = fl_copy_matrix(s, k, m, B, ldb, work, k);
+        if (e != hipSuccess) return e;
+        return fl_dgemm(s, 1, 0, k, m, k, 1.0, Linv, LB, work, k, 0.0, B, ldb);
+    }
+    int64_t k1 = split_point(k), k2 = k - k1;
+    e = fl_trsm_llt(s, k2, m, L + k1 + k1 * ldl, ldl, Linv + (k1 / LB) * LB * LB, B + k1, ldb, work);
+    if (e != hipSuccess) return e;
+    e = fl_dgemm(s, 1, 0, k1, m, k2, -1.0, L + k1, ldl, B + k1, ldb, 1.0, B, ldb);
+    if (e != hipSuccess) return e;
+    return fl_trsm_llt(s, k1, m, L, ldl, Linv, B, ldb, work);
+}
+
+hipError_t fl_trtri_leaves(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Linv) {
+    if (n <= 0) return hipSuccess;
+    trtri_leaves_kernel<<<(unsigned)FL_DIV_UP(n, LB), LT, 0, s>>>(n, L, ldl, Linv);
+    return hipGetLastError();
+}
+
+hipError_t fl_symmetrize(hipStream_t s, int64_t n, double* A, int64_t lda) {
+    if (n <= 1) return hipSuccess;
+    dim3 grid((unsigned)FL_DIV_UP(n, 256), (unsigned)(n < 65535 ? n : 65535));
+    symmetrize_kernel<<<grid, 256, 0, s>>>(n, A, lda);
+    return hipGetLastError();
+}

@@ -1,0 +1,48 @@
+// Shared declarations of the fraclap HIP library (gfx950 / MI355X).
+// All dense matrices are column-major, element (i, j) at A[i + j * lda].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+#define FL_DIV_UP(a, b) (((a) + (b) - 1) / (b))
+
+// One GEMM problem C = alpha * op(A) op(B) + beta * C, op(A) m x k, op(B) k x n.
+struct GemmProblem {
+    int64_t m, n, k;
+    const double* A;
+    int64_t lda;
+    const double* B;
+    int64_t ldb;
+    double* C;
+    int64_t ldc;
+    double alpha, beta;
+};
+
+// Launchers (stream-ordered, asynchronous).  ta / tb: 0 = N, 1 = T.
+// lower != 0 skips output tiles strictly above the diagonal (SYRK-style
+// updates of a lower-stored symmetric matrix; diagonal tiles are written in
+// full).
+hipError_t fl_dgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+                    const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                    int64_t ldc, int lower = 0);
+// Batched GEMM over problems held in DEVICE memory; grid sized for the largest
+// (max_m, max_n) and each tile exits early if outside its own problem.
+hipError_t fl_dgemm_batched(hipStream_t s, int ta, int tb, const GemmProblem* dev_probs, int count,
+                            int64_t max_m, int64_t max_n);
+
+// FP32 GEMM (mixed-precision mode): same conventions.
+hipError_t fl_sgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, float alpha,
+                    const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+                    int64_t ldc);
+
+// small helpers
+hipError_t fl_copy_matrix(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, double* B,
+                          int64_t ldb);
+hipError_t fl_transpose(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, double* B,
+                        int64_t ldb);
+hipError_t fl_fill(hipStream_t s, int64_t m, int64_t n, double v, double* A, int64_t lda);
+hipError_t fl_set_identity(hipStream_t s, int64_t n, double* A, int64_t lda);

@@ -1,0 +1,127 @@
+// FP64 MFMA GEMM tile machinery shared by the plain GEMM and the fused
+// spectral-application GEMM (operand B produced on the fly).
+//
+// v_mfma_f64_16x16x4f64 operand layout (measured on gfx950): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l holds
+// D[l/16 + 4r][l%16].  We compute C^T tiles (MFMA "A" <- op(B), "B" <- op(A))
+// so that lanes sharing an accumulator row write consecutive rows of the
+// column-major C.  Workgroup tile 128 x 128, k-step 16, 256 threads as 2 x 2
+// waves of 64 x 64, operands staged k-major in LDS and double buffered.
+#pragma once
+#include "common.h"
+
+namespace fl_tile {
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int SA = BM + 2;  // LDS row strides (doubles)
+constexpr int SB = BN + 2;
+constexpr int NT = 256;
+
+// Source of op(B)[kk][j].  KFAST: consecutive threads take consecutive kk.
+struct BPlain {
+    const double* B;
+    int64_t ldb;
+    bool trans;
+    __device__ inline double get(int64_t kk, int64_t j) const { return trans ? B[j + kk * ldb] : B[kk + j * ldb]; }
+};
+
+template <bool TA, bool KFAST_B, class BSrc>
+__device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const double* __restrict__ A, int64_t lda,
+                                 const BSrc& bs, double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                 int64_t bi, int64_t bj, double* As, double* Bs) {
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wi = wave & 1, wj = wave >> 1;
+    const int64_t i0 = bi * BM, j0 = bj * BN;
+    d4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+    constexpr int NA = BM * BK / NT, NB = BN * BK / NT;
+    double ra[NA], rb[NB];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+            int e = t + NT * r;
+            int ii, kk;
+            if (!TA) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
+            int64_t gi = i0 + ii, gk = k0 + kk;
+            double v = 0.0;
+            if (gi < m && gk < k) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+            ra[r] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            int e = t + NT * r;
+            int jj, kk;
+            if (KFAST_B) { kk = e % BK; jj = e / BK; } else { jj = e % BN; kk = e / BN; }
+            int64_t gj = j0 + jj, gk = k0 + kk;
+            rb[r] = (gj < n && gk < k) ? bs.get(gk, gj) : 0.0;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+            int e = t + NT * r;
+            int ii, kk;
+            if (!TA) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
+            As[buf * BK * SA + kk * SA + ii] = ra[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            int e = t + NT * r;
+            int jj, kk;
+            if (KFAST_B) { kk = e % BK; jj = e / BK; } else { jj = e % BN; kk = e / BN; }
+            Bs[buf * BK * SB + kk * SB + jj] = rb[r];
+        }
+    };
+    const int64_t nkt = FL_DIV_UP(k, BK);
+    if (nkt > 0) {
+        gload(0);
+        sstore(0);
+    }
+    __syncthreads();
+    const int lr = lane >> 4, lc = lane & 15;
+    for (int64_t kt = 0; kt < nkt; ++kt) {
+        const int cur = (int)(kt & 1);
+        if (kt + 1 < nkt) gload((kt + 1) * BK);
+        const double* Ac = As + cur * BK * SA;
+        const double* Bc = Bs + cur * BK * SB;
+#pragma unroll
+        for (int k4 = 0; k4 < BK; k4 += 4) {
+            double fa[4], fb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                fa[q] = Bc[(k4 + lr) * SB + wj * 64 + q * 16 + lc];  // MFMA A operand <- op(B)
+                fb[q] = Ac[(k4 + lr) * SA + wi * 64 + q * 16 + lc];  // MFMA B operand <- op(A)
+            }
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[jb], fb[ib], acc[ib][jb], 0, 0, 0);
+        }
+        if (kt + 1 < nkt) sstore(1 - cur);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) {
+        int64_t gi = i0 + wi * 64 + ib * 16 + lc;
+        if (gi >= m) continue;
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int64_t gj = j0 + wj * 64 + jb * 16 + lr + 4 * r;
+                if (gj >= n) continue;
+                double* cp = C + gi + gj * ldc;
+                double v = alpha * acc[ib][jb][r];
+                if (beta != 0.0) v += beta * (*cp);
+                *cp = v;
+            }
+        }
+    }
+}
+
+}  // namespace fl_tile
