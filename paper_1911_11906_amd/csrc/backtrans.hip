@@ -1,0 +1,235 @@
+// Back-transformation of the tridiagonal eigenvectors: Z := Q1 Q2 Z.
+//
+// Q2 (bulge chasing) is the product, in generation order, of the reflectors
+// H(i, j) of sweep i, task j, acting on rows [i+1+jb, i+(j+1)b].  Reflectors
+// of different sweeps overlap only as (i, j) with (i+d, j) (d < b) or
+// (i+d, j-1) (1 <= d < 2b), so for a group of b consecutive sweeps the
+// product equals prod_j-descending B(G, j) with B(G, j) = H(g, j) ... H(g+b-1, j),
+// a (2b-1) x b staircase block reflector I - V T V^T.  Applying Q2: groups
+// last to first, within a group j ascending.  Each workgroup owns a 32-column
+// slab of Z and runs W = V^T Z, W = T W, Z -= V W on the matrix cores from LDS.
+//
+// Q1 (band reduction) is applied panel by panel, last first, with GEMMs.
+#include "internal.h"
+
+namespace {
+
+constexpr int QB = 64;      // max band width
+constexpr int QR = 128;     // rows of a block (2b - 1 padded)
+constexpr int NC = 32;      // Z columns per workgroup
+constexpr int LV = QB + 1;  // LDS leading dimensions
+constexpr int LZ = QR + 1;
+constexpr int LW = QB + 1;
+
+__device__ inline int64_t ntasks(int64_t n, int b, int64_t i) { return 1 + (n - 3 - i) / b; }
+
+// T factor of block (g, j): one workgroup of 64 threads.
+__global__ __launch_bounds__(64) void q2_larft_kernel(int64_t n, int b, const double* __restrict__ V2,
+                                                      const double* __restrict__ tau2, int64_t maxt, int64_t g,
+                                                      double* T2) {
+    __shared__ double Vb[QR * QB];  // row-major by reflector: Vb[s*QR + r]
+    __shared__ double Gs[QB * LV];
+    __shared__ double Ts[QB * LV];
+    __shared__ double y[QB], tv[QB];
+    const int t = threadIdx.x;
+    const int64_t j = blockIdx.x;
+    const int64_t nsw = n - 2;
+    const int64_t base = g + 1 + j * b;
+    // column s = sweep g+s
+    for (int s = 0; s < QB; ++s) {
+        bool ex = (s < b) && (g + s < nsw) && (j < ntasks(n, b, g + s));
+        int L = 0;
+        if (ex) {
+            int64_t r0 = base + s;
+            L = (int)((n - r0) < b ? (n - r0) : b);
+        }
+        const double* src = V2 + ((g + s) * maxt + j) * (int64_t)b;
+        for (int r = t; r < QR; r += 64) {
+            int rr = r - s;
+            Vb[s * QR + r] = (ex && rr >= 0 && rr < L) ? src[rr] : 0.0;
+        }
+        if (t == 0) tv[s] = ex ? tau2[(g + s) * maxt + j] : 0.0;
+    }
+    __syncthreads();
+    // Gram: G[s1][s2] = sum_r V[r][s1] V[r][s2], thread t = column s2
+    for (int s1 = 0; s1 < QB; ++s1) {
+        double acc = 0.0;
+        for (int r = 0; r < QR; ++r) acc += Vb[s1 * QR + r] * Vb[t * QR + r];
+        Gs[s1 + t * LV] = acc;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < QB; ++jj) {
+        if (t < jj) y[t] = Gs[t + jj * LV];
+        __syncthreads();
+        if (t < jj) {
+            double acc = 0.0;
+            for (int k = t; k < jj; ++k) acc += Ts[t + k * LV] * y[k];
+            Ts[t + jj * LV] = -tv[jj] * acc;
+        }
+        if (t == jj) Ts[jj + jj * LV] = tv[jj];
+        if (t > jj) Ts[t + jj * LV] = 0.0;
+        __syncthreads();
+    }
+    double* out = T2 + ((g / b) * maxt + j) * (int64_t)QB * QB;
+    for (int jj = 0; jj < QB; ++jj) out[t + jj * QB] = Ts[t + jj * LV];
+}
+
+// Apply the blocks of group g (j ascending) to Z[:, slab].
+__global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, const double* __restrict__ V2, int64_t maxt,
+                                                       int64_t g, const double* __restrict__ T2, double* Z,
+                                                       int64_t ldz, int64_t ncols) {
+    __shared__ double Vt[QR * LV];  // Vt[s + r*LV] = V[r][s]
+    __shared__ double Ts[QB * LV];
+    __shared__ double Zs[NC * LZ];  // Zs[r + c*LZ]
+    __shared__ double W[NC * LW];   // W[s + c*LW]
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int lr = lane >> 4, lc = lane & 15;
+    const int64_t col0 = (int64_t)blockIdx.x * NC;
+    const int64_t nsw = n - 2;
+    const int64_t ntg = ntasks(n, b, g);
+    for (int64_t j = 0; j < ntg; ++j) {
+        const int64_t base = g + 1 + j * b;
+        const int rows = (int)((n - base) < QR ? (n - base) : QR);
+        // stage V (transposed), T, Z slab
+        for (int e = t; e < QR * QB; e += 256) {
+            int r = e % QR, s = e / QR;
+            double v = 0.0;
+            if (s < b && g + s < nsw && j < ntasks(n, b, g + s)) {
+                int64_t r0 = base + s;
+                int L = (int)((n - r0) < b ? (n - r0) : b);
+                int rr = r - s;
+                if (rr >= 0 && rr < L) v = V2[((g + s) * maxt + j) * (int64_t)b + rr];
+            }
+            Vt[s + r * LV] = v;
+        }
+        const double* Tb = T2 + ((g / b) * maxt + j) * (int64_t)QB * QB;
+        for (int e = t; e < QB * QB; e += 256) Ts[(e % QB) + (e / QB) * LV] = Tb[e];
+        for (int e = t; e < QR * NC; e += 256) {
+            int r = e % QR, c = e / QR;
+            Zs[r + c * LZ] = (r < rows && col0 + c < ncols) ? Z[(base + r) + (col0 + c) * ldz] : 0.0;
+        }
+        __syncthreads();
+        // W = V^T Zs  (64 x 32): wave w -> tiles (ti = w, tj = 0, 1)
+        {
+            d4_t acc[2];
+            acc[0] = d4_t{0, 0, 0, 0};
+            acc[1] = d4_t{0, 0, 0, 0};
+            const int ti = wave;
+            for (int k0 = 0; k0 < QR; k0 += 4) {
+                double a = Vt[(ti * 16 + lc) + (k0 + lr) * LV];
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) {
+                    double bb = Zs[(k0 + lr) + (tj * 16 + lc) * LZ];
+                    acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[tj], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W[(ti * 16 + lr + 4 * r) + (tj * 16 + lc) * LW] = acc[tj][r];
+        }
+        __syncthreads();
+        // W := T W  (computed in registers, then written over W)
+        {
+            d4_t acc[2];
+            acc[0] = d4_t{0, 0, 0, 0};
+            acc[1] = d4_t{0, 0, 0, 0};
+            const int ti = wave;
+            for (int k0 = 0; k0 < QB; k0 += 4) {
+                double a = Ts[(ti * 16 + lc) + (k0 + lr) * LV];
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) {
+                    double bb = W[(k0 + lr) + (tj * 16 + lc) * LW];
+                    acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[tj], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W[(ti * 16 + lr + 4 * r) + (tj * 16 + lc) * LW] = acc[tj][r];
+        }
+        __syncthreads();
+        // Zs -= V W  (128 x 32): wave w -> tiles ti = 2w, 2w+1; tj = 0, 1
+        {
+            d4_t acc[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[a][c] = d4_t{0, 0, 0, 0};
+            for (int k0 = 0; k0 < QB; k0 += 4) {
+                double bb[2];
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) bb[tj] = W[(k0 + lr) + (tj * 16 + lc) * LW];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int ti = 2 * wave + a;
+                    double av = Vt[(k0 + lr) + (ti * 16 + lc) * LV];
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj)
+                        acc[a][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bb[tj], acc[a][tj], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int ti = 2 * wave + a;
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Zs[(ti * 16 + lr + 4 * r) + (tj * 16 + lc) * LZ] -= acc[a][tj][r];
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < QR * NC; e += 256) {
+            int r = e % QR, c = e / QR;
+            if (r < rows && col0 + c < ncols) Z[(base + r) + (col0 + c) * ldz] = Zs[r + c * LZ];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) { return (FL_DIV_UP(n, b) + 1) * maxt * (int64_t)QB * QB; }
+
+// Z (n x ncols) := Q2 Z with the reflectors of fl_sb2st.  T2: fl_q2_t_elems doubles.
+hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* T2,
+                       double* Z, int64_t ldz, int64_t ncols) {
+    if (n < 3 || b < 2) return hipSuccess;
+    const int64_t nsw = n - 2;
+    hipError_t e;
+    for (int64_t g = 0; g < nsw; g += b) {
+        int64_t nt = 1 + (n - 3 - g) / b;
+        q2_larft_kernel<<<(unsigned)nt, 64, 0, s>>>(n, b, V2, tau2, maxt, g, T2);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int64_t ngroups = FL_DIV_UP(nsw, b);
+    for (int64_t gi = ngroups - 1; gi >= 0; --gi) {
+        int64_t g = gi * b;
+        q2_apply_kernel<<<(unsigned)FL_DIV_UP(ncols, NC), 256, 0, s>>>(n, b, V2, maxt, g, T2, Z, ldz, ncols);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Z (n x ncols) := Q1 Z, Q1 = prod over panels of (I - V_p T_p V_p^T).
+// work: >= 2 * b * ncols doubles.
+hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
+                       int64_t ldz, int64_t ncols, double* work) {
+    int64_t np = fl_sy2sb_panels(n, b);
+    hipError_t e;
+    for (int64_t p = np - 1; p >= 0; --p) {
+        const int64_t c0 = p * b, r0 = c0 + b, m = n - r0;
+        const int kref = (int)std::min<int64_t>(b, m - 1);
+        if (kref <= 0) continue;
+        const double* Vp = V1 + r0 + c0 * ldv;
+        const double* Tp = T1 + p * (int64_t)b * b;
+        double* W1 = work;
+        double* W2 = work + (int64_t)b * ncols;
+        if ((e = fl_dgemm(s, 1, 0, kref, ncols, m, 1.0, Vp, ldv, Z + r0, ldz, 0.0, W1, b))) return e;
+        if ((e = fl_dgemm(s, 0, 0, kref, ncols, kref, 1.0, Tp, b, W1, b, 0.0, W2, b))) return e;
+        if ((e = fl_dgemm(s, 0, 0, m, ncols, kref, -1.0, Vp, ldv, W2, b, 1.0, Z + r0, ldz))) return e;
+    }
+    return hipSuccess;
+}

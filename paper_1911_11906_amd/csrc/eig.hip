@@ -1,0 +1,275 @@
+// The full-spectrum generalized eigensolve K phi = theta M phi (eq.
+// discrete_laplace) with M-orthonormal eigenvectors (Section
+// "Post-processing"), as a dense FP64 pipeline on one GPU:
+//   M = L L^T;  C = L^-1 K L^-T;  C -> band -> tridiagonal T (two stages);
+//   T = Z_T diag(theta) Z_T^T (divide and conquer);  Z = Q1 Q2 Z_T;  V = L^-T Z.
+// V^T M V = Z^T L^-1 L L^T L^-T Z = Z^T Z = I.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+#include "internal.h"
+
+// sy2sb.hip
+hipError_t fl_sy2sb(hipStream_t s, int64_t n, int b, double* A, int64_t lda, double* V1, int64_t ldv, double* T1,
+                    double* tau1, double* work, double* part, unsigned* cnt, int* abort);
+int64_t fl_sy2sb_work_elems(int64_t n, int b);
+int64_t fl_sy2sb_part_elems(int64_t n);
+hipError_t fl_extract_band(hipStream_t s, int64_t n, int b, const double* A, int64_t lda, double* AB, int64_t ldab);
+// sb2st.hip
+int64_t fl_sb2st_maxt(int64_t n, int b);
+hipError_t fl_sb2st(hipStream_t s, int64_t n, int b, double* AB, int64_t ldab, double* d, double* e, double* V2,
+                    double* tau2, int* prog, int grid, int* abort);
+// backtrans.hip
+int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt);
+hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* T2,
+                       double* Z, int64_t ldz, int64_t ncols);
+hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
+                       int64_t ldz, int64_t ncols, double* work);
+// stedc.hip
+int fl_stedc_device(fl_ctx* ctx, int64_t n, double* d, const double* e, double* Zout, int64_t ldz, int leaf);
+
+namespace {
+
+struct StageTimer {
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> stage;
+    explicit StageTimer(hipStream_t st) : s(st) {}
+    ~StageTimer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t mark(int st) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+        stage.push_back(st);
+        return hipEventRecord(e, s);
+    }
+    // stage_ms[stage[k]] += time between mark k and k+1
+    void collect(fl_eig_info* info) {
+        if (!info) return;
+        for (size_t k = 0; k + 1 < ev.size(); ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess && stage[k] >= 0) info->stage_ms[stage[k]] += ms;
+        }
+        float tot = 0.f;
+        if (ev.size() >= 2 && hipEventElapsedTime(&tot, ev.front(), ev.back()) == hipSuccess) info->total_ms = tot;
+    }
+};
+
+int clamp_band(int64_t n, int band) {
+    int b = band > 0 ? band : 64;
+    b = std::max(2, std::min(b, 64));
+    return b;
+}
+
+int grid_for_sb2st(int64_t n, int b) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    int64_t useful = n / (3 * (int64_t)b) + 2;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(useful, cus));
+}
+
+}  // namespace
+
+// Two-stage tridiagonalisation + D&C + back-transforms of the symmetric A
+// (full storage, destroyed).  w (n) ascending, Z (n x n, ld ldz).
+int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* w, double* Z, int64_t ldz,
+                    fl_eig_info* info, int leaf, StageTimer* tm_ext = nullptr);
+
+int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* w, double* Z, int64_t ldz,
+                    fl_eig_info* info, int leaf, StageTimer* tm) {
+    hipStream_t s = ctx->stream;
+    const int b = clamp_band(n, band);
+    const int64_t ldab = 2 * b + 1;
+    const int64_t np = std::max<int64_t>(1, fl_sy2sb_panels(n, b));
+    const int64_t maxt = fl_sb2st_maxt(n, b);
+    const int64_t nsw = std::max<int64_t>(1, n - 2);
+    DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
+    FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+    FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
+    FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
+    FL_HIP(ctx, btau1.alloc(sizeof(double) * (n + b)));
+    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+    FL_HIP(ctx, bpart.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
+    FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
+    FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
+    FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
+    FL_HIP(ctx, bprog.alloc(sizeof(int) * (n + 2)));
+    FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
+    double* e = be.as<double>();
+    int* abort_flag = bprog.as<int>() + n + 1;
+    FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
+
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
+    FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, bV1.as<double>(), n, bT1.as<double>(), btau1.as<double>(),
+                         bwork.as<double>(), bpart.as<double>(), bcnt.as<unsigned>(), abort_flag));
+    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, bAB.as<double>(), ldab));
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
+    FL_HIP(ctx, fl_sb2st(s, n, b, bAB.as<double>(), ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
+                         grid_for_sb2st(n, b), abort_flag));
+    {
+        int ab = 0;
+        FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        if (ab) {
+            if (info) info->index = FL_STAGE_SB2ST;
+            return fl_fail(ctx, FL_ENOCONV, "tridiagonalisation: a cooperative wait was abandoned");
+        }
+    }
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_STEDC));
+    int rc = fl_stedc_device(ctx, n, w, e, Z, ldz, leaf);
+    if (rc) {
+        if (info) info->index = FL_STAGE_STEDC;
+        return rc;
+    }
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q2));
+    FL_HIP(ctx, bT2.alloc(sizeof(double) * fl_q2_t_elems(n, b, maxt)));
+    FL_HIP(ctx, fl_q2_apply(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<double>(), Z, ldz, n));
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q1));
+    FL_HIP(ctx, fl_q1_apply(s, n, b, bV1.as<double>(), n, bT1.as<double>(), Z, ldz, n, bwork.as<double>()));
+    if (tm) FL_HIP(ctx, tm->mark(-1));
+    FL_HIP(ctx, hipStreamSynchronize(s));
+    return FL_OK;
+}
+
+extern "C" {
+
+int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info* info) {
+    if (!op) return FL_EINVAL;
+    fl_ctx* ctx = op->ctx;
+    if (precision != FL_FP64 && precision != FL_MIXED) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve: bad precision");
+    if (info) *info = fl_eig_info{};
+    FL_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t n = op->n, ld = op->ld;
+    const int band = opts ? opts->band : 0;
+    const int leaf = opts ? opts->leaf : 0;
+    hipStream_t s = ctx->stream;
+    DevBuf bL, bC, blinv, bwork, binfo;
+    FL_HIP(ctx, bL.alloc(sizeof(double) * ld * n));
+    FL_HIP(ctx, bC.alloc(sizeof(double) * ld * n));
+    FL_HIP(ctx, blinv.alloc(sizeof(double) * fl_potrf_linv_elems(n)));
+    FL_HIP(ctx, bwork.alloc(sizeof(double) * fl_trsm_work_elems(n, n)));
+    FL_HIP(ctx, binfo.alloc(sizeof(int64_t)));
+    if (!op->theta || !op->V || !op->logtheta) {
+        if (!op->theta) FL_HIP(ctx, hipMalloc(&op->theta, sizeof(double) * n));
+        if (!op->logtheta) FL_HIP(ctx, hipMalloc(&op->logtheta, sizeof(double) * n));
+        if (!op->V) FL_HIP(ctx, hipMalloc(&op->V, sizeof(double) * ld * n));
+    }
+    op->has_eig = 0;
+    double* L = bL.as<double>();
+    double* C = bC.as<double>();
+    StageTimer tm(s);
+    FL_HIP(ctx, tm.mark(FL_STAGE_POTRF));
+    FL_HIP(ctx, hipMemcpyAsync(L, op->M, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
+    FL_HIP(ctx, hipMemsetAsync(binfo.p, 0, sizeof(int64_t), s));
+    FL_HIP(ctx, fl_potrf(s, n, L, ld, blinv.as<double>(), binfo.as<int64_t>(), bwork.as<double>()));
+    int64_t piv = 0;
+    FL_HIP(ctx, hipMemcpyAsync(&piv, binfo.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FL_HIP(ctx, hipStreamSynchronize(s));
+    if (piv) {
+        if (info) {
+            info->status = FL_ENOTSPD;
+            info->index = piv;
+        }
+        return fl_fail(ctx, FL_ENOTSPD, "fl_eigensolve: M is not positive definite at pivot " + std::to_string(piv));
+    }
+    FL_HIP(ctx, tm.mark(FL_STAGE_SYGST));
+    FL_HIP(ctx, hipMemcpyAsync(C, op->K, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
+    int rc = fl_sygst_device(ctx, n, L, ld, blinv.as<double>(), C, ld, bwork.as<double>());
+    if (rc) return rc;
+    rc = fl_syevd_device(ctx, n, C, ld, band, op->theta, op->V, ld, info, leaf, &tm);
+    if (rc) {
+        if (info) info->status = rc;
+        return rc;
+    }
+    FL_HIP(ctx, tm.mark(FL_STAGE_TRSM));
+    FL_HIP(ctx, fl_trsm_llt(s, n, n, L, ld, blinv.as<double>(), op->V, ld, bwork.as<double>()));
+    FL_HIP(ctx, fl_log_kernel(s, n, op->theta, op->logtheta));
+    FL_HIP(ctx, tm.mark(-1));
+    FL_HIP(ctx, hipStreamSynchronize(s));
+    if (info) {
+        tm.collect(info);
+        info->flops_nominal = 9.0 * (double)n * (double)n * (double)n;
+    }
+    double th0 = 0.0;
+    FL_HIP(ctx, hipMemcpy(&th0, op->theta, sizeof(double), hipMemcpyDeviceToHost));
+    if (!(th0 > 0.0)) {
+        if (info) info->status = FL_EINVAL;
+        return fl_fail(ctx, FL_EINVAL, "fl_eigensolve: smallest eigenvalue is not positive");
+    }
+    op->has_eig = 1;
+    return FL_OK;
+}
+
+int fl_dstedc(fl_ctx* ctx, int64_t n, double* d, double* e, double* Z, int64_t ldz) {
+    if (!ctx) return FL_EINVAL;
+    if (n <= 0 || !d || !Z || ldz < n || (n > 1 && !e)) return fl_fail(ctx, FL_EINVAL, "fl_dstedc: bad arguments");
+    FL_HIP(ctx, hipSetDevice(ctx->device));
+    DevBuf be;
+    FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
+    FL_HIP(ctx, hipMemsetAsync(be.p, 0, sizeof(double) * (n + 1), ctx->stream));
+    if (n > 1)
+        FL_HIP(ctx, hipMemcpyAsync(be.p, e, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, ctx->stream));
+    return fl_stedc_device(ctx, n, d, be.as<double>(), Z, ldz, 0);
+}
+
+int fl_dsyevd(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* w, double* Z, int64_t ldz) {
+    if (!ctx) return FL_EINVAL;
+    if (n <= 0 || !A || !w || !Z || lda < n || ldz < n) return fl_fail(ctx, FL_EINVAL, "fl_dsyevd: bad arguments");
+    FL_HIP(ctx, hipSetDevice(ctx->device));
+    return fl_syevd_device(ctx, n, A, lda, band, w, Z, ldz, nullptr, 0, nullptr);
+}
+
+int fl_dsytrd_2stage(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* d, double* e, double* Q,
+                     int64_t ldq) {
+    if (!ctx) return FL_EINVAL;
+    if (n <= 0 || !A || !d || !e || lda < n || (Q && ldq < n)) return fl_fail(ctx, FL_EINVAL, "fl_dsytrd_2stage: bad arguments");
+    FL_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int b = clamp_band(n, band);
+    const int64_t ldab = 2 * b + 1;
+    const int64_t np = std::max<int64_t>(1, fl_sy2sb_panels(n, b));
+    const int64_t maxt = fl_sb2st_maxt(n, b);
+    const int64_t nsw = std::max<int64_t>(1, n - 2);
+    DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
+    FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+    FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
+    FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
+    FL_HIP(ctx, btau1.alloc(sizeof(double) * (n + b)));
+    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+    FL_HIP(ctx, bpart.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
+    FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
+    FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
+    FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
+    FL_HIP(ctx, bprog.alloc(sizeof(int) * (n + 2)));
+    FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
+    int* abort_flag = bprog.as<int>() + n + 1;
+    FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
+    FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, bV1.as<double>(), n, bT1.as<double>(), btau1.as<double>(), bwork.as<double>(),
+                         bpart.as<double>(), bcnt.as<unsigned>(), abort_flag));
+    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, bAB.as<double>(), ldab));
+    FL_HIP(ctx, fl_sb2st(s, n, b, bAB.as<double>(), ldab, d, be.as<double>(), bV2.as<double>(), btau2.as<double>(),
+                         bprog.as<int>(), grid_for_sb2st(n, b), abort_flag));
+    {
+        int ab = 0;
+        FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        if (ab) return fl_fail(ctx, FL_ENOCONV, "tridiagonalisation: a cooperative wait was abandoned");
+    }
+    if (n > 1) FL_HIP(ctx, hipMemcpyAsync(e, be.p, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, s));
+    if (Q) {
+        FL_HIP(ctx, fl_set_identity(s, n, Q, ldq));
+        FL_HIP(ctx, bT2.alloc(sizeof(double) * fl_q2_t_elems(n, b, maxt)));
+        FL_HIP(ctx, fl_q2_apply(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<double>(), Q, ldq, n));
+        FL_HIP(ctx, fl_q1_apply(s, n, b, bV1.as<double>(), n, bT1.as<double>(), Q, ldq, n, bwork.as<double>()));
+    }
+    FL_HIP(ctx, hipStreamSynchronize(s));
+    return FL_OK;
+}
+
+}  // extern "C"

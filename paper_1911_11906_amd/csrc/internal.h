@@ -1,5 +1,6 @@
 // Internal state and launchers of the fraclap library.
 #pragma once
+#include <algorithm>
 #include <string>
 #include <vector>
 #include "common.h"
@@ -107,7 +108,5 @@ int fl_sygst_device(fl_ctx* ctx, int64_t n, const double* L, int64_t ldl, const 
 // work size (doubles) needed by the TRSMs for an RHS block with `cols` columns / rows
 int64_t fl_trsm_work_elems(int64_t n, int64_t other);
 
-// eig.hip (two-stage tridiagonalisation, D&C, back-transforms)
-struct EigWork;
-int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* w, double* Z, int64_t ldz,
-                    fl_eig_info* info, int mixed);
+// sy2sb.hip: number of band-reduction panels for band width b
+int64_t fl_sy2sb_panels(int64_t n, int b);

@@ -1,0 +1,236 @@
+// Stage 2 of the two-stage tridiagonalisation: symmetric band (width b) ->
+// tridiagonal by bulge chasing.
+//
+// Sweep i annihilates column i below its subdiagonal with a Householder
+// reflector on rows R_0 = [i+1, i+b]; applying it from the right to the
+// block below creates a bulge, whose first column is annihilated by the next
+// reflector on rows R_1 = [i+b+1, i+2b], and so on down the band.  Only the
+// first column of each bulge is removed; the rest is removed by later sweeps,
+// so the working band holds 2b sub-diagonals.  Task (i, j) touches
+// rows/columns [i+1+(j-1)b, i+(j+2)b]; tasks of sweep i-1 overlap it for
+// j' in [j-3, j+3], so (i, j) may start once sweep i-1 has finished task j+3.
+//
+// One persistent cooperative launch: workgroup w runs sweeps w, w+G, ...;
+// each task stages its three b x b blocks in LDS; per-sweep progress
+// counters are published with agent-scope release and read with acquire
+// (they order the band traffic across the XCD L2 caches).
+#include "internal.h"
+
+namespace {
+
+constexpr int BMAX = 64;
+constexpr int LDB = BMAX + 1;
+constexpr int NTH = 256;
+
+__device__ inline int64_t ntasks(int64_t n, int b, int64_t i) { return 1 + (n - 3 - i) / b; }
+
+__device__ inline double band_get(const double* AB, int64_t ldab, int64_t r, int64_t c) {
+    return AB[(r - c) + c * ldab];
+}
+
+constexpr long SPIN_CAP = 20000000;  // bounded wait: every wave exits even if a predecessor stalls
+
+__global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB, int64_t ldab, double* V2,
+                                                    double* tau2, int64_t maxt, int* prog, int* abort) {
+    __shared__ double bufA[BMAX * LDB], bufB[BMAX * LDB];  // off-diagonal / below blocks (rotate roles)
+    __shared__ double S[BMAX * LDB];                        // symmetric diagonal block (full)
+    __shared__ double vv[BMAX], pv[BMAX], wv[BMAX];
+    __shared__ double red[4][BMAX];
+    __shared__ double sc[4];
+    __shared__ int quit;
+    const int t = threadIdx.x;
+    const int64_t nsweeps = n - 2;
+    for (int64_t i = blockIdx.x; i < nsweeps; i += gridDim.x) {
+        const int64_t nt = ntasks(n, b, i);
+        const int64_t ntp = (i > 0) ? ntasks(n, b, i - 1) : 0;
+        double* Boff = bufA;
+        double* Bbl = bufB;
+        for (int64_t j = 0; j < nt; ++j) {
+            // ---- wait for sweep i-1 to clear our region (bounded)
+            if (t == 0) {
+                quit = 0;
+                if (i > 0) {
+                    int need = (int)((j + 4 < ntp) ? (j + 4) : ntp);
+                    long spins = 0;
+                    while (__hip_atomic_load(&prog[i - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > SPIN_CAP || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            quit = 1;
+                            break;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (quit) return;
+            const int64_t r0 = i + 1 + j * b;
+            const int L = (int)((n - r0) < b ? (n - r0) : b);          // rows of R_j
+            const int64_t q0 = r0 + L;
+            const int Lb = (int)(q0 < n ? ((n - q0) < b ? (n - q0) : b) : 0);  // rows of R_{j+1}
+            const int64_t c0 = r0 - b;                                   // first column of R_{j-1}
+            // ---- load: x (j == 0: column i), S = A[R_j, R_j], Bbl = A[R_{j+1}, R_j]
+            if (j == 0) {
+                for (int r = t; r < L; r += NTH) Boff[r] = band_get(AB, ldab, r0 + r, i);
+            }
+            for (int e = t; e < L * L; e += NTH) {
+                int r = e % L, c = e / L;
+                if (r >= c) {
+                    double v = band_get(AB, ldab, r0 + r, r0 + c);
+                    S[r + c * LDB] = v;
+                    S[c + r * LDB] = v;
+                }
+            }
+            for (int e = t; e < Lb * L; e += NTH) {
+                int r = e % Lb, c = e / Lb;
+                Bbl[r + c * LDB] = band_get(AB, ldab, q0 + r, r0 + c);
+            }
+            __syncthreads();
+            // ---- Householder of x = Boff[:, 0] (length L)
+            if (t < 64) {
+                double s2 = 0.0;
+                for (int r = 1 + t; r < L; r += 64) s2 += Boff[r] * Boff[r];
+                for (int off = 32; off > 0; off >>= 1) s2 += __shfl_down(s2, off, 64);
+                if (t == 0) {
+                    double x0 = Boff[0];
+                    double beta, tauc, scale;
+                    if (s2 == 0.0 || L < 2) {
+                        beta = x0;
+                        tauc = 0.0;
+                        scale = 0.0;
+                    } else {
+                        double nrm = sqrt(x0 * x0 + s2);
+                        beta = (x0 >= 0.0) ? -nrm : nrm;
+                        tauc = (beta - x0) / beta;
+                        scale = 1.0 / (x0 - beta);
+                    }
+                    sc[0] = scale;
+                    sc[1] = tauc;
+                    sc[2] = beta;
+                }
+            }
+            __syncthreads();
+            const double scale = sc[0], tauc = sc[1], beta = sc[2];
+            for (int r = t; r < BMAX; r += NTH) vv[r] = (r == 0) ? 1.0 : (r < L ? Boff[r] * scale : 0.0);
+            __syncthreads();
+            if (t == 0) Boff[0] = beta;
+            for (int r = 1 + t; r < L; r += NTH) Boff[r] = 0.0;
+            // ---- left-apply to the remaining columns of the off-diagonal block (j >= 1)
+            if (j > 0 && tauc != 0.0) {
+                // w_c = v^T Boff[:, c], c = 1..b-1 ; thread (grp, col)
+                const int col = t & 63, grp = t >> 6;
+                double s = 0.0;
+                if (col >= 1 && col < b)
+                    for (int r = grp; r < L; r += 4) s += vv[r] * Boff[r + col * LDB];
+                red[grp][col] = s;
+                __syncthreads();
+                if (t < 64) wv[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+                __syncthreads();
+                for (int e = t; e < L * b; e += NTH) {
+                    int r = e % L, c = e / L;
+                    if (c >= 1) Boff[r + c * LDB] -= tauc * vv[r] * wv[c];
+                }
+            }
+            __syncthreads();
+            // ---- two-sided update of S: p = tau S v, w = p - (tau/2)(v^T p) v, S -= v w^T + w v^T
+            if (tauc != 0.0) {
+                const int row = t & 63, grp = t >> 6;
+                double s = 0.0;
+                if (row < L)
+                    for (int c = grp; c < L; c += 4) s += S[row + c * LDB] * vv[c];
+                red[grp][row] = s;
+                __syncthreads();
+                if (t < 64) pv[t] = (t < L) ? tauc * (red[0][t] + red[1][t] + red[2][t] + red[3][t]) : 0.0;
+                __syncthreads();
+                if (t < 64) {
+                    double a = (t < L) ? vv[t] * pv[t] : 0.0;
+                    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+                    if (t == 0) sc[3] = 0.5 * tauc * a;
+                }
+                __syncthreads();
+                const double al = sc[3];
+                if (t < 64) wv[t] = pv[t] - al * vv[t];
+                __syncthreads();
+                for (int e = t; e < L * L; e += NTH) {
+                    int r = e % L, c = e / L;
+                    S[r + c * LDB] -= vv[r] * wv[c] + wv[r] * vv[c];
+                }
+                // ---- right-apply to the block below: Bbl -= tau (Bbl v) v^T
+                {
+                    double y = 0.0;
+                    const int rr = t & 63;
+                    if (rr < Lb)
+                        for (int c = grp; c < L; c += 4) y += Bbl[rr + c * LDB] * vv[c];
+                    red[grp][rr] = y;
+                    __syncthreads();
+                    if (t < 64) pv[t] = tauc * (red[0][t] + red[1][t] + red[2][t] + red[3][t]);
+                    __syncthreads();
+                    for (int e = t; e < Lb * L; e += NTH) {
+                        int r = e % Lb, c = e / Lb;
+                        Bbl[r + c * LDB] -= pv[r] * vv[c];
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- write back
+            if (j == 0) {
+                for (int r = t; r < L; r += NTH) AB[(r0 + r - i) + i * ldab] = Boff[r];
+            } else {
+                for (int e = t; e < L * b; e += NTH) {
+                    int r = e % L, c = e / L;
+                    AB[(r0 + r - (c0 + c)) + (c0 + c) * ldab] = Boff[r + c * LDB];
+                }
+            }
+            for (int e = t; e < L * L; e += NTH) {
+                int r = e % L, c = e / L;
+                if (r >= c) AB[(r - c) + (r0 + c) * ldab] = S[r + c * LDB];
+            }
+            for (int e = t; e < Lb * L; e += NTH) {
+                int r = e % Lb, c = e / Lb;
+                AB[(q0 + r - (r0 + c)) + (r0 + c) * ldab] = Bbl[r + c * LDB];
+            }
+            double* vout = V2 + (i * maxt + j) * (int64_t)b;
+            for (int r = t; r < b; r += NTH) vout[r] = (r < L) ? vv[r] : 0.0;
+            if (t == 0) tau2[i * maxt + j] = tauc;
+            // ---- publish progress
+            __threadfence();
+            __syncthreads();
+            if (t == 0) __hip_atomic_store(&prog[i], (int)(j + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // the block below becomes the next off-diagonal block
+            double* tmp = Boff;
+            Boff = Bbl;
+            Bbl = tmp;
+        }
+    }
+}
+
+__global__ void band_to_tridiag_kernel(int64_t n, const double* __restrict__ AB, int64_t ldab, double* d, double* e) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = AB[i * ldab];
+    if (i < n - 1) e[i] = AB[1 + i * ldab];
+}
+
+}  // namespace
+
+int64_t fl_sb2st_maxt(int64_t n, int b) { return n >= 3 ? 1 + (n - 3) / b : 1; }
+
+// Band AB (lower, ld ldab >= 2b+1, zero below the first b+1 diagonals) ->
+// d, e.  V2 (n-2 sweeps x maxt tasks x b) and tau2 receive the reflectors.
+// prog: n ints of scratch; abort: device flag raised if a wait was abandoned.
+hipError_t fl_sb2st(hipStream_t s, int64_t n, int b, double* AB, int64_t ldab, double* d, double* e, double* V2,
+                    double* tau2, int* prog, int grid, int* abort) {
+    hipError_t err;
+    if (n >= 3 && b > 1) {
+        if ((err = hipMemsetAsync(prog, 0, sizeof(int) * n, s)) != hipSuccess) return err;
+        int64_t maxt = fl_sb2st_maxt(n, b);
+        int64_t nsw = n - 2;
+        unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nsw, grid));
+        int64_t nn = n, lda = ldab, mt = maxt;
+        int bb = b;
+        void* args[] = {&nn, &bb, &AB, &lda, &V2, &tau2, &mt, &prog, &abort};
+        err = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(G), dim3(NTH), args, 0, s);
+        if (err != hipSuccess) return err;
+    }
+    band_to_tridiag_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, AB, ldab, d, e);
+    return hipGetLastError();
+}

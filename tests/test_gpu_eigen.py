@@ -1,0 +1,171 @@
+"""GPU parity of the eigensolver stages against the CPU oracle (marker: gpu).
+
+Eigenvectors are compared only through quantities that do not depend on the
+free choices (sign, rotation inside a degenerate eigenspace): sorted
+eigenvalues, orthonormality, residuals, and products that reassemble the
+input.  Tolerances are multiples of eps * n * ||A||.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_11906_amd import inputs
+from oracle.closed_form import Q1Rectangle
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1911_11906_amd.api import Context
+    return Context(0)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def tridiag(kind, n, rng):
+    if kind == "rand":
+        return rng.standard_normal(n), rng.standard_normal(max(n - 1, 0))
+    if kind == "wilkinson":
+        m = (n - 1) / 2
+        return np.abs(np.arange(n) - m), np.ones(n - 1)
+    if kind == "glued":
+        d = np.tile([1.0, 2.0, 3.0, 4.0], n // 4 + 1)[:n]
+        e = np.full(n - 1, 1e-15)
+        e[::7] = 0.3
+        return d, e
+    if kind == "laplace":
+        return 2 * np.ones(n), -np.ones(n - 1)
+    if kind == "zero_e":
+        return rng.standard_normal(n), np.zeros(n - 1)
+    raise KeyError(kind)
+
+
+@pytest.mark.parametrize("n,kind", [(1, "rand"), (2, "rand"), (17, "rand"), (64, "rand"), (65, "rand"),
+                                    (300, "rand"), (1000, "rand"), (301, "wilkinson"), (257, "glued"),
+                                    (500, "laplace"), (130, "zero_e")])
+def test_stedc_vs_oracle(ctx, oracle_mod, n, kind):
+    note("stedc", n, kind)
+    rng = np.random.default_rng(n)
+    d, e = tridiag(kind, n, rng)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    w, Z = ctx.dstedc(d, e)
+    w, Z = to_np(w), to_np(Z)
+    wo, _, _ = oracle_mod.jacobi(T)
+    wo = np.sort(wo)
+    scale = max(np.abs(T).max(), 1e-300)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - wo).max() <= 50 * n * EPS * scale
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 50 * n * EPS
+    assert np.abs(T @ Z - Z * w).max() <= 50 * n * EPS * scale
+
+
+def random_sym(n, rng, spread=False):
+    X = rng.standard_normal((n, n))
+    A = X + X.T
+    if spread:
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        A = (Q * np.geomspace(1, 1e4, n)) @ Q.T
+        A = 0.5 * (A + A.T)
+    return A
+
+
+@pytest.mark.parametrize("n,b", [(3, 2), (10, 4), (100, 8), (257, 32), (300, 64), (600, 64)])
+def test_sytrd_2stage(ctx, oracle_mod, n, b):
+    note("sytrd_2stage", n, b)
+    rng = np.random.default_rng(7 * n + b)
+    A = random_sym(n, rng)
+    d, e, Q = ctx.dsytrd_2stage(A, band=b)
+    d, e, Q = to_np(d), to_np(e), to_np(Q)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    scale = np.abs(A).max()
+    assert np.abs(Q.T @ Q - np.eye(n)).max() <= 100 * n * EPS
+    assert np.abs(Q @ T @ Q.T - A).max() <= 100 * n * EPS * scale
+    wo, _, _ = oracle_mod.jacobi(A)
+    assert np.abs(np.sort(np.linalg.eigvalsh(T)) - np.sort(wo)).max() <= 100 * n * EPS * scale
+
+
+@pytest.mark.parametrize("n,b", [(50, 8), (513, 64), (1000, 32)])
+def test_syevd(ctx, oracle_mod, n, b):
+    note("syevd", n, b)
+    rng = np.random.default_rng(n)
+    A = random_sym(n, rng, spread=True)
+    w, Z = ctx.dsyevd(A, band=b)
+    w, Z = to_np(w), to_np(Z)
+    wo, _, _ = oracle_mod.jacobi(A)
+    scale = np.abs(w).max()
+    assert np.abs(w - np.sort(wo)).max() <= 100 * n * EPS * scale
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 100 * n * EPS
+    assert np.abs(A @ Z - Z * w).max() <= 100 * n * EPS * scale
+
+
+def check_pencil(K, M, th, V, th_ref, rel_tol, orth_tol):
+    n = K.shape[0]
+    assert np.all(np.diff(th) >= 0)
+    assert np.max(np.abs(th - th_ref) / th_ref) <= rel_tol
+    assert np.abs(V.T @ M @ V - np.eye(n)).max() <= orth_tol
+    R = K @ V - (M @ V) * th[None, :]
+    assert np.abs(R).max() <= 1e-11 * th.max() * np.abs(V).max()
+
+
+@pytest.mark.parametrize("band", [0, 16])
+def test_eigensolve_q1_c1(ctx, oracle_mod, band):
+    """Q1 on the 24 x 24 unit-square grid (n = 576): the exact discrete spectrum
+    is known in closed form; 276 eigenvalues are exactly double."""
+    note("eigensolve c1 band", band)
+    from paper_1911_11906_amd.api import Operator
+    mesh = inputs.q1_rectangle(24, 24)
+    op = Operator.assemble(ctx, mesh)
+    info = op.eigensolve("fp64", band=band)
+    th, V = op.eigenpairs()
+    th, V = to_np(th), to_np(V)
+    K, M = oracle_mod.assemble(mesh)
+    ref = Q1Rectangle(24, 24).eigenvalues()
+    check_pencil(K, M, th, V, ref, 1e-12, 1e-11)
+    assert info["total_ms"] > 0
+    # apply parity against the oracle on the oracle's own basis
+    tho, Vo = oracle_mod.eigensolve(K, M)
+    F = np.concatenate([inputs.sine_mode(mesh), inputs.polynomial_forcings(mesh, 3, tag=21)], axis=1)
+    al = np.array([0.5, 1.0, 1.5])
+    U = to_np(op.apply(F, al))
+    Uo = oracle_mod.apply_fractional(tho, Vo, M, F, al)
+    num = np.sqrt(np.einsum("ij,ij->j", (U - Uo), M @ (U - Uo)))
+    den = np.sqrt(np.einsum("ij,ij->j", Uo, M @ Uo))
+    assert np.max(num / den) <= 1e-10
+
+
+def test_eigensolve_p1_vs_oracle(ctx, oracle_mod):
+    note("eigensolve p1 poly 700")
+    from paper_1911_11906_amd.api import Operator
+    mesh = inputs.p1_polygon_with_holes(700, seed=12)
+    op = Operator.assemble(ctx, mesh)
+    op.eigensolve("fp64", band=32)
+    th, V = op.eigenpairs()
+    th, V = to_np(th), to_np(V)
+    K, M = oracle_mod.assemble(mesh)
+    tho, Vo = oracle_mod.eigensolve(K, M)
+    check_pencil(K, M, th, V, tho, 1e-11, 1e-11)
+    # spectral projector of the first 10 modes agrees (basis-choice independent)
+    P = V[:, :10] @ V[:, :10].T @ M
+    Po = Vo[:, :10] @ Vo[:, :10].T @ M
+    assert np.abs(P - Po).max() <= 1e-9 * np.abs(Po).max()
+
+
+def test_eigensolve_rejects_indefinite_mass(ctx):
+    from paper_1911_11906_amd.api import Operator
+    from paper_1911_11906_amd._lib import FraclapError, FL_ENOTSPD
+    n = 40
+    K = np.eye(n) * 2
+    M = np.eye(n)
+    M[30, 30] = -1
+    op = Operator.from_dense(ctx, K, M)
+    with pytest.raises(FraclapError) as e:
+        op.eigensolve()
+    assert e.value.status == FL_ENOTSPD
+    assert op.info["index"] == 31
