@@ -42,7 +42,7 @@ __global__ void weights_kernel(int64_t n, const double* __restrict__ logtheta, i
     for (int64_t i = blockIdx.y; i < na; i += gridDim.y) W[k + i * ldw] = exp(-0.5 * alpha[i] * lt);
 }
 
-// op(B)[kk][col] = W[kk, i(col)] * C[kk, j(col)]
+// op(B)[kk][col] = W[kk, i(col)] * C[kk, j(col)], col = j + i nf (paired: i = j = col)
 struct BScaled {
     const double* W;
     int64_t ldw;
@@ -50,19 +50,48 @@ struct BScaled {
     int64_t ldc;
     int64_t nf;
     int paired;
-    __device__ inline double get(int64_t kk, int64_t col) const {
+    struct H {
+        const double* w;
+        const double* c;
+    };
+    __device__ inline H col(int64_t col) const {
         int64_t i = paired ? col : col / nf;
         int64_t j = paired ? col : col - i * nf;
-        return W[kk + i * ldw] * Cc[kk + j * ldc];
+        return H{W + i * ldw, Cc + j * ldc};
     }
+    __device__ inline double at(const H& h, int64_t kk) const { return h.w[kk] * h.c[kk]; }
+    static constexpr bool KSCALE = false;
+    __device__ inline double kscale(int64_t, int64_t) const { return 1.0; }
 };
 
+// Same operand when every column of a 128-wide tile has the same alpha
+// (all pairs with nf a multiple of 128): the weight is one number per
+// (tile, k-row), loaded once per k-step instead of once per element.
+struct BScaledUniform {
+    const double* W;
+    int64_t ldw;
+    const double* Cc;
+    int64_t ldc;
+    int64_t nf;
+    struct H {
+        const double* c;
+    };
+    __device__ inline H col(int64_t col) const {
+        int64_t i = col / nf;
+        return H{Cc + (col - i * nf) * ldc};
+    }
+    __device__ inline double at(const H& h, int64_t kk) const { return h.c[kk]; }
+    static constexpr bool KSCALE = true;
+    __device__ inline double kscale(int64_t col0, int64_t kk) const { return W[kk + (col0 / nf) * ldw]; }
+};
+
+template <class BS>
 __global__ __launch_bounds__(NT) void scaled_gemm_kernel(int64_t n, int64_t ncol, const double* __restrict__ V,
-                                                         int64_t ldv, BScaled bs, double* __restrict__ U,
+                                                         int64_t ldv, BS bs, double* __restrict__ U,
                                                          int64_t ldu) {
-    __shared__ double As[2 * BK * SA];
-    __shared__ double Bs[2 * BK * SB];
-    tile_gemm<false, true>(n, ncol, n, V, ldv, bs, 1.0, 0.0, U, ldu, blockIdx.x, blockIdx.y, As, Bs);
+    __shared__ double As[TileLds<32, 1>::A];
+    __shared__ double Bs[TileLds<32, 1>::B];
+    tile_gemm<false, true, BS, 32, 1>(n, ncol, n, V, ldv, bs, 1.0, 0.0, U, ldu, blockIdx.x, blockIdx.y, As, Bs);
 }
 
 // galpha[b] = sum_k P[k,b] * (-0.5 ln theta_k) * W[k,b] * C[k,b]; one block per b,
@@ -124,9 +153,14 @@ hipError_t fl_scaled_gemm(hipStream_t s, int64_t n, const double* V, int64_t ldv
                           int64_t ldu) {
     int64_t ncol = paired ? nf : nf * na;
     if (n <= 0 || ncol <= 0) return hipSuccess;
-    BScaled bs{W, ldw, C, ldc, nf, paired};
     dim3 grid((unsigned)FL_DIV_UP(n, BM), (unsigned)FL_DIV_UP(ncol, BN));
-    scaled_gemm_kernel<<<grid, NT, 0, s>>>(n, ncol, V, ldv, bs, U, ldu);
+    if (!paired && nf % BN == 0) {
+        BScaledUniform bs{W, ldw, C, ldc, nf};
+        scaled_gemm_kernel<BScaledUniform><<<grid, NT, 0, s>>>(n, ncol, V, ldv, bs, U, ldu);
+    } else {
+        BScaled bs{W, ldw, C, ldc, nf, paired};
+        scaled_gemm_kernel<BScaled><<<grid, NT, 0, s>>>(n, ncol, V, ldv, bs, U, ldu);
+    }
     return hipGetLastError();
 }
 

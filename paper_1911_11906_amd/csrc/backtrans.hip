@@ -23,11 +23,17 @@ constexpr int LW = QB + 1;
 
 __device__ inline int64_t ntasks(int64_t n, int b, int64_t i) { return 1 + (n - 3 - i) / b; }
 
-// T factor of block (g, j): one workgroup of 64 threads.
-__global__ __launch_bounds__(64) void q2_larft_kernel(int64_t n, int b, const double* __restrict__ V2,
-                                                      const double* __restrict__ tau2, int64_t maxt, int64_t g,
-                                                      double* T2) {
-    __shared__ double Vb[QR * QB];  // row-major by reflector: Vb[s*QR + r]
+// Block (g, j): explicit staircase V (written as Vt[s + r*LV], the apply
+// kernel's LDS layout) and its forward T factor (T[t + jj*LV]); one
+// workgroup of 64 threads per block.
+constexpr int LQ = QR + 1;
+constexpr int64_t VBLK = (int64_t)QR * LV;  // doubles per packed V block
+constexpr int64_t TBLK = (int64_t)QB * LV;  // doubles per packed T block
+
+__global__ __launch_bounds__(64) void q2_prep_kernel(int64_t n, int b, const double* __restrict__ V2,
+                                                     const double* __restrict__ tau2, int64_t maxt, int64_t g,
+                                                     double* VB, double* TB) {
+    __shared__ double Vb[QB * LQ];  // Vb[s*LQ + r]
     __shared__ double Gs[QB * LV];
     __shared__ double Ts[QB * LV];
     __shared__ double y[QB], tv[QB];
@@ -35,8 +41,9 @@ __global__ __launch_bounds__(64) void q2_larft_kernel(int64_t n, int b, const do
     const int64_t j = blockIdx.x;
     const int64_t nsw = n - 2;
     const int64_t base = g + 1 + j * b;
-    // column s = sweep g+s
-    for (int s = 0; s < QB; ++s) {
+    // reflector s of the block is sweep g+s, task j (if it exists)
+    {
+        const int s = t;
         bool ex = (s < b) && (g + s < nsw) && (j < ntasks(n, b, g + s));
         int L = 0;
         if (ex) {
@@ -44,17 +51,17 @@ __global__ __launch_bounds__(64) void q2_larft_kernel(int64_t n, int b, const do
             L = (int)((n - r0) < b ? (n - r0) : b);
         }
         const double* src = V2 + ((g + s) * maxt + j) * (int64_t)b;
-        for (int r = t; r < QR; r += 64) {
+        for (int r = 0; r < QR; ++r) {
             int rr = r - s;
-            Vb[s * QR + r] = (ex && rr >= 0 && rr < L) ? src[rr] : 0.0;
+            Vb[s * LQ + r] = (ex && rr >= 0 && rr < L) ? src[rr] : 0.0;
         }
-        if (t == 0) tv[s] = ex ? tau2[(g + s) * maxt + j] : 0.0;
+        tv[s] = ex ? tau2[(g + s) * maxt + j] : 0.0;
     }
     __syncthreads();
-    // Gram: G[s1][s2] = sum_r V[r][s1] V[r][s2], thread t = column s2
+    // Gram G[s1][s2] = sum_r V[r][s1] V[r][s2], thread t = column s2
     for (int s1 = 0; s1 < QB; ++s1) {
         double acc = 0.0;
-        for (int r = 0; r < QR; ++r) acc += Vb[s1 * QR + r] * Vb[t * QR + r];
+        for (int r = 0; r < QR; ++r) acc += Vb[s1 * LQ + r] * Vb[t * LQ + r];
         Gs[s1 + t * LV] = acc;
     }
     __syncthreads();
@@ -70,41 +77,43 @@ __global__ __launch_bounds__(64) void q2_larft_kernel(int64_t n, int b, const do
         if (t > jj) Ts[t + jj * LV] = 0.0;
         __syncthreads();
     }
-    double* out = T2 + ((g / b) * maxt + j) * (int64_t)QB * QB;
-    for (int jj = 0; jj < QB; ++jj) out[t + jj * QB] = Ts[t + jj * LV];
+    double* vout = VB + j * VBLK;
+    for (int e = t; e < QR * QB; e += 64) {
+        int sidx = e % QB, r = e / QB;
+        vout[sidx + r * LV] = Vb[sidx * LQ + r];
+    }
+    double* tout = TB + j * TBLK;
+    for (int e = t; e < QB * QB; e += 64) {
+        int tt = e % QB, jj = e / QB;
+        tout[tt + jj * LV] = Ts[tt + jj * LV];
+    }
 }
 
 // Apply the blocks of group g (j ascending) to Z[:, slab].
-__global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, const double* __restrict__ V2, int64_t maxt,
-                                                       int64_t g, const double* __restrict__ T2, double* Z,
-                                                       int64_t ldz, int64_t ncols) {
-    __shared__ double Vt[QR * LV];  // Vt[s + r*LV] = V[r][s]
-    __shared__ double Ts[QB * LV];
+__global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t g, const double* __restrict__ VB,
+                                                       const double* __restrict__ TB, double* Z, int64_t ldz,
+                                                       int64_t ncols) {
+    __shared__ __attribute__((aligned(16))) double Vt[QR * LV];  // Vt[s + r*LV] = V[r][s]
+    __shared__ __attribute__((aligned(16))) double Ts[QB * LV];
     __shared__ double Zs[NC * LZ];  // Zs[r + c*LZ]
     __shared__ double W[NC * LW];   // W[s + c*LW]
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int lr = lane >> 4, lc = lane & 15;
     const int64_t col0 = (int64_t)blockIdx.x * NC;
-    const int64_t nsw = n - 2;
     const int64_t ntg = ntasks(n, b, g);
     for (int64_t j = 0; j < ntg; ++j) {
         const int64_t base = g + 1 + j * b;
         const int rows = (int)((n - base) < QR ? (n - base) : QR);
-        // stage V (transposed), T, Z slab
-        for (int e = t; e < QR * QB; e += 256) {
-            int r = e % QR, s = e / QR;
-            double v = 0.0;
-            if (s < b && g + s < nsw && j < ntasks(n, b, g + s)) {
-                int64_t r0 = base + s;
-                int L = (int)((n - r0) < b ? (n - r0) : b);
-                int rr = r - s;
-                if (rr >= 0 && rr < L) v = V2[((g + s) * maxt + j) * (int64_t)b + rr];
-            }
-            Vt[s + r * LV] = v;
+        // stage the packed V (transposed) and T blocks, and the Z slab
+        {
+            const double2* vsrc = reinterpret_cast<const double2*>(VB + j * VBLK);
+            double2* vdst = reinterpret_cast<double2*>(Vt);
+            for (int e = t; e < VBLK / 2; e += 256) vdst[e] = vsrc[e];
+            const double2* tsrc = reinterpret_cast<const double2*>(TB + j * TBLK);
+            double2* tdst = reinterpret_cast<double2*>(Ts);
+            for (int e = t; e < TBLK / 2; e += 256) tdst[e] = tsrc[e];
         }
-        const double* Tb = T2 + ((g / b) * maxt + j) * (int64_t)QB * QB;
-        for (int e = t; e < QB * QB; e += 256) Ts[(e % QB) + (e / QB) * LV] = Tb[e];
         for (int e = t; e < QR * NC; e += 256) {
             int r = e % QR, c = e / QR;
             Zs[r + c * LZ] = (r < rows && col0 + c < ncols) ? Z[(base + r) + (col0 + c) * ldz] : 0.0;
@@ -191,23 +200,24 @@ __global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, const d
 
 }  // namespace
 
-int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) { return (FL_DIV_UP(n, b) + 1) * maxt * (int64_t)QB * QB; }
+// Packed blocks of one group: maxt V blocks and maxt T blocks.
+int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) { (void)n; (void)b; return maxt * (VBLK + TBLK) + 2; }
 
-// Z (n x ncols) := Q2 Z with the reflectors of fl_sb2st.  T2: fl_q2_t_elems doubles.
-hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* T2,
+// Z (n x ncols) := Q2 Z with the reflectors of fl_sb2st.  work: fl_q2_t_elems doubles.
+hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* work,
                        double* Z, int64_t ldz, int64_t ncols) {
     if (n < 3 || b < 2) return hipSuccess;
     const int64_t nsw = n - 2;
+    double* VB = work;
+    double* TB = work + maxt * VBLK;
     hipError_t e;
-    for (int64_t g = 0; g < nsw; g += b) {
-        int64_t nt = 1 + (n - 3 - g) / b;
-        q2_larft_kernel<<<(unsigned)nt, 64, 0, s>>>(n, b, V2, tau2, maxt, g, T2);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     const int64_t ngroups = FL_DIV_UP(nsw, b);
     for (int64_t gi = ngroups - 1; gi >= 0; --gi) {
-        int64_t g = gi * b;
-        q2_apply_kernel<<<(unsigned)FL_DIV_UP(ncols, NC), 256, 0, s>>>(n, b, V2, maxt, g, T2, Z, ldz, ncols);
+        const int64_t g = gi * b;
+        const int64_t nt = 1 + (n - 3 - g) / b;
+        q2_prep_kernel<<<(unsigned)nt, 64, 0, s>>>(n, b, V2, tau2, maxt, g, VB, TB);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        q2_apply_kernel<<<(unsigned)FL_DIV_UP(ncols, NC), 256, 0, s>>>(n, b, g, VB, TB, Z, ldz, ncols);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

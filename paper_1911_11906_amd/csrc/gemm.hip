@@ -12,35 +12,105 @@
 // Workgroup tile 128 x 128, k-step 16, 256 threads = 2 x 2 waves of 64 x 64.
 // Both operand tiles are staged k-major in LDS and double buffered; one
 // barrier per k-step.
+#include <algorithm>
 #include "gemm_tile.h"
 
 namespace {
 using namespace fl_tile;
 
+constexpr int GKB = 32, GNBUF = 1;  // k-step 32 with register prefetch (measured best on gfx950)
+
 template <bool TA, bool TB, bool LOWER>
 __global__ __launch_bounds__(NT) void dgemm_kernel(GemmProblem g) {
-    __shared__ double As[2 * BK * SA];
-    __shared__ double Bs[2 * BK * SB];
+    __shared__ double As[TileLds<GKB, GNBUF>::A];
+    __shared__ double Bs[TileLds<GKB, GNBUF>::B];
     const int64_t bi = blockIdx.x, bj = blockIdx.y;
     if (LOWER && (bi + 1) * BM <= bj * BN) return;  // tile strictly above the diagonal
     BPlain bsrc{g.B, g.ldb, TB};
-    tile_gemm<TA, !TB>(g.m, g.n, g.k, g.A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi, bj, As, Bs);
+    tile_gemm<TA, !TB, BPlain, GKB, GNBUF>(g.m, g.n, g.k, g.A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi, bj, As,
+                                           Bs);
+}
+
+// Split-K: slice z of the k range into its own partial product P_z (beta = 0).
+template <bool TA, bool TB>
+__global__ __launch_bounds__(NT) void dgemm_splitk_kernel(GemmProblem g, int64_t kc, double* P) {
+    __shared__ double As[TileLds<GKB, GNBUF>::A];
+    __shared__ double Bs[TileLds<GKB, GNBUF>::B];
+    const int64_t z = blockIdx.z;
+    const int64_t koff = z * kc;
+    const int64_t ks = (g.k - koff) < kc ? (g.k - koff) : kc;
+    const double* A = TA ? g.A + koff : g.A + koff * g.lda;
+    const double* B = TB ? g.B + koff * g.ldb : g.B + koff;
+    BPlain bsrc{B, g.ldb, TB};
+    tile_gemm<TA, !TB, BPlain, GKB, GNBUF>(g.m, g.n, ks > 0 ? ks : 0, A, g.lda, bsrc, g.alpha, 0.0, P + z * g.m * g.n,
+                                           g.m, blockIdx.x, blockIdx.y, As, Bs);
+}
+
+// C = beta C + sum_z P_z, fixed summation order (deterministic)
+__global__ void splitk_reduce_kernel(int64_t m, int64_t n, int S, const double* __restrict__ P, double beta,
+                                     double* C, int64_t ldc) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+        double acc = 0.0;
+        for (int z = 0; z < S; ++z) acc += P[(int64_t)z * m * n + i + j * m];
+        double* c = C + i + j * ldc;
+        *c = (beta != 0.0) ? beta * (*c) + acc : acc;
+    }
 }
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(NT) void dgemm_batched_kernel(const GemmProblem* __restrict__ probs) {
-    __shared__ double As[2 * BK * SA];
-    __shared__ double Bs[2 * BK * SB];
+    __shared__ double As[TileLds<GKB, GNBUF>::A];
+    __shared__ double Bs[TileLds<GKB, GNBUF>::B];
     const GemmProblem g = probs[blockIdx.z];
     const int64_t bi = blockIdx.x, bj = blockIdx.y;
     if (bi * BM >= g.m || bj * BN >= g.n) return;
     BPlain bsrc{g.B, g.ldb, TB};
-    tile_gemm<TA, !TB>(g.m, g.n, g.k, g.A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi, bj, As, Bs);
+    tile_gemm<TA, !TB, BPlain, GKB, GNBUF>(g.m, g.n, g.k, g.A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi, bj, As,
+                                           Bs);
+}
+
+// Split-K workspace: one buffer per device, allocated once and never resized
+// (a resize could free memory that queued kernels still use); the split
+// factor is capped to what fits.
+constexpr int64_t SPLITK_WS = 32ll << 20;  // doubles (256 MB)
+double* splitk_ws(int dev) {
+    static double* ws[64] = {nullptr};
+    static bool failed[64] = {false};
+    if (dev < 0 || dev >= 64) return nullptr;
+    if (!ws[dev] && !failed[dev]) {
+        if (hipMalloc(&ws[dev], sizeof(double) * SPLITK_WS) != hipSuccess) {
+            ws[dev] = nullptr;
+            failed[dev] = true;
+            (void)hipGetLastError();
+        }
+    }
+    return ws[dev];
 }
 
 template <bool TA, bool TB>
 hipError_t launch(hipStream_t s, const GemmProblem& g, int lower) {
-    dim3 grid((unsigned)FL_DIV_UP(g.m, BM), (unsigned)FL_DIV_UP(g.n, BN));
+    const int64_t tm = FL_DIV_UP(g.m, BM), tn = FL_DIV_UP(g.n, BN);
+    const int64_t tiles = tm * tn;
+    // few output tiles and a long k: split k so that the chip fills up
+    if (!lower && tiles < 384 && g.k >= 2048) {
+        int64_t S = std::min<int64_t>({FL_DIV_UP(768, tiles), g.k / 512, 32});
+        while (S > 1 && S * g.m * g.n > SPLITK_WS) --S;
+        int dev = 0;
+        double* P = (S > 1 && hipGetDevice(&dev) == hipSuccess) ? splitk_ws(dev) : nullptr;
+        if (S > 1 && P) {
+            int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), GKB) * GKB;
+            S = FL_DIV_UP(g.k, kc);
+            dgemm_splitk_kernel<TA, TB><<<dim3((unsigned)tm, (unsigned)tn, (unsigned)S), NT, 0, s>>>(g, kc, P);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            dim3 rg((unsigned)FL_DIV_UP(g.m, 256), (unsigned)std::min<int64_t>(g.n, 65535));
+            splitk_reduce_kernel<<<rg, 256, 0, s>>>(g.m, g.n, (int)S, P, g.beta, g.C, g.ldc);
+            return hipGetLastError();
+        }
+    }
+    dim3 grid((unsigned)tm, (unsigned)tn);
     if (lower)
         dgemm_kernel<TA, TB, true><<<grid, NT, 0, s>>>(g);
     else

@@ -7,8 +7,10 @@
 // reflector on rows R_1 = [i+b+1, i+2b], and so on down the band.  Only the
 // first column of each bulge is removed; the rest is removed by later sweeps,
 // so the working band holds 2b sub-diagonals.  Task (i, j) touches
-// rows/columns [i+1+(j-1)b, i+(j+2)b]; tasks of sweep i-1 overlap it for
-// j' in [j-3, j+3], so (i, j) may start once sweep i-1 has finished task j+3.
+// the blocks (R_j, R_{j-1}), (R_j, R_j) and (R_{j+1}, R_j); the blocks of task
+// (i-1, j') are the same blocks shifted up by one row and column, which meet
+// those of (i, j) only for j' in [j-1, j+2].  So (i, j) may start once sweep
+// i-1 has finished task j+2.
 //
 // One persistent cooperative launch: workgroup w runs sweeps w, w+G, ...;
 // each task stages its three b x b blocks in LDS; per-sweep progress
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
             if (t == 0) {
                 quit = 0;
                 if (i > 0) {
-                    int need = (int)((j + 4 < ntp) ? (j + 4) : ntp);
+                    int need = (int)((j + 3 < ntp) ? (j + 3) : ntp);
                     long spins = 0;
                     while (__hip_atomic_load(&prog[i - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         __builtin_amdgcn_s_sleep(2);
@@ -192,8 +194,8 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
             double* vout = V2 + (i * maxt + j) * (int64_t)b;
             for (int r = t; r < b; r += NTH) vout[r] = (r < L) ? vv[r] : 0.0;
             if (t == 0) tau2[i * maxt + j] = tauc;
-            // ---- publish progress
-            __threadfence();
+            // ---- publish progress: the barrier orders every wave's stores before
+            // thread 0's agent-scope release (which writes the L2 back)
             __syncthreads();
             if (t == 0) __hip_atomic_store(&prog[i], (int)(j + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             // the block below becomes the next off-diagonal block

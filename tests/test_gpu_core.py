@@ -164,3 +164,19 @@ def test_error_paths(ctx, c1_oracle):
     with pytest.raises(FraclapError) as e:
         Operator.assemble(ctx, bad)
     assert e.value.status == FL_EINVAL
+
+
+def test_apply_uniform_tile_path(ctx, oracle_mod, c1_oracle):
+    """nf a multiple of 128: every GEMM tile shares one alpha (the weight is
+    applied once per k-row); same answer as the oracle."""
+    note("apply nf=256 uniform-tile path")
+    from paper_1911_11906_amd.api import Operator
+    mesh, K, M, th, V = c1_oracle
+    op = Operator.assemble(ctx, mesh)
+    op.set_eigenpairs(th, V)
+    F = inputs.polynomial_forcings(mesh, 256, tag=31)
+    al = np.array([0.0, 0.8, 2.0])
+    U = to_np(op.apply(F, al))
+    Uo = oracle_mod.apply_fractional(th, V, M, F, al)
+    assert np.abs(U - Uo).max() <= 1e-12 * np.abs(Uo).max()
+    assert np.abs(U[:, :256] - F).max() <= 2e-12 * np.abs(F).max()
