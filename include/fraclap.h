@@ -71,9 +71,13 @@ enum {
 typedef struct fl_eig_opts {
     int32_t band;             /* band width of the two-stage reduction (0 = default 64) */
     int32_t leaf;             /* divide-and-conquer leaf size (0 = default 32) */
-    int32_t refine_max_iters; /* mixed mode: refinement sweeps (-1 = default 2) */
+    int32_t refine_max_iters; /* refinement steps (-1 = default: 3 in mixed mode, 0 in FP64) */
     double refine_tol;        /* mixed mode: stop when max |r_ij| below this (0 = default 1e-13) */
+    int32_t mixed_flags;      /* mixed mode: 0 = FP32 band reduction and back-transforms;
+                                 FL_MIXED_FP64_BAND = FP64 band reduction, FP32 back-transforms */
 } fl_eig_opts;
+
+enum { FL_MIXED_FP64_BAND = 1 };
 
 typedef struct fl_eig_info {
     int32_t status;           /* FL_OK or the failing status */
@@ -172,6 +176,15 @@ int fl_dsytrd_2stage(fl_ctx *ctx, int64_t n, double *A, int64_t lda, int band, d
 /* All eigenpairs of the symmetric A (full storage, destroyed): w ascending,
  * Z orthonormal (n x n, ld ldz). */
 int fl_dsyevd(fl_ctx *ctx, int64_t n, double *A, int64_t lda, int band, double *w, double *Z, int64_t ldz);
+
+/* ---- diagnostics ----------------------------------------------------------
+ * Per-kernel timing for the library's main kernels ("q2_apply", "sb2st",
+ * "scaled_gemm"): while enabled, HIP events are recorded on the launching
+ * stream around each launch.  fl_kernel_time waits for the recorded events,
+ * returns the launch count and the summed duration for `name`, and clears
+ * them.  Process-wide; FL_EINVAL for NULL arguments. */
+int fl_kernel_timing(int enable);
+int fl_kernel_time(const char *name, int64_t *count, double *total_ms);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@ SO_PATH = os.path.join(HERE, "libfraclap.so")
 FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENOTSPD, FL_ENOCONV, FL_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FL_ELEM_P1, FL_ELEM_Q1 = 3, 4
 FL_FP64, FL_MIXED = 0, 1
+FL_MIXED_FP64_BAND = 1
 STAGES = ["potrf", "sygst", "sy2sb", "sb2st", "stedc", "q2", "q1", "trsm", "refine"]
 FL_NSTAGES = len(STAGES)
 
@@ -27,12 +28,14 @@ EXPORTS = [
     "fl_eigensolve", "fl_eigenpairs", "fl_op_set_eigenpairs",
     "fl_apply_fractional", "fl_grad_apply",
     "fl_dgemm", "fl_dpotrf", "fl_dsygst", "fl_dstedc", "fl_dsytrd_2stage", "fl_dsyevd",
+    "fl_kernel_timing", "fl_kernel_time",
 ]
 
 
 class FlEigOpts(ctypes.Structure):
     _fields_ = [("band", ctypes.c_int32), ("leaf", ctypes.c_int32),
-                ("refine_max_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
+                ("refine_max_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double),
+                ("mixed_flags", ctypes.c_int32)]
 
 
 class FlEigInfo(ctypes.Structure):
@@ -87,6 +90,8 @@ def load(path: str = SO_PATH):
         "fl_dstedc": ([P, i64, P, P, P, i64], i32),
         "fl_dsytrd_2stage": ([P, i64, P, i64, i32, P, P, P, i64], i32),
         "fl_dsyevd": ([P, i64, P, i64, i32, P, P, i64], i32),
+        "fl_kernel_timing": ([i32], i32),
+        "fl_kernel_time": ([ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

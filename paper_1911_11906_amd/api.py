@@ -197,9 +197,11 @@ class Operator:
         return K, M
 
     def eigensolve(self, precision: str = "fp64", band: int = 0, leaf: int = 0, refine_max_iters: int = -1,
-                   refine_tol: float = 0.0) -> dict:
+                   refine_tol: float = 0.0, fp64_band: bool = False) -> dict:
+        """precision "fp64" or "mixed"; fp64_band keeps the band reduction in
+        FP64 in mixed mode (back-transforms stay FP32)."""
         prec = {"fp64": _lib.FL_FP64, "mixed": _lib.FL_MIXED}[precision]
-        opts = FlEigOpts(band, leaf, refine_max_iters, refine_tol)
+        opts = FlEigOpts(band, leaf, refine_max_iters, refine_tol, _lib.FL_MIXED_FP64_BAND if fp64_band else 0)
         info = FlEigInfo()
         self.ctx._sync_stream()
         rc = self.ctx.lib.fl_eigensolve(self.ptr, prec, ctypes.byref(opts), ctypes.byref(info))

@@ -154,6 +154,7 @@ hipError_t fl_scaled_gemm(hipStream_t s, int64_t n, const double* V, int64_t ldv
     int64_t ncol = paired ? nf : nf * na;
     if (n <= 0 || ncol <= 0) return hipSuccess;
     dim3 grid((unsigned)FL_DIV_UP(n, BM), (unsigned)FL_DIV_UP(ncol, BN));
+    KScope ks("scaled_gemm", s);
     if (!paired && nf % BN == 0) {
         BScaledUniform bs{W, ldw, C, ldc, nf};
         scaled_gemm_kernel<BScaledUniform><<<grid, NT, 0, s>>>(n, ncol, V, ldv, bs, U, ldu);

@@ -11,6 +11,7 @@
 //
 // Q1 (band reduction) is applied panel by panel, last first, with GEMMs.
 #include "internal.h"
+#include "gemm_tile.h"
 
 namespace {
 
@@ -30,9 +31,10 @@ constexpr int LQ = QR + 1;
 constexpr int64_t VBLK = (int64_t)QR * LV;  // doubles per packed V block
 constexpr int64_t TBLK = (int64_t)QB * LV;  // doubles per packed T block
 
+template <class OT>
 __global__ __launch_bounds__(64) void q2_prep_kernel(int64_t n, int b, const double* __restrict__ V2,
                                                      const double* __restrict__ tau2, int64_t maxt, int64_t g,
-                                                     double* VB, double* TB) {
+                                                     OT* VB, OT* TB) {
     __shared__ double Vb[QB * LQ];  // Vb[s*LQ + r]
     __shared__ double Gs[QB * LV];
     __shared__ double Ts[QB * LV];
@@ -77,26 +79,28 @@ __global__ __launch_bounds__(64) void q2_prep_kernel(int64_t n, int b, const dou
         if (t > jj) Ts[t + jj * LV] = 0.0;
         __syncthreads();
     }
-    double* vout = VB + j * VBLK;
+    OT* vout = VB + j * VBLK;
     for (int e = t; e < QR * QB; e += 64) {
         int sidx = e % QB, r = e / QB;
-        vout[sidx + r * LV] = Vb[sidx * LQ + r];
+        vout[sidx + r * LV] = (OT)Vb[sidx * LQ + r];
     }
-    double* tout = TB + j * TBLK;
+    OT* tout = TB + j * TBLK;
     for (int e = t; e < QB * QB; e += 64) {
         int tt = e % QB, jj = e / QB;
-        tout[tt + jj * LV] = Ts[tt + jj * LV];
+        tout[tt + jj * LV] = (OT)Ts[tt + jj * LV];
     }
 }
 
 // Apply the blocks of group g (j ascending) to Z[:, slab].
-__global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t g, const double* __restrict__ VB,
-                                                       const double* __restrict__ TB, double* Z, int64_t ldz,
-                                                       int64_t ncols) {
-    __shared__ __attribute__((aligned(16))) double Vt[QR * LV];  // Vt[s + r*LV] = V[r][s]
-    __shared__ __attribute__((aligned(16))) double Ts[QB * LV];
-    __shared__ double Zs[NC * LZ];  // Zs[r + c*LZ]
-    __shared__ double W[NC * LW];   // W[s + c*LW]
+template <class T>
+__global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t g, const T* __restrict__ VB,
+                                                       const T* __restrict__ TB, T* Z, int64_t ldz, int64_t ncols) {
+    typedef fl_tile::Mfma<T> MM;
+    typedef typename MM::acc acc_t;
+    __shared__ __attribute__((aligned(16))) T Vt[QR * LV];  // Vt[s + r*LV] = V[r][s]
+    __shared__ __attribute__((aligned(16))) T Ts[QB * LV];
+    __shared__ T Zs[NC * LZ];  // Zs[r + c*LZ]
+    __shared__ T W[NC * LW];   // W[s + c*LW]
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int lr = lane >> 4, lc = lane & 15;
@@ -107,77 +111,77 @@ __global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t
         const int rows = (int)((n - base) < QR ? (n - base) : QR);
         // stage the packed V (transposed) and T blocks, and the Z slab
         {
-            const double2* vsrc = reinterpret_cast<const double2*>(VB + j * VBLK);
-            double2* vdst = reinterpret_cast<double2*>(Vt);
-            for (int e = t; e < VBLK / 2; e += 256) vdst[e] = vsrc[e];
-            const double2* tsrc = reinterpret_cast<const double2*>(TB + j * TBLK);
-            double2* tdst = reinterpret_cast<double2*>(Ts);
-            for (int e = t; e < TBLK / 2; e += 256) tdst[e] = tsrc[e];
+            // 16-byte copies (VBLK and TBLK are multiples of 4 elements; blocks 16-byte aligned)
+            const uint4* vsrc = reinterpret_cast<const uint4*>(VB + j * VBLK);
+            uint4* vdst = reinterpret_cast<uint4*>(Vt);
+            for (int e = t; e < (int)(VBLK * sizeof(T) / 16); e += 256) vdst[e] = vsrc[e];
+            const uint4* tsrc = reinterpret_cast<const uint4*>(TB + j * TBLK);
+            uint4* tdst = reinterpret_cast<uint4*>(Ts);
+            for (int e = t; e < (int)(TBLK * sizeof(T) / 16); e += 256) tdst[e] = tsrc[e];
         }
         for (int e = t; e < QR * NC; e += 256) {
             int r = e % QR, c = e / QR;
-            Zs[r + c * LZ] = (r < rows && col0 + c < ncols) ? Z[(base + r) + (col0 + c) * ldz] : 0.0;
+            Zs[r + c * LZ] = (r < rows && col0 + c < ncols) ? Z[(base + r) + (col0 + c) * ldz] : T(0);
         }
         __syncthreads();
         // W = V^T Zs  (64 x 32): wave w -> tiles (ti = w, tj = 0, 1)
         {
-            d4_t acc[2];
-            acc[0] = d4_t{0, 0, 0, 0};
-            acc[1] = d4_t{0, 0, 0, 0};
+            acc_t acc[2];
+            acc[0] = acc_t{0, 0, 0, 0};
+            acc[1] = acc_t{0, 0, 0, 0};
             const int ti = wave;
             for (int k0 = 0; k0 < QR; k0 += 4) {
-                double a = Vt[(ti * 16 + lc) + (k0 + lr) * LV];
+                T a = Vt[(ti * 16 + lc) + (k0 + lr) * LV];
 #pragma unroll
                 for (int tj = 0; tj < 2; ++tj) {
-                    double bb = Zs[(k0 + lr) + (tj * 16 + lc) * LZ];
-                    acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[tj], 0, 0, 0);
+                    T bb = Zs[(k0 + lr) + (tj * 16 + lc) * LZ];
+                    acc[tj] = MM::mma(a, bb, acc[tj]);
                 }
             }
 #pragma unroll
             for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) W[(ti * 16 + lr + 4 * r) + (tj * 16 + lc) * LW] = acc[tj][r];
+                for (int r = 0; r < 4; ++r) W[(ti * 16 + MM::row(lr, r)) + (tj * 16 + lc) * LW] = acc[tj][r];
         }
         __syncthreads();
         // W := T W  (computed in registers, then written over W)
         {
-            d4_t acc[2];
-            acc[0] = d4_t{0, 0, 0, 0};
-            acc[1] = d4_t{0, 0, 0, 0};
+            acc_t acc[2];
+            acc[0] = acc_t{0, 0, 0, 0};
+            acc[1] = acc_t{0, 0, 0, 0};
             const int ti = wave;
             for (int k0 = 0; k0 < QB; k0 += 4) {
-                double a = Ts[(ti * 16 + lc) + (k0 + lr) * LV];
+                T a = Ts[(ti * 16 + lc) + (k0 + lr) * LV];
 #pragma unroll
                 for (int tj = 0; tj < 2; ++tj) {
-                    double bb = W[(k0 + lr) + (tj * 16 + lc) * LW];
-                    acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[tj], 0, 0, 0);
+                    T bb = W[(k0 + lr) + (tj * 16 + lc) * LW];
+                    acc[tj] = MM::mma(a, bb, acc[tj]);
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) W[(ti * 16 + lr + 4 * r) + (tj * 16 + lc) * LW] = acc[tj][r];
+                for (int r = 0; r < 4; ++r) W[(ti * 16 + MM::row(lr, r)) + (tj * 16 + lc) * LW] = acc[tj][r];
         }
         __syncthreads();
         // Zs -= V W  (128 x 32): wave w -> tiles ti = 2w, 2w+1; tj = 0, 1
         {
-            d4_t acc[2][2];
+            acc_t acc[2][2];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int c = 0; c < 2; ++c) acc[a][c] = d4_t{0, 0, 0, 0};
+                for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
             for (int k0 = 0; k0 < QB; k0 += 4) {
-                double bb[2];
+                T bb[2];
 #pragma unroll
                 for (int tj = 0; tj < 2; ++tj) bb[tj] = W[(k0 + lr) + (tj * 16 + lc) * LW];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
                     const int ti = 2 * wave + a;
-                    double av = Vt[(k0 + lr) + (ti * 16 + lc) * LV];
+                    T av = Vt[(k0 + lr) + (ti * 16 + lc) * LV];
 #pragma unroll
-                    for (int tj = 0; tj < 2; ++tj)
-                        acc[a][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bb[tj], acc[a][tj], 0, 0, 0);
+                    for (int tj = 0; tj < 2; ++tj) acc[a][tj] = MM::mma(av, bb[tj], acc[a][tj]);
                 }
             }
 #pragma unroll
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t
 #pragma unroll
                 for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Zs[(ti * 16 + lr + 4 * r) + (tj * 16 + lc) * LZ] -= acc[a][tj][r];
+                    for (int r = 0; r < 4; ++r) Zs[(ti * 16 + MM::row(lr, r)) + (tj * 16 + lc) * LZ] -= acc[a][tj][r];
             }
         }
         __syncthreads();
@@ -199,47 +203,75 @@ __global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t
 }
 
 }  // namespace
+int64_t fl_sy2sb_panels(int64_t n, int b);
+namespace {
 
-// Packed blocks of one group: maxt V blocks and maxt T blocks.
-int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) { (void)n; (void)b; return maxt * (VBLK + TBLK) + 2; }
-
-// Z (n x ncols) := Q2 Z with the reflectors of fl_sb2st.  work: fl_q2_t_elems doubles.
-hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* work,
-                       double* Z, int64_t ldz, int64_t ncols) {
+template <class T>
+hipError_t q2_apply_t(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, T* work,
+                      T* Z, int64_t ldz, int64_t ncols) {
+    static_assert((VBLK * sizeof(float)) % 16 == 0 && (TBLK * sizeof(float)) % 16 == 0, "16-byte blocks");
     if (n < 3 || b < 2) return hipSuccess;
     const int64_t nsw = n - 2;
-    double* VB = work;
-    double* TB = work + maxt * VBLK;
+    T* VB = work;
+    T* TB = work + maxt * VBLK;
     hipError_t e;
     const int64_t ngroups = FL_DIV_UP(nsw, b);
     for (int64_t gi = ngroups - 1; gi >= 0; --gi) {
         const int64_t g = gi * b;
         const int64_t nt = 1 + (n - 3 - g) / b;
-        q2_prep_kernel<<<(unsigned)nt, 64, 0, s>>>(n, b, V2, tau2, maxt, g, VB, TB);
+        q2_prep_kernel<T><<<(unsigned)nt, 64, 0, s>>>(n, b, V2, tau2, maxt, g, VB, TB);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        q2_apply_kernel<<<(unsigned)FL_DIV_UP(ncols, NC), 256, 0, s>>>(n, b, g, VB, TB, Z, ldz, ncols);
+        {
+            KScope ks("q2_apply", s);
+            q2_apply_kernel<T><<<(unsigned)FL_DIV_UP(ncols, NC), 256, 0, s>>>(n, b, g, VB, TB, Z, ldz, ncols);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// Z (n x ncols) := Q1 Z, Q1 = prod over panels of (I - V_p T_p V_p^T).
-// work: >= 2 * b * ncols doubles.
-hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
-                       int64_t ldz, int64_t ncols, double* work) {
+template <class T>
+hipError_t q1_apply_t(hipStream_t s, int64_t n, int b, const T* V1, int64_t ldv, const T* T1, T* Z, int64_t ldz,
+                      int64_t ncols, T* work) {
     int64_t np = fl_sy2sb_panels(n, b);
     hipError_t e;
     for (int64_t p = np - 1; p >= 0; --p) {
         const int64_t c0 = p * b, r0 = c0 + b, m = n - r0;
         const int kref = (int)std::min<int64_t>(b, m - 1);
         if (kref <= 0) continue;
-        const double* Vp = V1 + r0 + c0 * ldv;
-        const double* Tp = T1 + p * (int64_t)b * b;
-        double* W1 = work;
-        double* W2 = work + (int64_t)b * ncols;
-        if ((e = fl_dgemm(s, 1, 0, kref, ncols, m, 1.0, Vp, ldv, Z + r0, ldz, 0.0, W1, b))) return e;
-        if ((e = fl_dgemm(s, 0, 0, kref, ncols, kref, 1.0, Tp, b, W1, b, 0.0, W2, b))) return e;
-        if ((e = fl_dgemm(s, 0, 0, m, ncols, kref, -1.0, Vp, ldv, W2, b, 1.0, Z + r0, ldz))) return e;
+        const T* Vp = V1 + r0 + c0 * ldv;
+        const T* Tp = T1 + p * (int64_t)b * b;
+        T* W1 = work;
+        T* W2 = work + (int64_t)b * ncols;
+        if ((e = fl_gemm_t(s, 1, 0, kref, ncols, m, 1.0, Vp, ldv, Z + r0, ldz, 0.0, W1, b))) return e;
+        if ((e = fl_gemm_t(s, 0, 0, kref, ncols, kref, 1.0, Tp, b, W1, b, 0.0, W2, b))) return e;
+        if ((e = fl_gemm_t(s, 0, 0, m, ncols, kref, -1.0, Vp, ldv, W2, b, 1.0, Z + r0, ldz))) return e;
     }
     return hipSuccess;
+}
+
+}  // namespace
+
+// Packed blocks of one group: maxt V blocks and maxt T blocks (elements).
+int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) { (void)n; (void)b; return maxt * (VBLK + TBLK) + 4; }
+
+// Z (n x ncols) := Q2 Z with the reflectors of fl_sb2st.  work: fl_q2_t_elems elements.
+hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* work,
+                       double* Z, int64_t ldz, int64_t ncols) {
+    return q2_apply_t<double>(s, n, b, V2, tau2, maxt, work, Z, ldz, ncols);
+}
+hipError_t fl_q2_apply_f(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt,
+                         float* work, float* Z, int64_t ldz, int64_t ncols) {
+    return q2_apply_t<float>(s, n, b, V2, tau2, maxt, work, Z, ldz, ncols);
+}
+
+// Z (n x ncols) := Q1 Z, Q1 = prod over panels of (I - V_p T_p V_p^T).
+// work: >= 2 * b * ncols elements.
+hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
+                       int64_t ldz, int64_t ncols, double* work) {
+    return q1_apply_t<double>(s, n, b, V1, ldv, T1, Z, ldz, ncols, work);
+}
+hipError_t fl_q1_apply_f(hipStream_t s, int64_t n, int b, const float* V1, int64_t ldv, const float* T1, float* Z,
+                         int64_t ldz, int64_t ncols, float* work) {
+    return q1_apply_t<float>(s, n, b, V1, ldv, T1, Z, ldz, ncols, work);
 }

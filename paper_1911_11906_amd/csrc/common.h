@@ -39,6 +39,21 @@ hipError_t fl_sgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t
                     const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                     int64_t ldc);
 
+hipError_t fl_d2s(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, float* B, int64_t ldb);
+hipError_t fl_s2d(hipStream_t s, int64_t m, int64_t n, const float* A, int64_t lda, double* B, int64_t ldb);
+
+// type-dispatched GEMM (FP64 or FP32 matrix cores)
+inline hipError_t fl_gemm_t(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+                            const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                            int64_t ldc) {
+    return fl_dgemm(s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+inline hipError_t fl_gemm_t(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+                            const float* A, int64_t lda, const float* B, int64_t ldb, double beta, float* C,
+                            int64_t ldc) {
+    return fl_sgemm(s, ta, tb, m, n, k, (float)alpha, A, lda, B, ldb, (float)beta, C, ldc);
+}
+
 // small helpers
 hipError_t fl_copy_matrix(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, double* B,
                           int64_t ldb);

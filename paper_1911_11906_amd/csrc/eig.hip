@@ -25,8 +25,18 @@ hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const 
                        double* Z, int64_t ldz, int64_t ncols);
 hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
                        int64_t ldz, int64_t ncols, double* work);
+hipError_t fl_ssy2sb(hipStream_t s, int64_t n, int b, float* A, int64_t lda, float* V1, int64_t ldv, float* T1,
+                     float* tau1, float* work, float* part, unsigned* cnt, int* abort);
+hipError_t fl_extract_band_f(hipStream_t s, int64_t n, int b, const float* A, int64_t lda, double* AB, int64_t ldab);
+hipError_t fl_q2_apply_f(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt,
+                         float* work, float* Z, int64_t ldz, int64_t ncols);
+hipError_t fl_q1_apply_f(hipStream_t s, int64_t n, int b, const float* V1, int64_t ldv, const float* T1, float* Z,
+                         int64_t ldz, int64_t ncols, float* work);
 // stedc.hip
 int fl_stedc_device(fl_ctx* ctx, int64_t n, double* d, const double* e, double* Zout, int64_t ldz, int leaf);
+// refine.hip
+int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t ldx, int max_iters, double tol,
+                     fl_eig_info* info);
 
 namespace {
 
@@ -137,6 +147,87 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
     return FL_OK;
 }
 
+// Mixed precision: both back-transforms (and, with fp32_band, the band
+// reduction) on the FP32 matrix cores; the bulge chasing and the divide and
+// conquer in FP64.  C is destroyed.
+int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int band, int fp32_band, double* w,
+                          double* Z, int64_t ldz, fl_eig_info* info, int leaf, StageTimer* tm) {
+    hipStream_t s = ctx->stream;
+    const int b = clamp_band(n, band);
+    const int64_t ldab = 2 * b + 1;
+    const int64_t np = std::max<int64_t>(1, fl_sy2sb_panels(n, b));
+    const int64_t maxt = fl_sb2st_maxt(n, b);
+    const int64_t nsw = std::max<int64_t>(1, n - 2);
+    DevBuf bA, bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
+    FL_HIP(ctx, bA.alloc(sizeof(float) * (size_t)n * n));
+    FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+    FL_HIP(ctx, bV1.alloc(sizeof(float) * (size_t)n * n));
+    FL_HIP(ctx, bT1.alloc(sizeof(float) * np * b * b));
+    FL_HIP(ctx, btau1.alloc(sizeof(float) * (n + b)));
+    FL_HIP(ctx, bwork.alloc(sizeof(float) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+    FL_HIP(ctx, bpart.alloc(sizeof(float) * fl_sy2sb_part_elems(n)));
+    FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
+    FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
+    FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
+    FL_HIP(ctx, bprog.alloc(sizeof(int) * (n + 2)));
+    FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
+    double* e = be.as<double>();
+    float* A = bA.as<float>();
+    int* abort_flag = bprog.as<int>() + n + 1;
+    FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
+
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
+    if (fp32_band) {
+        FL_HIP(ctx, fl_d2s(s, n, n, C, ldc, A, n));
+        FL_HIP(ctx, fl_ssy2sb(s, n, b, A, n, bV1.as<float>(), n, bT1.as<float>(), btau1.as<float>(),
+                              bwork.as<float>(), bpart.as<float>(), bcnt.as<unsigned>(), abort_flag));
+        FL_HIP(ctx, fl_extract_band_f(s, n, b, A, n, bAB.as<double>(), ldab));
+    } else {
+        // FP64 band reduction; its block reflectors are rounded to FP32 for Q1
+        DevBuf bV1d, bT1d, btau1d, bworkd, bpartd;
+        FL_HIP(ctx, bV1d.alloc(sizeof(double) * (size_t)n * n));
+        FL_HIP(ctx, bT1d.alloc(sizeof(double) * np * b * b));
+        FL_HIP(ctx, btau1d.alloc(sizeof(double) * (n + b)));
+        FL_HIP(ctx, bworkd.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+        FL_HIP(ctx, bpartd.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
+        FL_HIP(ctx, fl_sy2sb(s, n, b, C, ldc, bV1d.as<double>(), n, bT1d.as<double>(), btau1d.as<double>(),
+                             bworkd.as<double>(), bpartd.as<double>(), bcnt.as<unsigned>(), abort_flag));
+        FL_HIP(ctx, fl_extract_band(s, n, b, C, ldc, bAB.as<double>(), ldab));
+        FL_HIP(ctx, fl_d2s(s, n, n, bV1d.as<double>(), n, bV1.as<float>(), n));
+        FL_HIP(ctx, fl_d2s(s, np * b, b, bT1d.as<double>(), np * b, bT1.as<float>(), np * b));
+        FL_HIP(ctx, hipStreamSynchronize(s));  // the FP64 buffers are released at scope exit
+    }
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
+    FL_HIP(ctx, fl_sb2st(s, n, b, bAB.as<double>(), ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
+                         grid_for_sb2st(n, b), abort_flag));
+    {
+        int ab = 0;
+        FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        if (ab) {
+            if (info) info->index = FL_STAGE_SB2ST;
+            return fl_fail(ctx, FL_ENOCONV, "tridiagonalisation: a cooperative wait was abandoned");
+        }
+    }
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_STEDC));
+    int rc = fl_stedc_device(ctx, n, w, e, Z, ldz, leaf);
+    if (rc) {
+        if (info) info->index = FL_STAGE_STEDC;
+        return rc;
+    }
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q2));
+    float* Zf = A;  // the reduced matrix is no longer needed
+    FL_HIP(ctx, fl_d2s(s, n, n, Z, ldz, Zf, n));
+    FL_HIP(ctx, bT2.alloc(sizeof(float) * fl_q2_t_elems(n, b, maxt)));
+    FL_HIP(ctx, fl_q2_apply_f(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<float>(), Zf, n, n));
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q1));
+    FL_HIP(ctx, fl_q1_apply_f(s, n, b, bV1.as<float>(), n, bT1.as<float>(), Zf, n, n, bwork.as<float>()));
+    FL_HIP(ctx, fl_s2d(s, n, n, Zf, n, Z, ldz));
+    if (tm) FL_HIP(ctx, tm->mark(-1));
+    FL_HIP(ctx, hipStreamSynchronize(s));
+    return FL_OK;
+}
+
 extern "C" {
 
 int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info* info) {
@@ -182,13 +273,34 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     FL_HIP(ctx, hipMemcpyAsync(C, op->K, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
     int rc = fl_sygst_device(ctx, n, L, ld, blinv.as<double>(), C, ld, bwork.as<double>());
     if (rc) return rc;
-    rc = fl_syevd_device(ctx, n, C, ld, band, op->theta, op->V, ld, info, leaf, &tm);
+    if (precision == FL_MIXED)
+        rc = fl_syevd_mixed_device(ctx, n, C, ld, band, opts ? !(opts->mixed_flags & FL_MIXED_FP64_BAND) : 1,
+                                   op->theta, op->V, ld, info, leaf, &tm);
+    else
+        rc = fl_syevd_device(ctx, n, C, ld, band, op->theta, op->V, ld, info, leaf, &tm);
     if (rc) {
         if (info) info->status = rc;
         return rc;
     }
     FL_HIP(ctx, tm.mark(FL_STAGE_TRSM));
     FL_HIP(ctx, fl_trsm_llt(s, n, n, L, ld, blinv.as<double>(), op->V, ld, bwork.as<double>()));
+    // refinement: default up to 3 steps in mixed mode (early exit at tol), none in FP64 mode
+    int iters = (opts && opts->refine_max_iters >= 0) ? opts->refine_max_iters : (precision == FL_MIXED ? 3 : 0);
+    double tol = (opts && opts->refine_tol > 0.0) ? opts->refine_tol : 1e-13;
+    if (iters > 0) {
+        FL_HIP(ctx, hipStreamSynchronize(s));  // the TRSM above still reads L
+        bL.release();  // L and C are not needed any more: room for the refinement buffers
+        bC.release();
+        FL_HIP(ctx, tm.mark(FL_STAGE_REFINE));
+        rc = fl_refine_device(ctx, op, op->theta, op->V, ld, iters, tol, info);
+        if (rc) {
+            if (info) {
+                info->status = rc;
+                info->index = FL_STAGE_REFINE;
+            }
+            return rc;
+        }
+    }
     FL_HIP(ctx, fl_log_kernel(s, n, op->theta, op->logtheta));
     FL_HIP(ctx, tm.mark(-1));
     FL_HIP(ctx, hipStreamSynchronize(s));

@@ -12,6 +12,26 @@
 
 namespace fl_tile {
 
+// Matrix-core instruction per element type.  FP64: v_mfma_f64_16x16x4f64,
+// accumulator register r of lane l holds D[l/16 + 4r][l%16]; FP32:
+// v_mfma_f32_16x16x4f32, D[4(l/16) + r][l%16].  Inputs: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16] for both.
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4_t acc;
+    static __device__ inline acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lr, int r) { return lr + 4 * r; }
+};
+template <> struct Mfma<float> {
+    typedef f4_t acc;
+    static __device__ inline acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lr, int r) { return 4 * lr + r; }
+};
+
 constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int SA = BM + 2;  // LDS row strides (doubles)
 constexpr int SB = BN + 2;
@@ -22,42 +42,46 @@ struct TileLds {
     static constexpr int A = NBUF * KB * SA;
     static constexpr int B = NBUF * KB * SB;
 };
+// (elements of the tile's element type)
 
 // Source of op(B)[kk][j].  A thread's columns j are fixed for the whole k
 // loop, so each source hands out a per-column handle once (col()) and then
 // reads element kk through it (at()).
-struct BPlain {
-    const double* B;
+template <class T>
+struct BPlainT {
+    const T* B;
     int64_t ldb;
     bool trans;
     struct H {
-        const double* p;
+        const T* p;
         int64_t stride;
     };
     __device__ inline H col(int64_t j) const { return trans ? H{B + j, ldb} : H{B + j * ldb, 1}; }
-    __device__ inline double at(const H& h, int64_t kk) const { return h.p[kk * h.stride]; }
+    __device__ inline T at(const H& h, int64_t kk) const { return h.p[kk * h.stride]; }
     // per-(tile, k-row) factor applied to every element of that k-row
     static constexpr bool KSCALE = false;
-    __device__ inline double kscale(int64_t, int64_t) const { return 1.0; }
+    __device__ inline T kscale(int64_t, int64_t) const { return T(1); }
 };
+typedef BPlainT<double> BPlain;
 
 // KB: k-step; NBUF: LDS buffers (2 = double buffered, one barrier per step;
 // 1 = register prefetch, two barriers per step, half the LDS).
-template <bool TA, bool KFAST_B, class BSrc, int KB = 32, int NBUF = 1>
-__device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const double* __restrict__ A, int64_t lda,
-                                 const BSrc& bs, double alpha, double beta, double* __restrict__ C, int64_t ldc,
-                                 int64_t bi, int64_t bj, double* As, double* Bs) {
+template <bool TA, bool KFAST_B, class BSrc, int KB = 32, int NBUF = 1, class T = double>
+__device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __restrict__ A, int64_t lda,
+                                 const BSrc& bs, T alpha, T beta, T* __restrict__ C, int64_t ldc,
+                                 int64_t bi, int64_t bj, T* As, T* Bs) {
+    typedef typename Mfma<T>::acc acc_t;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wi = wave & 1, wj = wave >> 1;
     const int64_t i0 = bi * BM, j0 = bj * BN;
-    d4_t acc[4][4];
+    acc_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
     constexpr int NA = BM * KB / NT, NB = BN * KB / NT;
-    double ra[NA], rb[NB];
+    T ra[NA], rb[NB];
     typename BSrc::H bh[NB];
     bool bok[NB];
 #pragma unroll
@@ -75,12 +99,12 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const double* 
             int ii, kk;
             if (!TA) { ii = e % BM; kk = e / BM; } else { kk = e % KB; ii = e / KB; }
             int64_t gi = i0 + ii, gk = k0 + kk;
-            double v = 0.0;
+            T v = T(0);
             if (gi < m && gk < k) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
             ra[r] = v;
         }
         // with KFAST_B every element a thread loads shares one k-row (t % KB)
-        double ks = 1.0;
+        T ks = T(1);
         if (BSrc::KSCALE && KFAST_B && k0 + (t % KB) < k) ks = bs.kscale(j0, k0 + (t % KB));
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
@@ -89,7 +113,7 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const double* 
             if (KFAST_B) { kk = e % KB; jj = e / KB; } else { jj = e % BN; kk = e / BN; }
             int64_t gk = k0 + kk;
             (void)jj;
-            double v = (bok[r] && gk < k) ? bs.at(bh[r], gk) : 0.0;
+            T v = (bok[r] && gk < k) ? bs.at(bh[r], gk) : T(0);
             rb[r] = BSrc::KSCALE ? v * ks : v;
         }
     };
@@ -111,10 +135,10 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const double* 
     };
     const int64_t nkt = FL_DIV_UP(k, KB);
     const int lr = lane >> 4, lc = lane & 15;
-    auto compute = [&](const double* Ac, const double* Bc) {
+    auto compute = [&](const T* Ac, const T* Bc) {
 #pragma unroll
         for (int k4 = 0; k4 < KB; k4 += 4) {
-            double fa[4], fb[4];
+            T fa[4], fb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 fa[q] = Bc[(k4 + lr) * SB + wj * 64 + q * 16 + lc];  // MFMA A operand <- op(B)
@@ -124,7 +148,7 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const double* 
             for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
-                    acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[jb], fb[ib], acc[ib][jb], 0, 0, 0);
+                    acc[ib][jb] = Mfma<T>::mma(fa[jb], fb[ib], acc[ib][jb]);
         }
     };
     if (NBUF == 2) {
@@ -158,11 +182,11 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const double* 
         for (int jb = 0; jb < 4; ++jb) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int64_t gj = j0 + wj * 64 + jb * 16 + lr + 4 * r;
+                int64_t gj = j0 + wj * 64 + jb * 16 + Mfma<T>::row(lr, r);
                 if (gj >= n) continue;
-                double* cp = C + gi + gj * ldc;
-                double v = alpha * acc[ib][jb][r];
-                if (beta != 0.0) v += beta * (*cp);
+                T* cp = C + gi + gj * ldc;
+                T v = alpha * acc[ib][jb][r];
+                if (beta != T(0)) v += beta * (*cp);
                 *cp = v;
             }
         }

@@ -35,6 +35,21 @@ struct fl_op {
     size_t ws_bytes = 0;
 };
 
+// Optional per-kernel timing (ktimer.hip): events around one launch when
+// timing is enabled; a no-op otherwise.
+struct KScope {
+    KScope(const char* name, hipStream_t s);
+    ~KScope();
+    KScope(const KScope&) = delete;
+    KScope& operator=(const KScope&) = delete;
+
+   private:
+    const char* name_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+    bool on_ = false;
+};
+
 // status helpers ------------------------------------------------------------
 int fl_fail(fl_ctx* ctx, int code, const std::string& msg);
 #define FL_HIP(ctx, expr)                                                                     \

@@ -230,7 +230,10 @@ hipError_t fl_sb2st(hipStream_t s, int64_t n, int b, double* AB, int64_t ldab, d
         int64_t nn = n, lda = ldab, mt = maxt;
         int bb = b;
         void* args[] = {&nn, &bb, &AB, &lda, &V2, &tau2, &mt, &prog, &abort};
-        err = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(G), dim3(NTH), args, 0, s);
+        {
+            KScope ks("sb2st", s);
+            err = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(G), dim3(NTH), args, 0, s);
+        }
         if (err != hipSuccess) return err;
     }
     band_to_tridiag_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, AB, ldab, d, e);

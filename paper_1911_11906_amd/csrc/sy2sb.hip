@@ -45,23 +45,24 @@ __device__ inline bool grid_barrier(unsigned* counter, unsigned target, int* abo
 // (ld ldv) the explicit unit-lower V (zeros above the diagonal), tau[c].
 // part: scratch of 2 * G * 64 doubles; prow: 2 * 64; counter: zeroed;
 // abort: raised when a barrier wait is abandoned (the result is then invalid).
-__global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kref, double* P, int64_t lda,
-                                                       double* Vx, int64_t ldv, double* tau, double* part,
-                                                       double* prow, unsigned* counter, int* abort) {
-    __shared__ double xc[PROWS];
-    __shared__ double red[4][64];
-    __shared__ double wv[64];
-    __shared__ double sc[4];  // scale, tau, beta, x0
+template <class T>
+__global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kref, T* P, int64_t lda, T* Vx,
+                                                       int64_t ldv, T* tau, T* part, T* prow, unsigned* counter,
+                                                       int* abort) {
+    __shared__ T xc[PROWS];
+    __shared__ T red[4][64];
+    __shared__ T wv[64];
+    __shared__ T sc[4];  // scale, tau, beta, x0
     const int t = threadIdx.x;
     const int lane = t & 63;   // panel column handled by this thread
     const int grp = t >> 6;    // row group
     const unsigned G = gridDim.x;
     const int64_t slab0 = (int64_t)blockIdx.x * PROWS;
-    double v[PRPT];
+    T v[PRPT];
 #pragma unroll
     for (int q = 0; q < PRPT; ++q) {
         int64_t r = slab0 + grp + 4 * q;
-        v[q] = (r < m && lane < kb) ? P[r + lane * lda] : 0.0;
+        v[q] = (r < m && lane < kb) ? P[r + lane * lda] : T(0);
     }
     for (int c = 0; c < kref; ++c) {
         const int par = c & 1;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         }
         __syncthreads();
         // partial dot products over rows r > c of this slab: s_j = sum x_r a_j[r]
-        double s = 0.0;
+        T s = T(0);
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
             int64_t r = slab0 + grp + 4 * q;
@@ -91,25 +92,25 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         if (!grid_barrier(counter, (unsigned)(c + 1) * G, abort)) return;
         // reduce the partials of all workgroups (fixed order)
         if (t < 64) {
-            double acc = 0.0;
-            const double* pp = part + (size_t)par * G * 64 + t;
+            T acc = T(0);
+            const T* pp = part + (size_t)par * G * 64 + t;
             for (unsigned w = 0; w < G; ++w) acc += pp[(size_t)w * 64];
             wv[t] = acc;
         }
         __syncthreads();
         if (t == 0) {
-            const double x0 = prow[par * 64 + c];
-            const double sig = wv[c];  // |x(1:)|^2
-            double beta, tauc, scale;
-            if (sig == 0.0) {
+            const T x0 = prow[par * 64 + c];
+            const T sig = wv[c];  // |x(1:)|^2
+            T beta, tauc, scale;
+            if (sig == T(0)) {
                 beta = x0;
-                tauc = 0.0;
-                scale = 0.0;
+                tauc = T(0);
+                scale = T(0);
             } else {
-                double nrm = sqrt(x0 * x0 + sig);
-                beta = (x0 >= 0.0) ? -nrm : nrm;
+                T nrm = sqrt(x0 * x0 + sig);
+                beta = (x0 >= T(0)) ? -nrm : nrm;
                 tauc = (beta - x0) / beta;
-                scale = 1.0 / (x0 - beta);
+                scale = T(1) / (x0 - beta);
             }
             sc[0] = scale;
             sc[1] = tauc;
@@ -118,9 +119,9 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
             if (blockIdx.x == 0) tau[c] = tauc;
         }
         __syncthreads();
-        const double scale = sc[0], tauc = sc[1], beta = sc[2];
+        const T scale = sc[0], tauc = sc[1], beta = sc[2];
         // w_j = v^T a_j = a_j[c] + scale * s_j   (j > c)
-        const double wj = (lane > c && lane < kb) ? (prow[par * 64 + lane] + scale * wv[lane]) : 0.0;
+        const T wj = (lane > c && lane < kb) ? (prow[par * 64 + lane] + scale * wv[lane]) : T(0);
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
             int64_t r = slab0 + grp + 4 * q;
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
                 if (r > c) v[q] = scale * v[q];          // reflector entry
                 else if (r == c) v[q] = beta;
             } else if (lane > c && lane < kb) {
-                double vr = (r > c) ? scale * xc[grp + 4 * q] : (r == c ? 1.0 : 0.0);
+                T vr = (r > c) ? scale * xc[grp + 4 * q] : (r == c ? T(1) : T(0));
                 v[q] -= tauc * vr * wj;
             }
         }
@@ -141,28 +142,29 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         int64_t r = slab0 + grp + 4 * q;
         if (r < m && lane < kb) {
             P[r + lane * lda] = v[q];
-            if (lane < kref) Vx[r + lane * ldv] = (r > lane) ? v[q] : (r == lane ? 1.0 : 0.0);
+            if (lane < kref) Vx[r + lane * ldv] = (r > lane) ? v[q] : (r == lane ? T(1) : T(0));
         }
     }
 }
 
 // T (kref x kref upper, ld ldt) of the forward block reflector from the Gram
 // matrix G = V^T V and tau: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) G(0:j, j).
-__global__ __launch_bounds__(64) void larft_gram_kernel(int kref, const double* __restrict__ G, int64_t ldg,
-                                                        const double* __restrict__ tau, double* T, int64_t ldt) {
-    __shared__ double Ts[64 * 64];
-    __shared__ double y[64];
+template <class E>
+__global__ __launch_bounds__(64) void larft_gram_kernel(int kref, const E* __restrict__ G, int64_t ldg,
+                                                        const E* __restrict__ tau, E* T, int64_t ldt) {
+    __shared__ E Ts[64 * 64];
+    __shared__ E y[64];
     const int t = threadIdx.x;
     for (int j = 0; j < kref; ++j) {
         if (t < j) y[t] = G[t + j * ldg];
         __syncthreads();
         if (t < j) {
-            double acc = 0.0;
+            E acc = E(0);
             for (int k = t; k < j; ++k) acc += Ts[t + k * 64] * y[k];
             Ts[t + j * 64] = -tau[j] * acc;
         }
         if (t == j) Ts[j + j * 64] = tau[j];
-        if (t > j && t < kref) Ts[t + j * 64] = 0.0;
+        if (t > j && t < kref) Ts[t + j * 64] = E(0);
         __syncthreads();
     }
     for (int j = 0; j < kref; ++j)
@@ -171,14 +173,94 @@ __global__ __launch_bounds__(64) void larft_gram_kernel(int kref, const double* 
 
 // Band (lower, ld ldab, 2b+1 rows reserved) from the reduced matrix: the
 // first b+1 diagonals, zeros below (room for the bulge-chasing fill).
-__global__ void extract_band_kernel(int64_t n, int b, const double* __restrict__ A, int64_t lda, double* AB,
+template <class T>
+__global__ void extract_band_kernel(int64_t n, int b, const T* __restrict__ A, int64_t lda, double* AB,
                                     int64_t ldab) {
     int64_t c = blockIdx.x;
     for (int d = threadIdx.x; d < ldab; d += blockDim.x) {
         double v = 0.0;
-        if (d <= b && c + d < n) v = A[(c + d) + c * lda];
+        if (d <= b && c + d < n) v = (double)A[(c + d) + c * lda];
         AB[d + c * ldab] = v;
     }
+}
+
+template <class T>
+__global__ void copy_t_kernel(int64_t m, int64_t n, const T* __restrict__ A, int64_t lda, T* __restrict__ B,
+                              int64_t ldb) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        if (i < m) B[i + j * ldb] = A[i + j * lda];
+}
+
+template <class T>
+hipError_t copy_t(hipStream_t s, int64_t m, int64_t n, const T* A, int64_t lda, T* B, int64_t ldb) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    dim3 g((unsigned)FL_DIV_UP(m, 256), (unsigned)std::min<int64_t>(n, 65535));
+    copy_t_kernel<T><<<g, 256, 0, s>>>(m, n, A, lda, B, ldb);
+    return hipGetLastError();
+}
+
+}  // namespace
+int64_t fl_sy2sb_panels(int64_t n, int b);
+namespace {
+
+template <class T>
+hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, int64_t ldv, T* T1, T* tau1, T* work,
+                   T* part, unsigned* cnt, int* abort) {
+    const int64_t np = fl_sy2sb_panels(n, b);
+    hipError_t e;
+    if (np > 0) {
+        e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * np, s);
+        if (e != hipSuccess) return e;
+    }
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t c0 = p * b, r0 = c0 + b, m = n - r0;
+        const int kb = b;
+        const int kref = (int)std::min<int64_t>(b, m - 1);
+        if (kref <= 0) break;
+        T* Pn = A + r0 + c0 * lda;
+        T* Vp = V1 + r0 + c0 * ldv;
+        T* tp = tau1 + c0;
+        const unsigned G = (unsigned)FL_DIV_UP(m, PROWS);
+        {
+            int64_t mm = m;
+            int kbb = kb, krf = kref;
+            int64_t ldaa = lda, ldvv = ldv;
+            T* prow = part + 2 * FL_DIV_UP(n, PROWS) * 64;
+            unsigned* counter = cnt + p;
+            void* args[] = {&mm, &kbb, &krf, &Pn, &ldaa, &Vp, &ldvv, &tp, &part, &prow, &counter, &abort};
+            e = hipLaunchCooperativeKernel((const void*)panel_qr_kernel<T>, dim3(G), dim3(PNT), args, 0, s);
+            if (e != hipSuccess) return e;
+        }
+        // T from G = V^T V
+        T* Gm = work;                 // b x b
+        T* Tp = T1 + p * (int64_t)b * b;
+        e = fl_gemm_t(s, 1, 0, kref, kref, m, 1.0, Vp, ldv, Vp, ldv, 0.0, Gm, b);
+        if (e != hipSuccess) return e;
+        larft_gram_kernel<T><<<1, 64, 0, s>>>(kref, Gm, b, tp, Tp, b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // two-sided update of A22 = A[r0:n, r0:n]
+        T* A22 = A + r0 + r0 * lda;
+        T* Y = work + (int64_t)b * b;     // m x kref
+        T* X = Y + m * (int64_t)b;        // m x kref
+        T* VW = X + m * (int64_t)b;       // m x 2 kref : [V W]
+        T* WV = VW + 2 * m * (int64_t)b;  // m x 2 kref : [W V]
+        T* S = WV + 2 * m * (int64_t)b;   // kref x kref
+        T* R = S + (int64_t)b * b;        // kref x kref
+        if ((e = fl_gemm_t(s, 0, 0, m, kref, m, 1.0, A22, lda, Vp, ldv, 0.0, Y, m))) return e;   // Y = A22 V
+        if ((e = fl_gemm_t(s, 0, 0, m, kref, kref, 1.0, Y, m, Tp, b, 0.0, X, m))) return e;      // X = Y T
+        if ((e = fl_gemm_t(s, 1, 0, kref, kref, m, 1.0, Vp, ldv, X, m, 0.0, S, b))) return e;     // S = V^T X
+        if ((e = fl_gemm_t(s, 1, 0, kref, kref, kref, 1.0, Tp, b, S, b, 0.0, R, b))) return e;   // R = T^T S
+        // W = X - 1/2 V R, written straight into both concatenations
+        if ((e = copy_t<T>(s, m, kref, X, m, VW + kref * m, m))) return e;
+        if ((e = fl_gemm_t(s, 0, 0, m, kref, kref, -0.5, Vp, ldv, R, b, 1.0, VW + kref * m, m))) return e;
+        if ((e = copy_t<T>(s, m, kref, Vp, ldv, VW, m))) return e;
+        if ((e = copy_t<T>(s, m, kref, VW + kref * m, m, WV, m))) return e;
+        if ((e = copy_t<T>(s, m, kref, Vp, ldv, WV + kref * m, m))) return e;
+        // A22 -= [V W] [W V]^T
+        if ((e = fl_gemm_t(s, 0, 1, m, m, 2 * kref, -1.0, VW, m, WV, m, 1.0, A22, lda))) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -197,60 +279,11 @@ int64_t fl_sy2sb_panels(int64_t n, int b) {
 // abort: device flag raised if a cooperative wait was abandoned.
 hipError_t fl_sy2sb(hipStream_t s, int64_t n, int b, double* A, int64_t lda, double* V1, int64_t ldv, double* T1,
                     double* tau1, double* work, double* part, unsigned* cnt, int* abort) {
-    const int64_t np = fl_sy2sb_panels(n, b);
-    hipError_t e;
-    if (np > 0) {
-        e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * np, s);
-        if (e != hipSuccess) return e;
-    }
-    for (int64_t p = 0; p < np; ++p) {
-        const int64_t c0 = p * b, r0 = c0 + b, m = n - r0;
-        const int kb = b;
-        const int kref = (int)std::min<int64_t>(b, m - 1);
-        if (kref <= 0) break;
-        double* Pn = A + r0 + c0 * lda;
-        double* Vp = V1 + r0 + c0 * ldv;
-        double* tp = tau1 + c0;
-        const unsigned G = (unsigned)FL_DIV_UP(m, PROWS);
-        {
-            int64_t mm = m;
-            int kbb = kb, krf = kref;
-            int64_t ldaa = lda, ldvv = ldv;
-            double* prow = part + 2 * FL_DIV_UP(n, PROWS) * 64;
-            unsigned* counter = cnt + p;
-            void* args[] = {&mm, &kbb, &krf, &Pn, &ldaa, &Vp, &ldvv, &tp, &part, &prow, &counter, &abort};
-            e = hipLaunchCooperativeKernel((const void*)panel_qr_kernel, dim3(G), dim3(PNT), args, 0, s);
-            if (e != hipSuccess) return e;
-        }
-        // T from G = V^T V
-        double* Gm = work;                 // b x b
-        double* Tp = T1 + p * (int64_t)b * b;
-        e = fl_dgemm(s, 1, 0, kref, kref, m, 1.0, Vp, ldv, Vp, ldv, 0.0, Gm, b);
-        if (e != hipSuccess) return e;
-        larft_gram_kernel<<<1, 64, 0, s>>>(kref, Gm, b, tp, Tp, b);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        // two-sided update of A22 = A[r0:n, r0:n]
-        double* A22 = A + r0 + r0 * lda;
-        double* Y = work + (int64_t)b * b;     // m x kref
-        double* X = Y + m * (int64_t)b;        // m x kref
-        double* VW = X + m * (int64_t)b;       // m x 2 kref : [V W]
-        double* WV = VW + 2 * m * (int64_t)b;  // m x 2 kref : [W V]
-        double* S = WV + 2 * m * (int64_t)b;   // kref x kref
-        double* R = S + (int64_t)b * b;        // kref x kref
-        if ((e = fl_dgemm(s, 0, 0, m, kref, m, 1.0, A22, lda, Vp, ldv, 0.0, Y, m))) return e;   // Y = A22 V
-        if ((e = fl_dgemm(s, 0, 0, m, kref, kref, 1.0, Y, m, Tp, b, 0.0, X, m))) return e;      // X = Y T
-        if ((e = fl_dgemm(s, 1, 0, kref, kref, m, 1.0, Vp, ldv, X, m, 0.0, S, b))) return e;     // S = V^T X
-        if ((e = fl_dgemm(s, 1, 0, kref, kref, kref, 1.0, Tp, b, S, b, 0.0, R, b))) return e;   // R = T^T S
-        // W = X - 1/2 V R, written straight into both concatenations
-        if ((e = fl_copy_matrix(s, m, kref, X, m, VW + kref * m, m))) return e;
-        if ((e = fl_dgemm(s, 0, 0, m, kref, kref, -0.5, Vp, ldv, R, b, 1.0, VW + kref * m, m))) return e;
-        if ((e = fl_copy_matrix(s, m, kref, Vp, ldv, VW, m))) return e;
-        if ((e = fl_copy_matrix(s, m, kref, VW + kref * m, m, WV, m))) return e;
-        if ((e = fl_copy_matrix(s, m, kref, Vp, ldv, WV + kref * m, m))) return e;
-        // A22 -= [V W] [W V]^T
-        if ((e = fl_dgemm(s, 0, 1, m, m, 2 * kref, -1.0, VW, m, WV, m, 1.0, A22, lda))) return e;
-    }
-    return hipSuccess;
+    return sy2sb_t<double>(s, n, b, A, lda, V1, ldv, T1, tau1, work, part, cnt, abort);
+}
+hipError_t fl_ssy2sb(hipStream_t s, int64_t n, int b, float* A, int64_t lda, float* V1, int64_t ldv, float* T1,
+                     float* tau1, float* work, float* part, unsigned* cnt, int* abort) {
+    return sy2sb_t<float>(s, n, b, A, lda, V1, ldv, T1, tau1, work, part, cnt, abort);
 }
 
 int64_t fl_sy2sb_work_elems(int64_t n, int b) { return 6 * n * (int64_t)b + 4 * (int64_t)b * b; }
@@ -258,6 +291,11 @@ int64_t fl_sy2sb_part_elems(int64_t n) { return 2 * FL_DIV_UP(n, PROWS) * 64 + 1
 
 hipError_t fl_extract_band(hipStream_t s, int64_t n, int b, const double* A, int64_t lda, double* AB, int64_t ldab) {
     if (n <= 0) return hipSuccess;
-    extract_band_kernel<<<(unsigned)n, 128, 0, s>>>(n, b, A, lda, AB, ldab);
+    extract_band_kernel<double><<<(unsigned)n, 128, 0, s>>>(n, b, A, lda, AB, ldab);
+    return hipGetLastError();
+}
+hipError_t fl_extract_band_f(hipStream_t s, int64_t n, int b, const float* A, int64_t lda, double* AB, int64_t ldab) {
+    if (n <= 0) return hipSuccess;
+    extract_band_kernel<float><<<(unsigned)n, 128, 0, s>>>(n, b, A, lda, AB, ldab);
     return hipGetLastError();
 }
