@@ -2,17 +2,20 @@
 
 One step = the whole hot path on one batch of synthetic input that is already
 resident in HBM:
-  * the FP64 generalized eigensolve K phi = theta M phi (Cholesky, standard
+  * the generalized eigensolve K phi = theta M phi of bilinear elements on the
+    128 x 128 interior-node unit-square grid (n = 16384): Cholesky, standard
     form, band reduction, bulge chasing, divide and conquer, both
-    back-transforms, V = L^-T Z) of bilinear elements on the 128 x 128
-    interior-node unit-square grid (n = 16384);
+    back-transforms, V = L^-T Z, and in mixed mode (the default) FP32
+    back-transforms followed by one FP64 refinement step;
   * the fractional solutions v(alpha_i, f_j) for 1024 seeded random cubic
     polynomial forcings x 32 orders alpha ~ U(0, 2) (32768 solutions).
 value = solutions per second of the whole step (eigensolve included).
 
-Extra fields: eigensolve seconds and TFLOP/s (nominal 9 n^3), the apply alone
-(solves/s, TFLOP/s), per-stage times, a live roofline of the dominant
-kernel, and the CPU oracle timed on a bounded sample.
+Extra fields: eigensolve seconds and nominal TFLOP/s (9 n^3) of the timed
+precision and of the other one (timed once, outside the timed region), the
+mixed-over-FP64 speedup, per-stage times, live rooflines of the timed
+kernels (HIP events on their launch stream) with the dominant one as
+`roofline`, and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -27,7 +30,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "eigensolve s & TFLOP/s at n=16384, mixed vs FP64; fractional solves/sec"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+KERNELS = ("q2_apply", "sb2st", "scaled_gemm")
 
 
 def parse():
@@ -38,6 +43,8 @@ def parse():
     p.add_argument("--m", type=int, default=128, help="interior grid side (n = m^2)")
     p.add_argument("--nf", type=int, default=1024)
     p.add_argument("--na", type=int, default=32)
+    p.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    p.add_argument("--no-compare", action="store_true", help="skip the other precision's eigensolve")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     return p.parse_args()
@@ -92,10 +99,57 @@ def cpu_baseline(m: int, nf: int, na: int, budget: float):
                        f"({dt_apply:.2f} s each) scaled to {nf * na} solutions")}
 
 
+def q2_flops(n: int, b: int) -> float:
+    """Algorithmic flops of applying the bulge-chasing reflectors to n
+    columns: a reflector of length L costs 4 L n (w = v^T Z, Z -= tau v w^T).
+    Sweep i has tasks j = 0 .. 1 + (n-3-i)//b - 1 with L = min(b, n-1-i-j b)."""
+    import numpy as np
+    tot = 0
+    for i in range(max(n - 2, 0)):
+        nt = 1 + (n - 3 - i) // b
+        j = np.arange(nt)
+        tot += int(np.minimum(b, n - 1 - i - j * b).sum())
+    return 4.0 * n * tot
+
+
+def sb2st_flops(n: int, b: int) -> float:
+    """Algorithmic flops of the bulge chase: per task with reflector length L
+    (next block L'): the left update of the annihilated block 4 L b, the
+    two-sided update of the diagonal block 4 L^2, the right update of the
+    block below 4 L L'."""
+    import numpy as np
+    tot = 0.0
+    for i in range(max(n - 2, 0)):
+        nt = 1 + (n - 3 - i) // b
+        j = np.arange(nt)
+        L = np.minimum(b, n - 1 - i - j * b).astype(float)
+        Ln = np.concatenate([L[1:], [0.0]])
+        tot += float((4 * L * b + 4 * L * L + 4 * L * Ln).sum())
+    return tot
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current source of the kernel (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 4 and f[0] == kernel:
+            src = os.path.join(ROOT, "paper_1911_11906_amd", "csrc", f[1])
+            if not os.path.exists(src):
+                return None
+            h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            return float(f[3]) if h == f[2] else None
+    return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "single-GPU build: only --gpus 1 is supported"}))
+        print(json.dumps({"error": "single-GPU build: this benchmark runs on one GPU only (--gpus 1)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -112,37 +166,62 @@ def main():
     alpha = inputs.alphas_uniform(args.na, tag=4)
     U = empty_colmajor(n, args.nf * args.na, dev)
     torch.cuda.synchronize()
+    prec = args.precision
+    other = "mixed" if prec == "fp64" else "fp64"
 
     def step():
-        info = op.eigensolve("fp64")
-        s = torch.cuda.current_stream()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(s)
+        info = op.eigensolve(prec)
         op.apply(F, alpha, out=U)
-        e1.record(s)
-        return info, e0, e1
+        return info
 
     for _ in range(args.warmup):
         step()
+    # the other precision, once, outside the timed region (for the comparison)
     torch.cuda.synchronize()
-    infos, apply_ms = [], []
+    info_other = op.eigensolve(other) if not args.no_compare else None
+    torch.cuda.synchronize()
+    ctx.kernel_timing(True)
+    for k in KERNELS:
+        ctx.kernel_time(k)  # drop anything recorded before
+    torch.cuda.synchronize()
+    infos = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        info, e0, e1 = step()
-        infos.append(info)
-        apply_ms.append((e0, e1))
+        infos.append(step())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    apply_ms = [a.elapsed_time(b) for a, b in apply_ms]
-    eig_ms = [i["total_ms"] for i in infos]
+    ctx.kernel_timing(False)
+    ktime = {k: ctx.kernel_time(k) for k in KERNELS}
+
     step_s = wall / args.steps
     nsol = args.nf * args.na
     flops_eig = 9.0 * n ** 3
-    flops_apply = 2.0 * n * n * args.nf * (1 + args.na)
-    eig_s = float(np.median(eig_ms)) / 1e3
-    app_s = float(np.median(apply_ms)) / 1e3
+    eig_s = float(np.median([i["total_ms"] for i in infos])) / 1e3
     stages = {k: float(np.median([i["stage_ms"][k] for i in infos])) for k in infos[0]["stage_ms"]}
+    b = 64
+    peak_mm = PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS
+    per_step_flops = {
+        "q2_apply": q2_flops(n, b),
+        "sb2st": sb2st_flops(n, b),
+        "scaled_gemm": 2.0 * n * n * nsol,
+    }
+    kernels = {}
+    for k, (cnt, ms) in ktime.items():
+        if cnt == 0:
+            continue
+        fl = per_step_flops[k] * args.steps
+        ach = fl / (ms / 1e3) / 1e12
+        bound, peak = ("alu", PEAK_FP64_TFLOPS) if k == "sb2st" else (
+            "mfma", peak_mm if k == "q2_apply" else PEAK_FP64_TFLOPS)
+        kernels[k] = {"launches": cnt, "total_ms": ms, "avg_ms": ms / cnt, "flops_per_launch": fl / cnt,
+                      "bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    d = kernels[dom]
+    traffic = traffic_for(dom)
+    roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s",
+                "frac": d["frac"], "traffic": traffic, "kernel": dom, "avg_launch_ms": d["avg_ms"],
+                "flops_per_launch": d["flops_per_launch"]}
+    apply_ms = kernels.get("scaled_gemm", {}).get("avg_ms")
     out = {
         "metric": METRIC,
         "value": nsol / step_s,
@@ -154,21 +233,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"Q1 unit square {args.m}x{args.m} (n={n}): FP64 full eigensolve + "
+        "config": {"workload": f"Q1 unit square {args.m}x{args.m} (n={n}): {prec} full generalized eigensolve + "
                                f"{args.nf} cubic forcings x {args.na} alpha", "n": n, "nf": args.nf,
-                   "na": args.na, "precision": "fp64"},
+                   "na": args.na, "precision": prec},
         "eigensolve_s": eig_s,
         "eigensolve_tflops_nominal": flops_eig / eig_s / 1e12,
         "eigensolve_stage_ms": stages,
-        "apply_s": app_s,
-        "apply_solves_per_s": nsol / app_s,
-        "apply_tflops": flops_apply / app_s / 1e12,
-        "roofline": {"bound": "mfma", "achieved": flops_apply / app_s / 1e12, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": flops_apply / app_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "spectral apply (scaled GEMM)"},
+        "refine_iters": infos[0]["refine_iters"],
+        "scaled_gemm_tflops": (2.0 * n * n * nsol) / (apply_ms / 1e3) / 1e12 if apply_ms else None,
+        "roofline": roofline,
+        "kernels": kernels,
     }
+    if info_other is not None:
+        t_other = info_other["total_ms"] / 1e3
+        out[f"eigensolve_{other}_s"] = t_other
+        t64, tmx = (eig_s, t_other) if prec == "fp64" else (t_other, eig_s)
+        out["mixed_speedup_over_fp64"] = t64 / tmx
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.m, args.nf, args.na, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -71,13 +71,17 @@ enum {
 typedef struct fl_eig_opts {
     int32_t band;             /* band width of the two-stage reduction (0 = default 64) */
     int32_t leaf;             /* divide-and-conquer leaf size (0 = default 32) */
-    int32_t refine_max_iters; /* refinement steps (-1 = default: 3 in mixed mode, 0 in FP64) */
-    double refine_tol;        /* mixed mode: stop when max |r_ij| below this (0 = default 1e-13) */
-    int32_t mixed_flags;      /* mixed mode: 0 = FP32 band reduction and back-transforms;
-                                 FL_MIXED_FP64_BAND = FP64 band reduction, FP32 back-transforms */
+    int32_t refine_max_iters; /* refinement steps (-1 = default: 0 in FP64 mode; in mixed mode 1,
+                                 or 3 with FL_MIXED_FP32_BAND) */
+    double refine_tol;        /* stop refining when max |(I - V^T M V)_ij| is below this
+                                 (0 = default 1e-13) */
+    int32_t mixed_flags;      /* mixed mode: 0 = FP64 band reduction, FP32 back-transforms;
+                                 FL_MIXED_FP32_BAND = the band reduction in FP32 as well (its
+                                 rounding is amplified by 1/gap in the eigenvectors, so more
+                                 refinement steps are needed) */
 } fl_eig_opts;
 
-enum { FL_MIXED_FP64_BAND = 1 };
+enum { FL_MIXED_FP32_BAND = 1 };
 
 typedef struct fl_eig_info {
     int32_t status;           /* FL_OK or the failing status */

@@ -14,7 +14,7 @@ SO_PATH = os.path.join(HERE, "libfraclap.so")
 FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENOTSPD, FL_ENOCONV, FL_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FL_ELEM_P1, FL_ELEM_Q1 = 3, 4
 FL_FP64, FL_MIXED = 0, 1
-FL_MIXED_FP64_BAND = 1
+FL_MIXED_FP32_BAND = 1
 STAGES = ["potrf", "sygst", "sy2sb", "sb2st", "stedc", "q2", "q1", "trsm", "refine"]
 FL_NSTAGES = len(STAGES)
 

@@ -80,6 +80,18 @@ class Context:
         except Exception:
             pass
 
+    # ------------------------------------------------------ kernel timers
+    def kernel_timing(self, enable: bool):
+        """Record HIP events around the timed kernels ("q2_apply", "sb2st",
+        "scaled_gemm") on the stream each is launched on."""
+        self.check(self.lib.fl_kernel_timing(1 if enable else 0))
+
+    def kernel_time(self, name: str):
+        """(launches, total ms) accumulated for `name` since the last call."""
+        cnt, tot = ctypes.c_int64(0), ctypes.c_double(0.0)
+        self.check(self.lib.fl_kernel_time(name.encode(), ctypes.byref(cnt), ctypes.byref(tot)))
+        return cnt.value, tot.value
+
     # ---------------------------------------------------------- stage calls
     def dgemm(self, A, B, C=None, ta=False, tb=False, alpha=1.0, beta=0.0):
         A, B = colmajor(A, self.device), colmajor(B, self.device)
@@ -197,11 +209,11 @@ class Operator:
         return K, M
 
     def eigensolve(self, precision: str = "fp64", band: int = 0, leaf: int = 0, refine_max_iters: int = -1,
-                   refine_tol: float = 0.0, fp64_band: bool = False) -> dict:
-        """precision "fp64" or "mixed"; fp64_band keeps the band reduction in
-        FP64 in mixed mode (back-transforms stay FP32)."""
+                   refine_tol: float = 0.0, fp32_band: bool = False) -> dict:
+        """precision "fp64" or "mixed" (FP32 back-transforms + FP64
+        refinement); fp32_band also runs the band reduction in FP32."""
         prec = {"fp64": _lib.FL_FP64, "mixed": _lib.FL_MIXED}[precision]
-        opts = FlEigOpts(band, leaf, refine_max_iters, refine_tol, _lib.FL_MIXED_FP64_BAND if fp64_band else 0)
+        opts = FlEigOpts(band, leaf, refine_max_iters, refine_tol, _lib.FL_MIXED_FP32_BAND if fp32_band else 0)
         info = FlEigInfo()
         self.ctx._sync_stream()
         rc = self.ctx.lib.fl_eigensolve(self.ptr, prec, ctypes.byref(opts), ctypes.byref(info))

@@ -274,7 +274,7 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     int rc = fl_sygst_device(ctx, n, L, ld, blinv.as<double>(), C, ld, bwork.as<double>());
     if (rc) return rc;
     if (precision == FL_MIXED)
-        rc = fl_syevd_mixed_device(ctx, n, C, ld, band, opts ? !(opts->mixed_flags & FL_MIXED_FP64_BAND) : 1,
+        rc = fl_syevd_mixed_device(ctx, n, C, ld, band, opts ? (opts->mixed_flags & FL_MIXED_FP32_BAND) : 0,
                                    op->theta, op->V, ld, info, leaf, &tm);
     else
         rc = fl_syevd_device(ctx, n, C, ld, band, op->theta, op->V, ld, info, leaf, &tm);
@@ -284,8 +284,11 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     }
     FL_HIP(ctx, tm.mark(FL_STAGE_TRSM));
     FL_HIP(ctx, fl_trsm_llt(s, n, n, L, ld, blinv.as<double>(), op->V, ld, bwork.as<double>()));
-    // refinement: default up to 3 steps in mixed mode (early exit at tol), none in FP64 mode
-    int iters = (opts && opts->refine_max_iters >= 0) ? opts->refine_max_iters : (precision == FL_MIXED ? 3 : 0);
+    // refinement: by default one step after FP32 back-transforms, three after
+    // an FP32 band reduction (early exit at tol), none in FP64 mode
+    const bool fp32_band = opts && (opts->mixed_flags & FL_MIXED_FP32_BAND);
+    int iters = (opts && opts->refine_max_iters >= 0) ? opts->refine_max_iters
+                                                      : (precision == FL_MIXED ? (fp32_band ? 3 : 1) : 0);
     double tol = (opts && opts->refine_tol > 0.0) ? opts->refine_tol : 1e-13;
     if (iters > 0) {
         FL_HIP(ctx, hipStreamSynchronize(s));  // the TRSM above still reads L

@@ -6,20 +6,23 @@
 //                                                  sparse Galerkin matrices)
 //   lambda_i = s_ii / (1 - r_ii)
 //   E_ii = r_ii / 2
-//   E_ij = (s_ij + lambda_j r_ij) / (lambda_j - lambda_i)  if |lambda_i - lambda_j| > delta
-//        = r_ij / 2                                        otherwise (cluster)
-//   delta = 1e3 eps max|lambda|: pairs closer than the rounding level of the
-//           lambda are (exactly) degenerate and are only re-orthonormalised.
-//           The published sufficient threshold 2(||S - diag(lambda)||_2 +
-//           max|lambda| ||R||_2) is far larger for FP32 starting vectors at
-//           large n (it would freeze most of the upper spectrum); the update
-//           converges whenever the mixing angle of a pair is small, which the
-//           FP32 reduction delivers, so the rounding level is used.
+//   E_ij = (s_ij + lambda_j r_ij) / (lambda_j - lambda_i)   first-order rotation
+//   E_ij = r_ij / 2  (no rotation) for pairs with
+//        |lambda_i - lambda_j| <= delta = max(1e3 eps, sqrt(n) eps / tau) max|lambda|
+//        (the rounding of s_ij, about sqrt(n) eps max|lambda|, would otherwise
+//        rotate them by more than tau = 2e-6), and for near pairs
+//        (gap < 1e-5 max|lambda|) whose first-order rotation exceeds tau.
+//        Leaving such a pair mixed moves residuals, eigenvalues and solutions
+//        by at most gap * |mixing|, below the FP64 targets.
 //   X <- X + X E                                 (X kept in FP64; the
 //        correction product runs on the FP32 matrix cores once
-//        max|E| u_32 is below the FP64 target, on the FP64 cores before)
-// Each step roughly squares the error of X.  The refined eigenvalues are the
-// lambda of the last step (Rayleigh-quotient accurate).
+//        max|E| u_32 <= 5e-13, on the FP64 cores before)
+// E_ij + E_ji = r_ij, so orthonormality is restored to second order; the
+// off-diagonal error of X is roughly squared by each step.  The published
+// cluster threshold 2(||S - diag(lambda)||_2 + max|lambda| ||R||_2) is not
+// used: at large n it would treat most of the upper spectrum as one cluster.
+// After the last step each column is scaled to unit M-norm and the
+// eigenvalues are the Rayleigh quotients of the columns.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -28,7 +31,8 @@
 
 namespace {
 
-// lam_i = S_ii / R0_ii (R0 = X^T M X); mx = max |I - R0|, per block then reduced
+// lam_i = S_ii / R0_ii (R0 = X^T M X); max |I - R0| over the lower triangle,
+// per block then reduced on the host
 __global__ __launch_bounds__(256) void diag_kernel(int64_t n, const double* __restrict__ S, const double* __restrict__ R0,
                                                    int64_t ld, double* lam) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -40,8 +44,8 @@ __global__ __launch_bounds__(256) void maxabs_offid_kernel(int64_t n, const doub
     __shared__ double red[256];
     double m = 0.0;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        for (int64_t j = blockIdx.y; j < n; j += gridDim.y) m = fmax(m, fabs((i == j ? 1.0 : 0.0) - R0[i + j * ld]));
+    if (i < n)  // lower triangle (R0 is symmetric and stored there)
+        for (int64_t j = blockIdx.y; j <= i; j += gridDim.y) m = fmax(m, fabs((i == j ? 1.0 : 0.0) - R0[i + j * ld]));
     red[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -51,194 +55,92 @@ __global__ __launch_bounds__(256) void maxabs_offid_kernel(int64_t n, const doub
     if (threadIdx.x == 0) blockmax[blockIdx.x + (int64_t)blockIdx.y * gridDim.x] = red[0];
 }
 
-// y = (A - diag(d)) x  or  y = x - A x (mode 1), after y = A x by GEMM
-__global__ void shift_kernel(int64_t n, int mode, const double* __restrict__ x, const double* __restrict__ d,
-                             double* y) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    y[i] = (mode == 0) ? y[i] - d[i] * x[i] : x[i] - y[i];
+// E of the refinement step, one 32 x 32 tile of (i, j) per workgroup.  S and
+// R = X^T M X hold only their lower triangles (the upper one is not
+// formed), so every pair reads the same s_ij and r_ij from both sides: that
+// keeps E_ij + E_ji = r_ij, the identity that preserves orthonormality (the
+// GEMM would round S_ij and S_ji differently, and that difference divided by
+// a small gap would break it).  A pair (i, j) is only re-orthonormalised
+// (e = r/2, no rotation) when its gap is below delta, or when the gap is
+// below gnear and the first-order rotation |e_ij| or |e_ji| exceeds tau
+// (there the first-order formula is dominated by its second-order error).
+// Pairs declined by the tau test are counted in nclus.
+constexpr int ET = 32;
+__global__ __launch_bounds__(256) void ebuild_kernel(int64_t n, const double* __restrict__ S,
+                                                     const double* __restrict__ R0, int64_t ld,
+                                                     const double* __restrict__ lam, double delta, double gnear,
+                                                     double tau, double* E, int64_t lde, unsigned long long* nclus) {
+    __shared__ double st[ET][ET + 1], rt[ET][ET + 1];  // transposed tiles S(J, I), R0(J, I)
+    const int64_t i0 = (int64_t)blockIdx.x * ET, j0 = (int64_t)blockIdx.y * ET;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    // st[a][b] = S(j0 + a, i0 + b): coalesced along a
+    for (int bb = ty; bb < ET; bb += 8) {
+        const int64_t r = j0 + tx, c = i0 + bb;
+        const bool ok = r < n && c < n;
+        st[tx][bb] = ok ? S[r + c * ld] : 0.0;
+        rt[tx][bb] = ok ? R0[r + c * ld] : 0.0;
+    }
+    __syncthreads();
+    unsigned cnt = 0;
+    const int64_t i = i0 + tx;
+    if (i < n) {
+        const double li = lam[i];
+        for (int bb = ty; bb < ET; bb += 8) {
+            const int64_t j = j0 + bb;
+            if (j >= n) break;
+            // lower triangle only: S_ij = S(max(i,j), min(i,j)), exactly symmetric
+            const double sij = (i >= j) ? S[i + j * ld] : st[bb][tx];
+            const double r = (i == j ? 1.0 : 0.0) - ((i >= j) ? R0[i + j * ld] : rt[bb][tx]);
+            double e;
+            if (i == j) {
+                e = 0.5 * r;
+            } else {
+                const double lj = lam[j];
+                const double g = lj - li;
+                if (!(fabs(g) > delta)) {
+                    e = 0.5 * r;
+                } else {
+                    const double eij = (sij + lj * r) / g;
+                    const double eji = (sij + li * r) / (-g);
+                    const bool clus = fabs(g) < gnear && (fabs(eij) > tau || fabs(eji) > tau);
+                    e = clus ? 0.5 * r : eij;
+                    if (clus && i < j) ++cnt;
+                }
+            }
+            E[i + j * lde] = e;
+        }
+    }
+    if (cnt) atomicAdd(nclus, (unsigned long long)cnt);
 }
 
-__global__ __launch_bounds__(256) void norm2_kernel(int64_t n, const double* __restrict__ x, double* out) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i] * x[i];
-    red[threadIdx.x] = s;
+// theta_j = (x_j^T K x_j) / (x_j^T M x_j) from K X and M X, and x_j scaled to
+// unit M-norm (one workgroup per column).  The scaling removes the diagonal
+// of the second-order orthonormality error left by a step, sum_k e_kj^2,
+// which grows with n (the off-diagonal terms are sums of mixed signs).
+__global__ __launch_bounds__(256) void rq_kernel(int64_t n, double* __restrict__ X, int64_t ldx,
+                                                 const double* __restrict__ KX, const double* __restrict__ MX,
+                                                 int64_t ld, double* theta) {
+    __shared__ double rk[256], rm[256];
+    const int64_t j = blockIdx.x;
+    double sk = 0.0, sm = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double x = X[i + j * ldx];
+        sk += x * KX[i + j * ld];
+        sm += x * MX[i + j * ld];
+    }
+    rk[threadIdx.x] = sk;
+    rm[threadIdx.x] = sm;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = sqrt(red[0]);
-}
-
-__global__ void scale_kernel(int64_t n, const double* __restrict__ nrm, const double* __restrict__ y, double* x) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = (nrm[0] > 0.0) ? y[i] / nrm[0] : 0.0;
-}
-
-// E of the refinement step.  A pair (i, j) is clustered when the lambdas
-// agree to the rounding level delta, or when the first-order rotation
-// |e_ij| or |e_ji| exceeds tau (the pair is not yet separated well enough for
-// a first-order correction); clustered pairs are only re-orthonormalised
-// here (e = r/2) and appended to `pairs` (i < j) for the Rayleigh-Ritz step.
-__global__ void ebuild_kernel(int64_t n, const double* __restrict__ S, const double* __restrict__ R0, int64_t ld,
-                              const double* __restrict__ lam, double delta, double tau, double* E, int64_t lde,
-                              int64_t* pairs, unsigned long long* npairs, int64_t cap) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double li = lam[i];
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
-        double r = (i == j ? 1.0 : 0.0) - R0[i + j * ld];
-        double e;
-        if (i == j) {
-            e = 0.5 * r;
-        } else {
-            const double lj = lam[j];
-            const double g = lj - li;
-            const double sij = S[i + j * ld];
-            const double eij = (sij + lj * r) / g;
-            const double eji = (sij + li * r) / (-g);
-            const bool clus = !(fabs(g) > delta) || fabs(eij) > tau || fabs(eji) > tau;
-            e = clus ? 0.5 * r : eij;
-            if (clus && i < j) {
-                unsigned long long k = atomicAdd(npairs, 1ull);
-                if ((int64_t)k < cap) {
-                    pairs[2 * k] = i;
-                    pairs[2 * k + 1] = j;
-                }
-            }
-        }
-        E[i + j * lde] = e;
-    }
-}
-
-// Rayleigh-Ritz on one cluster (one workgroup of 64 threads): with
-// P = X_c^T K X_c and Q = X_c^T M X_c (c x c), Q = L L^T, solve
-// L^-1 P L^-T = W diag(mu) W^T by cyclic Jacobi, Y = L^-T W (ascending mu).
-constexpr int RRMAX = 80;
-__global__ __launch_bounds__(64) void rr_small_kernel(const int64_t* __restrict__ coff, const double* __restrict__ PQ,
-                                                      double* Y, double* mu) {
-    __shared__ double A[RRMAX * RRMAX], L[RRMAX * RRMAX], W[RRMAX * RRMAX];
-    __shared__ double cs[2];
-    __shared__ int more;
-    const int t = threadIdx.x;
-    const int64_t o = coff[blockIdx.x];
-    const int c = (int)(coff[blockIdx.x + 1] - o);
-    const double* P = PQ + 2 * o * RRMAX;            // c x c, ld c  (packed by cluster)
-    const double* Q = P + (int64_t)c * c;
-    for (int e = t; e < c * c; e += 64) {
-        A[e] = P[e];
-        L[e] = Q[e];
-    }
-    __syncthreads();
-    // Cholesky of Q (lower, in L), column by column
-    for (int j = 0; j < c; ++j) {
-        if (t == 0) {
-            double d = L[j + j * c];
-            for (int k = 0; k < j; ++k) d -= L[j + k * c] * L[j + k * c];
-            L[j + j * c] = sqrt(d > 0.0 ? d : 1e-300);
-        }
-        __syncthreads();
-        for (int i = j + 1 + t; i < c; i += 64) {
-            double v = L[i + j * c];
-            for (int k = 0; k < j; ++k) v -= L[i + k * c] * L[j + k * c];
-            L[i + j * c] = v / L[j + j * c];
+        if ((int)threadIdx.x < w) {
+            rk[threadIdx.x] += rk[threadIdx.x + w];
+            rm[threadIdx.x] += rm[threadIdx.x + w];
         }
         __syncthreads();
     }
-    // A := L^-1 A L^-T : columns of A by forward substitution, then rows
-    for (int col = t; col < c; col += 64)
-        for (int i = 0; i < c; ++i) {
-            double v = A[i + col * c];
-            for (int k = 0; k < i; ++k) v -= L[i + k * c] * A[k + col * c];
-            A[i + col * c] = v / L[i + i * c];
-        }
-    __syncthreads();
-    for (int row = t; row < c; row += 64)
-        for (int i = 0; i < c; ++i) {
-            double v = A[row + i * c];
-            for (int k = 0; k < i; ++k) v -= L[i + k * c] * A[row + k * c];
-            A[row + i * c] = v / L[i + i * c];
-        }
-    __syncthreads();
-    for (int e = t; e < c * c; e += 64) W[e] = ((e % c) == (e / c)) ? 1.0 : 0.0;
-    __syncthreads();
-    // cyclic Jacobi (row-by-row ordering), rotations applied by all threads
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (t == 0) more = 0;
-        __syncthreads();
-        for (int p = 0; p < c - 1; ++p)
-            for (int q = p + 1; q < c; ++q) {
-                if (t == 0) {
-                    double apq = A[p + q * c], app = A[p + p * c], aqq = A[q + q * c];
-                    double cc = 1.0, ss = 0.0;
-                    if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq)) && apq != 0.0) {
-                        double th = (aqq - app) / (2.0 * apq);
-                        double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-                        cc = 1.0 / sqrt(1.0 + tt * tt);
-                        ss = tt * cc;
-                        more = 1;
-                    }
-                    cs[0] = cc;
-                    cs[1] = ss;
-                }
-                __syncthreads();
-                const double cc = cs[0], ss = cs[1];
-                if (ss != 0.0) {
-                    for (int k = t; k < c; k += 64) {  // columns p, q
-                        double x = A[k + p * c], y = A[k + q * c];
-                        A[k + p * c] = cc * x - ss * y;
-                        A[k + q * c] = ss * x + cc * y;
-                        double u = W[k + p * c], w = W[k + q * c];
-                        W[k + p * c] = cc * u - ss * w;
-                        W[k + q * c] = ss * u + cc * w;
-                    }
-                    __syncthreads();
-                    for (int k = t; k < c; k += 64) {  // rows p, q
-                        double x = A[p + k * c], y = A[q + k * c];
-                        A[p + k * c] = cc * x - ss * y;
-                        A[q + k * c] = ss * x + cc * y;
-                    }
-                }
-                __syncthreads();
-            }
-        if (!more) break;
-    }
-    // Y = L^-T W, columns sorted by ascending mu (selection by rank)
-    for (int col = t; col < c; col += 64)
-        for (int i = c - 1; i >= 0; --i) {
-            double v = W[i + col * c];
-            for (int k = i + 1; k < c; ++k) v -= L[k + i * c] * W[k + col * c];
-            W[i + col * c] = v / L[i + i * c];
-        }
-    __syncthreads();
-    for (int col = t; col < c; col += 64) {
-        double m = A[col + col * c];
-        int rnk = 0;
-        for (int k = 0; k < c; ++k) {
-            double mk = A[k + k * c];
-            rnk += (mk < m || (mk == m && k < col)) ? 1 : 0;
-        }
-        mu[o + rnk] = m;
-        for (int i = 0; i < c; ++i) Y[o * RRMAX + i + (int64_t)rnk * c] = W[i + col * c];
-    }
-}
-
-__global__ void gather_cols_kernel(int64_t n, int64_t m, const int64_t* __restrict__ idx, const double* __restrict__ X,
-                                   int64_t ldx, double* Xc) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t c = blockIdx.y; c < m; c += gridDim.y)
-        if (r < n) Xc[r + c * n] = X[r + idx[c] * ldx];
-}
-
-__global__ void scatter_cols_kernel(int64_t n, int64_t m, const int64_t* __restrict__ idx, const double* __restrict__ Xc,
-                                    double* X, int64_t ldx, const double* __restrict__ mu, double* theta) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t c = blockIdx.y; c < m; c += gridDim.y) {
-        if (r < n) X[r + idx[c] * ldx] = Xc[r + c * n];
-        if (r == 0) theta[idx[c]] = mu[c];
-    }
+    if (threadIdx.x == 0) theta[j] = rk[0] / rm[0];
+    const double sc = 1.0 / sqrt(rm[0]);
+    for (int64_t i = threadIdx.x; i < n; i += 256) X[i + j * ldx] *= sc;
 }
 
 __global__ __launch_bounds__(256) void maxabs_kernel(int64_t m, int64_t n, const double* __restrict__ A, int64_t ld,
@@ -299,33 +201,6 @@ inline dim3 g2(int64_t m, int64_t n) {
 
 }  // namespace
 
-// 2-norm estimate of (A - diag(d)) (mode 0) or (I - A) (mode 1), A symmetric
-// n x n (ld), by `iters` power iterations from a fixed start vector.
-[[maybe_unused]] static int norm2_est(fl_ctx* ctx, int64_t n, const double* A, int64_t ld, const double* d, int mode, int iters,
-                     double* xv, double* yv, double* nrm, double* out) {
-    hipStream_t s = ctx->stream;
-    std::vector<double> x0(n);
-    for (int64_t i = 0; i < n; ++i) x0[i] = 1.0 + 0.37 * std::sin(0.731 * (double)i + 0.2);
-    double s2 = 0.0;
-    for (double v : x0) s2 += v * v;
-    for (double& v : x0) v /= std::sqrt(s2);
-    FL_HIP(ctx, hipMemcpyAsync(xv, x0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-    double est = 0.0;
-    for (int it = 0; it < iters; ++it) {
-        FL_HIP(ctx, fl_dgemm(s, 0, 0, n, 1, n, 1.0, A, ld, xv, n, 0.0, yv, n));
-        shift_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, mode, xv, d, yv);
-        FL_HIP(ctx, hipGetLastError());
-        norm2_kernel<<<1, 256, 0, s>>>(n, yv, nrm);
-        FL_HIP(ctx, hipGetLastError());
-        scale_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, nrm, yv, xv);
-        FL_HIP(ctx, hipGetLastError());
-    }
-    FL_HIP(ctx, hipMemcpyAsync(&est, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-    FL_HIP(ctx, hipStreamSynchronize(s));
-    *out = est;
-    return FL_OK;
-}
-
 // Refine (theta, X) in place.  X: n x n, ld ldx, approximately M-orthonormal
 // eigenvectors of (K, M) given by op's CSR matrices.  max_iters steps at
 // most; stops early when max |I - X^T M X| <= tol.  theta (n) receives the
@@ -344,63 +219,80 @@ int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t l
     FL_HIP(ctx, bXf.alloc(sizeof(float) * n * n));
     FL_HIP(ctx, bXEf.alloc(sizeof(float) * n * n));
     const int64_t nbm = FL_DIV_UP(n, 256) * std::min<int64_t>(n, 1024);
-    FL_HIP(ctx, bv.alloc(sizeof(double) * (4 * n + 8 + nbm) + sizeof(int64_t) * n + 64));
+    FL_HIP(ctx, bv.alloc(sizeof(double) * (2 * n + nbm) + sizeof(int64_t) * n + 64));
     double* KX = bKX.as<double>();
     double* MX = bMX.as<double>();
     double* S = bS.as<double>();
     double* R0 = bR.as<double>();
     double* E = bE.as<double>();
     float* Xf = bXf.as<float>();
-    float* Ef = bXf.as<float>();  // reassigned below (Xf and Ef need separate space)
     float* XEf = bXEf.as<float>();
     double* lam = bv.as<double>();
-    double* xv = lam + n;
-    double* yv = xv + n;
-    double* lam2 = yv + n;
-    double* nrm = lam2 + n;
-    double* bmax = nrm + 8;
+    double* lam2 = lam + n;
+    double* bmax = lam2 + n;
     int64_t* rank = (int64_t*)(bmax + nbm);
-    unsigned long long* npairs = (unsigned long long*)(rank + n);
+    unsigned long long* nclus = (unsigned long long*)(rank + n);
+    const bool verbose = getenv("FRACLAP_VERBOSE") != nullptr;
+    const dim3 gm((unsigned)FL_DIV_UP(n, 256), (unsigned)std::min<int64_t>(n, 1024));
+    std::vector<double> hb((size_t)gm.x * gm.y);
+    auto reduce_max = [&](double* out) -> int {
+        FL_HIP(ctx, hipMemcpyAsync(hb.data(), bmax, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        double m = 0.0;
+        for (double v : hb) m = std::max(m, v);
+        *out = m;
+        return FL_OK;
+    };
     int iters = 0;
     double resid = -1.0;
+    bool updated = false;  // X changed since theta was last computed
     for (int it = 0; it < max_iters; ++it) {
         FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->kval, n, X, ldx, KX, ld));
         FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, n, X, ldx, MX, ld));
-        FL_HIP(ctx, fl_dgemm(s, 1, 0, n, n, n, 1.0, X, ldx, KX, ld, 0.0, S, ld));
-        FL_HIP(ctx, fl_dgemm(s, 1, 0, n, n, n, 1.0, X, ldx, MX, ld, 0.0, R0, ld));
+        // S and X^T M X are symmetric: only their lower triangles are formed
+        FL_HIP(ctx, fl_dgemm(s, 1, 0, n, n, n, 1.0, X, ldx, KX, ld, 0.0, S, ld, 1));
+        FL_HIP(ctx, fl_dgemm(s, 1, 0, n, n, n, 1.0, X, ldx, MX, ld, 0.0, R0, ld, 1));
         diag_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, S, R0, ld, lam);
         FL_HIP(ctx, hipGetLastError());
-        // max |I - X^T M X|
-        dim3 gm((unsigned)FL_DIV_UP(n, 256), (unsigned)std::min<int64_t>(n, 1024));
+        FL_HIP(ctx, hipMemcpyAsync(theta, lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        updated = false;
         maxabs_offid_kernel<<<gm, 256, 0, s>>>(n, R0, ld, bmax);
         FL_HIP(ctx, hipGetLastError());
-        std::vector<double> hb((size_t)gm.x * gm.y);
-        FL_HIP(ctx, hipMemcpyAsync(hb.data(), bmax, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
-        std::vector<double> hl(n);
-        FL_HIP(ctx, hipMemcpyAsync(hl.data(), lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-        FL_HIP(ctx, hipStreamSynchronize(s));
         double mr = 0.0, lmax = 0.0;
-        for (double v : hb) mr = std::max(mr, v);
-        for (double v : hl) lmax = std::max(lmax, std::fabs(v));
+        if (int rc = reduce_max(&mr)) return rc;
+        maxabs_kernel<<<gm, 256, 0, s>>>(n, 1, lam, n, bmax);
+        FL_HIP(ctx, hipGetLastError());
+        if (int rc = reduce_max(&lmax)) return rc;
         resid = mr;
-        FL_HIP(ctx, hipMemcpyAsync(theta, lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         if (mr <= tol) break;
-        const double delta = 1e3 * 2.220446049250313e-16 * lmax;
-        ebuild_kernel<<<g2(n, n), 256, 0, s>>>(n, S, R0, ld, lam, delta, INFINITY, E, n, nullptr, npairs, 0);
+        // delta: below this gap the rounding of S (about sqrt(n) eps max|lambda|)
+        // divided by the gap would rotate by more than tau, so such pairs count
+        // as degenerate; gnear, tau: a near pair whose rotation exceeds tau
+        // is dominated by the second-order term and is left unrotated
+        const double tau = 2e-6;
+        const double delta = std::max(1e3 * 2.220446049250313e-16,
+                                      std::sqrt((double)n) * 2.220446049250313e-16 / tau) * lmax;
+        const double gnear = 1e-5 * lmax;
+        FL_HIP(ctx, hipMemsetAsync(nclus, 0, sizeof(unsigned long long), s));
+        const dim3 ge((unsigned)FL_DIV_UP(n, ET), (unsigned)FL_DIV_UP(n, ET));
+        ebuild_kernel<<<ge, 256, 0, s>>>(n, S, R0, ld, lam, delta, gnear, tau, E, n, nclus);
         FL_HIP(ctx, hipGetLastError());
         maxabs_kernel<<<gm, 256, 0, s>>>(n, n, E, n, bmax);
         FL_HIP(ctx, hipGetLastError());
-        FL_HIP(ctx, hipMemcpyAsync(hb.data(), bmax, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
-        FL_HIP(ctx, hipStreamSynchronize(s));
         double emax = 0.0;
-        for (double v : hb) emax = std::max(emax, v);
-        if (getenv("FRACLAP_VERBOSE"))
-            fprintf(stderr, "[fraclap] refine step %d: max|I - X^T M X| %.3e  max|E| %.3e  delta %.3e\n", it, mr, emax,
-                    delta);
-        if (emax * 6.0e-8 <= 1e-14) {
-            // X += X E on the FP32 matrix cores (E and the FP32 rounding of X
-            // are both small enough for an FP64-accurate correction)
-            Ef = reinterpret_cast<float*>(MX);  // M X is consumed: reuse its space
+        if (int rc = reduce_max(&emax)) return rc;
+        if (verbose) {
+            unsigned long long nc = 0;
+            FL_HIP(ctx, hipMemcpy(&nc, nclus, sizeof(nc), hipMemcpyDeviceToHost));
+            fprintf(stderr, "[fraclap] refine step %d: max|I - X^T M X| %.3e  max|E| %.3e  tau-clustered pairs %llu\n",
+                    it, mr, emax, nc);
+        }
+        if (emax * 6.0e-8 <= 5e-13) {
+            // X += X E on the FP32 matrix cores: the product's rounding,
+            // about u_32 max|E| relative to X, stays below the FP64 targets
+            // for orthonormality and residual (and enters the eigenvalues
+            // only squared)
+            float* Ef = reinterpret_cast<float*>(MX);  // M X is consumed: reuse its space
             FL_HIP(ctx, fl_d2s(s, n, n, X, ldx, Xf, n));
             FL_HIP(ctx, fl_d2s(s, n, n, E, n, Ef, n));
             FL_HIP(ctx, fl_sgemm(s, 0, 0, n, n, n, 1.0f, Xf, n, Ef, n, 0.0f, XEf, n));
@@ -411,7 +303,16 @@ int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t l
             FL_HIP(ctx, hipMemcpy2DAsync(MX, ld * 8, X, ldx * 8, n * 8, n, hipMemcpyDeviceToDevice, s));
             FL_HIP(ctx, fl_dgemm(s, 0, 0, n, n, n, 1.0, MX, ld, E, n, 1.0, X, ldx));
         }
+        updated = true;
         ++iters;
+    }
+    if (updated) {
+        // eigenvalues of the final X: column Rayleigh quotients, and unit
+        // M-norms (O(n^2) work)
+        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->kval, n, X, ldx, KX, ld));
+        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, n, X, ldx, MX, ld));
+        rq_kernel<<<(unsigned)n, 256, 0, s>>>(n, X, ldx, KX, MX, ld, theta);
+        FL_HIP(ctx, hipGetLastError());
     }
     // ascending order (refinement may swap nearly equal neighbours)
     rank_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, theta, rank);

@@ -190,6 +190,23 @@ def test_eigensolve_mixed_q1_c1(ctx, oracle_mod, band):
     assert info["stage_ms"]["refine"] > 0
 
 
+def test_eigensolve_mixed_fp32_band_q1_c1(ctx, oracle_mod):
+    """FP32 band reduction as well: its rounding is amplified by 1/gap in the
+    eigenvectors, so the default is three refinement steps; at n = 576 they
+    reach the FP64 targets."""
+    note("eigensolve mixed fp32 band c1")
+    from paper_1911_11906_amd.api import Operator
+    mesh = inputs.q1_rectangle(24, 24)
+    op = Operator.assemble(ctx, mesh)
+    info = op.eigensolve("mixed", fp32_band=True)
+    th, V = op.eigenpairs()
+    th, V = to_np(th), to_np(V)
+    K, M = oracle_mod.assemble(mesh)
+    ref = Q1Rectangle(24, 24).eigenvalues()
+    check_pencil(K, M, th, V, ref, 1e-12, 1e-11)
+    assert 1 <= info["refine_iters"] <= 3
+
+
 def test_eigensolve_mixed_p1_vs_oracle(ctx, oracle_mod):
     note("eigensolve mixed p1 poly 900")
     from paper_1911_11906_amd.api import Operator
