@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--no-compare", action="store_true", help="skip the other precision's eigensolve")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="run one plain device copy of this many MiB before the timed region "
+                        "(reference reading for HBM byte counters)")
     return p.parse_args()
 
 
@@ -174,6 +177,12 @@ def main():
         op.apply(F, alpha, out=U)
         return info
 
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads and writes MIB MiB
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     # the other precision, once, outside the timed region (for the comparison)
