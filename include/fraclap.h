@@ -128,11 +128,26 @@ void fl_op_destroy(fl_op *op);
 /* ---- the eigensolve ------------------------------------------------------
  * All n pairs of K phi = theta M phi, theta ascending, V^T M V = I
  * (eq. discrete_laplace, Section "Post-processing").  Stages: FL_STAGE_*.
- * precision = FL_FP64 runs every stage in FP64; FL_MIXED runs the band
- * reduction and both back-transforms in FP32 on the matrix cores and restores
- * FP64 accuracy by eigenpair refinement.  opts/info may be NULL.
+ * precision = FL_FP64 runs every stage in FP64; FL_MIXED runs both
+ * back-transforms (and, with FL_MIXED_FP32_BAND, the band reduction) in FP32
+ * on the matrix cores and restores FP64 accuracy by eigenpair refinement.
+ * opts/info may be NULL.  Synchronous.
  * FL_ENOTSPD if M is not positive definite (info->index = pivot). */
 int fl_eigensolve(fl_op *op, int precision, const fl_eig_opts *opts, fl_eig_info *info);
+/* Many independent problems (one per domain; the basis of each is computed
+ * once and reused for every forcing, Section "Method") in one persistent
+ * launch: each workgroup takes the next problem, largest n first, from an
+ * atomic counter and runs Cholesky, reduction to standard form, Householder
+ * tridiagonalisation, implicit QL and the back-transforms on its own, in FP64.
+ * ops: host array of count distinct operators of this context's device, each
+ * with 1 <= n <= 1024.  precision must be FL_FP64.  On return each op holds
+ * theta ascending and M-orthonormal V, as after fl_eigensolve.  infos (host,
+ * count entries, may be NULL) receive per-problem status and index
+ * (FL_ENOTSPD: 1-based pivot; FL_ENOCONV: eigenvalue) and, in total_ms, the
+ * time of the whole launch.  Returns FL_OK, or the status of the first failed
+ * problem (the others are still solved).  Workspace: about 4 n^2 doubles per
+ * problem, allocated and released by the call.  Synchronous. */
+int fl_eigensolve_batched(fl_ctx *ctx, int64_t count, fl_op *const *ops, int precision, fl_eig_info *infos);
 /* Copy theta (n) and V (n x n, ld ldv; V may be NULL) out. */
 int fl_eigenpairs(const fl_op *op, double *theta, double *V, int64_t ldv, int on_device);
 /* Install eigenpairs computed elsewhere (resume, or testing the apply path

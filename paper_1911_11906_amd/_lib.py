@@ -25,7 +25,7 @@ STATUS_NAMES = {FL_OK: "FL_OK", FL_EINVAL: "FL_EINVAL", FL_ENOMEM: "FL_ENOMEM", 
 EXPORTS = [
     "fl_ctx_create", "fl_ctx_set_stream", "fl_ctx_destroy", "fl_last_error",
     "fl_assemble", "fl_op_from_dense", "fl_op_n", "fl_op_matrices", "fl_op_destroy",
-    "fl_eigensolve", "fl_eigenpairs", "fl_op_set_eigenpairs",
+    "fl_eigensolve", "fl_eigensolve_batched", "fl_eigenpairs", "fl_op_set_eigenpairs",
     "fl_apply_fractional", "fl_grad_apply",
     "fl_dgemm", "fl_dpotrf", "fl_dsygst", "fl_dstedc", "fl_dsytrd_2stage", "fl_dsyevd",
     "fl_kernel_timing", "fl_kernel_time",
@@ -80,6 +80,7 @@ def load(path: str = SO_PATH):
         "fl_op_matrices": ([P, P, P, i64, i32], i32),
         "fl_op_destroy": ([P], None),
         "fl_eigensolve": ([P, i32, ctypes.POINTER(FlEigOpts), ctypes.POINTER(FlEigInfo)], i32),
+        "fl_eigensolve_batched": ([P, i64, P, i32, P], i32),
         "fl_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_op_set_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_apply_fractional": ([P, i64, P, i64, i64, P, i32, P, i64], i32),

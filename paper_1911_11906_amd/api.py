@@ -92,6 +92,23 @@ class Context:
         self.check(self.lib.fl_kernel_time(name.encode(), ctypes.byref(cnt), ctypes.byref(tot)))
         return cnt.value, tot.value
 
+    def eigensolve_batched(self, ops, precision: str = "fp64"):
+        """Solve every Operator in `ops` in one persistent launch (FP64,
+        each n <= 1024); returns the per-problem info dicts."""
+        ops = list(ops)
+        prec = {"fp64": _lib.FL_FP64, "mixed": _lib.FL_MIXED}[precision]
+        arr = (P * len(ops))(*[o.ptr for o in ops])
+        infos = (FlEigInfo * max(len(ops), 1))()
+        self._sync_stream()
+        rc = self.lib.fl_eigensolve_batched(self.ptr, len(ops), ctypes.cast(arr, P), prec,
+                                            ctypes.cast(infos, P))
+        out = [infos[i].as_dict() for i in range(len(ops))]
+        for o, d in zip(ops, out):
+            o.info = d
+        if rc != 0:
+            raise FraclapError(rc, self.lib.fl_last_error(self.ptr).decode())
+        return out
+
     # ---------------------------------------------------------- stage calls
     def dgemm(self, A, B, C=None, ta=False, tb=False, alpha=1.0, beta=0.0):
         A, B = colmajor(A, self.device), colmajor(B, self.device)

@@ -1,0 +1,644 @@
+// Many small generalized eigenproblems K phi = theta M phi (eq.
+// discrete_laplace; the basis of each domain is computed once and reused,
+// Section "Method") in ONE persistent launch.
+//
+// Every workgroup takes the next problem from an atomic counter over the
+// problems sorted by n, largest first, and solves it alone, in FP64:
+//   M = L L^T                      blocked Cholesky (32-column panels)
+//   C = L^-1 (L^-1 K)^T            two blocked triangular solves
+//   C = Q T Q^T                    Householder tridiagonalisation
+//   T = Z_T diag(theta) Z_T^T      implicit QL with Wilkinson shifts; the
+//                                  rotations of each sweep are staged in LDS
+//                                  and applied to Z row-parallel
+//   Z = Q Z_T                      block reflectors (I - V T V^T), 32 at a time
+//   V = L^-T Z                     blocked triangular solve
+// then theta ascending and V = [phi_1 .. phi_n], M-orthonormal.  The dense
+// contractions use a register-tiled FP64 FMA tile (on gfx950 the FP64 vector
+// rate equals the FP64 matrix-core rate).  No workgroup waits on another:
+// the launch ends when the counter passes the last problem.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+#include "internal.h"
+
+namespace {
+
+constexpr int BT = 256;                   // threads per workgroup (4 waves)
+constexpr int NMAX = 1024;                // largest problem
+constexpr int PB = 32;                    // panel / reflector block width
+constexpr int TM = 64, TN = 64, TK = 16;  // GEMM tile (4 x 4 outputs per thread)
+constexpr double EPS = 2.220446049250313e-16;
+
+struct BProb {
+    int64_t n, ld;                                      // ld: of K, M and V
+    const double* K;
+    const double* M;
+    double* V;
+    double* theta;
+    double* logtheta;
+    double *L, *W, *A, *Z;                               // workspaces, ld n
+    double* tau;                                        // n
+};
+
+struct Lds {
+    double As[TK][TM + 1];
+    double Bs[TK][TN + 1];
+    double D[PB][PB + 1];
+    double red[BT / 64];
+    double vv[NMAX];  // Householder vector, QL cosines
+    double pp[NMAX];  // symv result, QL sines
+    double dd[NMAX];  // diagonal of T, then theta
+    double ee[NMAX];  // off-diagonal of T
+    int rk[NMAX];     // ranks of theta
+    int ival[4];
+};
+
+__device__ double wg_sum(double v, Lds& s) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < BT / 64; ++w) r += s.red[w];
+    return r;
+}
+
+// C (m x n) = alpha op(A) op(B) + beta C, column-major, op = transpose when
+// ta / tb.  C must not overlap A or B.
+__device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double beta, double* C, int64_t ldc, Lds& s) {
+    if (m <= 0 || n <= 0) return;
+    const int t = threadIdx.x;
+    const int r0 = (t & 15) * 4, c0 = (t >> 4) * 4;
+    const int tiles_m = (m + TM - 1) / TM, tiles_n = (n + TN - 1) / TN;
+    for (int tile = 0; tile < tiles_m * tiles_n; ++tile) {
+        const int i0 = (tile % tiles_m) * TM, j0 = (tile / tiles_m) * TN;
+        double acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        for (int k0 = 0; k0 < k; k0 += TK) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < (TM * TK) / BT; ++q) {
+                const int e = t + BT * q;
+                int i, kk;
+                if (!ta) {
+                    i = e % TM;
+                    kk = e / TM;
+                } else {
+                    kk = e % TK;
+                    i = e / TK;
+                }
+                const int gi = i0 + i, gk = k0 + kk;
+                double a = 0.0;
+                if (gi < m && gk < k) a = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
+                s.As[kk][i] = a;
+                int j, kb;
+                if (!tb) {
+                    kb = e % TK;
+                    j = e / TK;
+                } else {
+                    j = e % TN;
+                    kb = e / TN;
+                }
+                const int gj = j0 + j, gk2 = k0 + kb;
+                double b = 0.0;
+                if (gj < n && gk2 < k) b = tb ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb];
+                s.Bs[kb][j] = b;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < TK; ++kk) {
+                double a[4], b[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    a[x] = s.As[kk][r0 + x];
+                    b[x] = s.Bs[kk][c0 + x];
+                }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+            }
+        }
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int gj = j0 + c0 + y;
+            if (gj >= n) continue;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const int gi = i0 + r0 + x;
+                if (gi >= m) continue;
+                double* cp = C + gi + (int64_t)gj * ldc;
+                *cp = (beta == 0.0) ? alpha * acc[x][y] : alpha * acc[x][y] + beta * *cp;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Cholesky of the leading n x n of A (lower triangle used and overwritten).
+// Returns 0, or the 1-based index of the first non-positive pivot.
+__device__ int wg_potrf(int n, double* A, int64_t lda, Lds& s) {
+    const int t = threadIdx.x;
+    for (int j0 = 0; j0 < n; j0 += PB) {
+        const int jb = min(PB, n - j0);
+        if (j0 > 0)
+            wg_gemm(false, true, n - j0, jb, j0, -1.0, A + j0, lda, A + j0, lda, 1.0, A + j0 + (int64_t)j0 * lda,
+                    lda, s);
+        for (int e = t; e < jb * jb; e += BT) {
+            const int r = e % jb, c = e / jb;
+            s.D[r][c] = A[j0 + r + (int64_t)(j0 + c) * lda];
+        }
+        if (t == 0) s.ival[0] = 0;
+        __syncthreads();
+        for (int c = 0; c < jb; ++c) {
+            if (t == 0) {
+                double dcc = s.D[c][c];
+                if (!(dcc > 0.0)) {
+                    if (!s.ival[0]) s.ival[0] = j0 + c + 1;
+                    dcc = 1.0;
+                }
+                s.D[c][c] = sqrt(dcc);
+            }
+            __syncthreads();
+            if (t > c && t < jb) s.D[t][c] /= s.D[c][c];
+            __syncthreads();
+            for (int e = t; e < jb * jb; e += BT) {
+                const int r = e % jb, q = e / jb;
+                if (q > c && r >= q) s.D[r][q] -= s.D[r][c] * s.D[q][c];
+            }
+            __syncthreads();
+        }
+        const int bad = s.ival[0];
+        if (bad) return bad;
+        for (int e = t; e < jb * jb; e += BT) {
+            const int r = e % jb, c = e / jb;
+            if (r >= c) A[j0 + r + (int64_t)(j0 + c) * lda] = s.D[r][c];
+        }
+        // rows below the block: x L_jj^T = a
+        for (int r = j0 + jb + t; r < n; r += BT) {
+            double x[PB];
+#pragma unroll
+            for (int c = 0; c < PB; ++c) {
+                if (c < jb) {
+                    double v = A[r + (int64_t)(j0 + c) * lda];
+#pragma unroll
+                    for (int q = 0; q < c; ++q) v -= x[q] * s.D[c][q];
+                    x[c] = v / s.D[c][c];
+                    A[r + (int64_t)(j0 + c) * lda] = x[c];
+                } else {
+                    x[c] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    return 0;
+}
+
+// Solve L X = B in place (L lower, n x n; B n x nrhs).
+__device__ void wg_trsm_ln(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
+    const int t = threadIdx.x;
+    for (int i0 = 0; i0 < n; i0 += PB) {
+        const int ib = min(PB, n - i0);
+        for (int e = t; e < PB * PB; e += BT) {
+            const int r = e % PB, c = e / PB;
+            s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
+        }
+        __syncthreads();
+        for (int j = t; j < nrhs; j += BT) {
+            double x[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                if (r < ib) {
+                    double v = B[i0 + r + (int64_t)j * ldb];
+#pragma unroll
+                    for (int q = 0; q < r; ++q) v -= s.D[r][q] * x[q];
+                    x[r] = v / s.D[r][r];
+                    B[i0 + r + (int64_t)j * ldb] = x[r];
+                } else {
+                    x[r] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        if (i0 + ib < n)
+            wg_gemm(false, false, n - i0 - ib, nrhs, ib, -1.0, L + i0 + ib + (int64_t)i0 * ldl, ldl, B + i0, ldb,
+                    1.0, B + i0 + ib, ldb, s);
+    }
+}
+
+// Solve L^T X = B in place.
+__device__ void wg_trsm_lt(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
+    const int t = threadIdx.x;
+    const int nblk = (n + PB - 1) / PB;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int i0 = bi * PB, ib = min(PB, n - i0);
+        for (int e = t; e < PB * PB; e += BT) {
+            const int r = e % PB, c = e / PB;
+            s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
+        }
+        __syncthreads();
+        for (int j = t; j < nrhs; j += BT) {
+            double x[PB];
+#pragma unroll
+            for (int r = PB - 1; r >= 0; --r) {
+                if (r < ib) {
+                    double v = B[i0 + r + (int64_t)j * ldb];
+#pragma unroll
+                    for (int q = r + 1; q < PB; ++q)
+                        if (q < ib) v -= s.D[q][r] * x[q];
+                    x[r] = v / s.D[r][r];
+                    B[i0 + r + (int64_t)j * ldb] = x[r];
+                } else {
+                    x[r] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        if (i0 > 0) wg_gemm(true, false, i0, nrhs, ib, -1.0, L + i0, ldl, B + i0, ldb, 1.0, B, ldb, s);
+    }
+}
+
+// Householder tridiagonalisation of the symmetric A (full storage, lower
+// reflectors): reflector k has v = (1, A[k+2:n, k]) on rows k+1..n-1 and tau[k].
+// d and e (e[i] couples i and i+1) are left in s.dd, s.ee.
+__device__ void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < n - 2; ++k) {
+        const int m = n - k - 1;
+        double* x = A + (k + 1) + (int64_t)k * lda;
+        double loc = 0.0;
+        for (int r = 1 + t; r < m; r += BT) loc += x[r] * x[r];
+        const double xn2 = wg_sum(loc, s);
+        const double alpha = x[0];
+        double tk = 0.0, beta = alpha;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tk = (beta - alpha) / beta;
+            const double sc = 1.0 / (alpha - beta);
+            for (int r = 1 + t; r < m; r += BT) {
+                const double v = x[r] * sc;
+                x[r] = v;
+                s.vv[r] = v;
+            }
+        } else {
+            for (int r = 1 + t; r < m; r += BT) s.vv[r] = 0.0;
+        }
+        if (t == 0) {
+            s.vv[0] = 1.0;
+            s.dd[k] = A[k + (int64_t)k * lda];
+            s.ee[k] = beta;
+            tau[k] = tk;
+            x[0] = beta;
+        }
+        __syncthreads();
+        if (tk != 0.0) {
+            double* A22 = A + (k + 1) + (int64_t)(k + 1) * lda;
+            for (int i = t; i < m; i += BT) {
+                double acc = 0.0;
+                for (int j = 0; j < m; ++j) acc = fma(A22[i + (int64_t)j * lda], s.vv[j], acc);
+                s.pp[i] = tk * acc;
+            }
+            double loc2 = 0.0;
+            for (int i = t; i < m; i += BT) loc2 += s.pp[i] * s.vv[i];
+            const double hc = 0.5 * tk * wg_sum(loc2, s);
+            for (int i = t; i < m; i += BT) s.pp[i] -= hc * s.vv[i];
+            __syncthreads();
+            // A22 -= v w^T + w v^T, rounded identically for (i, j) and (j, i)
+            for (int j = 0; j < m; ++j) {
+                const double vj = s.vv[j], wj = s.pp[j];
+                for (int i = t; i < m; i += BT) {
+                    const double p1 = __dmul_rn(s.vv[i], wj), p2 = __dmul_rn(s.pp[i], vj);
+                    double* a = A22 + i + (int64_t)j * lda;
+                    *a = __dsub_rn(*a, __dadd_rn(p1, p2));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        if (n >= 2) {
+            s.dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * lda];
+            s.ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
+        }
+        s.dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * lda];
+        s.ee[n - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// Implicit QL with Wilkinson shifts on (s.dd, s.ee); Z (n x n, identity on
+// entry) accumulates the rotations.  One thread runs each sweep's scalar
+// recurrence and stages its rotations in LDS; then every thread applies them
+// to its rows of Z.  Returns 0, or l+1 if eigenvalue l took over 60 sweeps.
+__device__ int wg_steql(int n, double* Z, int64_t ldz, Lds& s) {
+    const int t = threadIdx.x;
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        for (;;) {
+            if (t == 0) {
+                int mm = l;
+                for (; mm < n - 1; ++mm) {
+                    const double dd = fabs(s.dd[mm]) + fabs(s.dd[mm + 1]);
+                    if (fabs(s.ee[mm]) <= EPS * dd) break;
+                }
+                s.ival[1] = mm;
+            }
+            __syncthreads();
+            const int m = s.ival[1];
+            __syncthreads();
+            if (m == l) break;
+            if (++iter > 60) return l + 1;
+            if (t == 0) {
+                // shift from the leading 2 x 2 of the unreduced block [l, m]
+                double g = (s.dd[l + 1] - s.dd[l]) / (2.0 * s.ee[l]);
+                double r = hypot(g, 1.0);
+                g = s.dd[m] - s.dd[l] + s.ee[l] / (g + copysign(r, g));
+                double sn = 1.0, c = 1.0, p = 0.0;
+                int i = m - 1;
+                bool early = false;
+                for (; i >= l; --i) {
+                    const double f = sn * s.ee[i], b = c * s.ee[i];
+                    r = hypot(f, g);
+                    s.ee[i + 1] = r;
+                    if (r == 0.0) {  // the block splits: restart on it
+                        s.dd[i + 1] -= p;
+                        s.ee[m] = 0.0;
+                        early = true;
+                        break;
+                    }
+                    sn = f / r;
+                    c = g / r;
+                    g = s.dd[i + 1] - p;
+                    r = (s.dd[i] - g) * sn + 2.0 * c * b;
+                    p = sn * r;
+                    s.dd[i + 1] = g + p;
+                    g = c * r - b;
+                    s.vv[i] = c;
+                    s.pp[i] = sn;
+                }
+                if (!early) {
+                    s.dd[l] -= p;
+                    s.ee[l] = g;
+                    s.ee[m] = 0.0;
+                    s.ival[2] = l;
+                } else {
+                    s.ival[2] = i + 1;
+                }
+                s.ival[3] = m - 1;
+            }
+            __syncthreads();
+            const int lo = s.ival[2], hi = s.ival[3];
+            for (int row = t; row < n; row += BT) {
+                double carry = Z[row + (int64_t)(hi + 1) * ldz];
+                for (int i = hi; i >= lo; --i) {
+                    const double c = s.vv[i], sn = s.pp[i];
+                    const double zi = Z[row + (int64_t)i * ldz];
+                    Z[row + (int64_t)(i + 1) * ldz] = sn * zi + c * carry;
+                    carry = c * zi - sn * carry;
+                }
+                Z[row + (int64_t)lo * ldz] = carry;
+            }
+            __syncthreads();
+        }
+    }
+    return 0;
+}
+
+// Z := Q Z with Q = H_0 H_1 ... H_{n-3} from wg_sytrd, applied as block
+// reflectors of PB consecutive H (forward, columnwise: I - V T V^T), last
+// block first.  work: >= 3 PB n + PB PB doubles.
+__device__ void wg_ormtr(int n, const double* A, int64_t lda, const double* tau, double* Z, int64_t ldz,
+                         double* work, Lds& s) {
+    const int t = threadIdx.x;
+    const int nref = n - 2;
+    if (nref <= 0) return;
+    const int nblk = (nref + PB - 1) / PB;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int k0 = bi * PB, nb = min(PB, nref - k0);
+        const int rows = n - k0 - 1;  // rows k0+1 .. n-1
+        double* Vb = work;                          // rows x nb
+        double* Tm = Vb + (int64_t)rows * PB;       // PB x PB
+        double* Wt = Tm + PB * PB;                  // nb x n
+        double* Wt2 = Wt + (int64_t)PB * n;         // nb x n
+        for (int c = 0; c < nb; ++c)
+            for (int rr = t; rr < rows; rr += BT)
+                Vb[rr + (int64_t)c * rows] =
+                    rr < c ? 0.0 : (rr == c ? 1.0 : A[(k0 + 1 + rr) + (int64_t)(k0 + c) * lda]);
+        __syncthreads();
+        // G = V^T V (in Wt), then T column by column: T[c][c] = tau_c,
+        // T[0:c, c] = -tau_c T[0:c, 0:c] G[0:c, c]
+        wg_gemm(true, false, nb, nb, rows, 1.0, Vb, rows, Vb, rows, 0.0, Wt, PB, s);
+        for (int e = t; e < PB * PB; e += BT) s.D[e % PB][e / PB] = 0.0;
+        __syncthreads();
+        for (int c = 0; c < nb; ++c) {
+            const double tc = tau[k0 + c];
+            double acc = 0.0;
+            if (t < c) {
+                for (int q = t; q < c; ++q) acc += s.D[t][q] * Wt[q + c * PB];
+            }
+            __syncthreads();
+            if (t < c) s.D[t][c] = -tc * acc;
+            if (t == c) s.D[c][c] = tc;
+            __syncthreads();
+        }
+        for (int e = t; e < PB * PB; e += BT) Tm[e] = s.D[e % PB][e / PB];
+        __syncthreads();
+        wg_gemm(true, false, nb, n, rows, 1.0, Vb, rows, Z + k0 + 1, ldz, 0.0, Wt, nb, s);
+        wg_gemm(false, false, nb, n, nb, 1.0, Tm, PB, Wt, nb, 0.0, Wt2, nb, s);
+        wg_gemm(false, false, rows, n, nb, -1.0, Vb, rows, Wt2, nb, 1.0, Z + k0 + 1, ldz, s);
+    }
+}
+
+__device__ int64_t solve_one(const BProb& p, Lds& s) {
+    const int t = threadIdx.x;
+    const int n = (int)p.n;
+    const int64_t ld = p.ld;
+    double *L = p.L, *W = p.W, *A = p.A, *Z = p.Z;
+    for (int j = 0; j < n; ++j)
+        for (int i = t; i < n; i += BT) {
+            L[i + (int64_t)j * n] = p.M[i + j * ld];
+            W[i + (int64_t)j * n] = p.K[i + j * ld];
+        }
+    __syncthreads();
+    const int piv = wg_potrf(n, L, n, s);
+    if (piv) return piv;
+    wg_trsm_ln(n, n, L, n, W, n, s);  // W = L^-1 K
+    for (int j = 0; j < n; ++j)
+        for (int i = t; i < n; i += BT) A[i + (int64_t)j * n] = W[j + (int64_t)i * n];
+    __syncthreads();
+    wg_trsm_ln(n, n, L, n, A, n, s);  // A = L^-1 K L^-T
+    for (int j = 0; j < n; ++j)
+        for (int i = j + 1 + t; i < n; i += BT) {
+            const double v = 0.5 * (A[i + (int64_t)j * n] + A[j + (int64_t)i * n]);
+            A[i + (int64_t)j * n] = v;
+            A[j + (int64_t)i * n] = v;
+        }
+    __syncthreads();
+    wg_sytrd(n, A, n, p.tau, s);
+    for (int j = 0; j < n; ++j)
+        for (int i = t; i < n; i += BT) Z[i + (int64_t)j * n] = (i == j) ? 1.0 : 0.0;
+    __syncthreads();
+    const int ql = wg_steql(n, Z, n, s);
+    if (ql) return -(int64_t)ql;
+    wg_ormtr(n, A, n, p.tau, Z, n, W, s);
+    wg_trsm_lt(n, n, L, n, Z, n, s);  // V = L^-T Z
+    for (int i = t; i < n; i += BT) {
+        const double di = s.dd[i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) {
+            const double dj = s.dd[j];
+            r += (dj < di || (dj == di && j < i)) ? 1 : 0;
+        }
+        s.rk[i] = r;
+        p.theta[r] = di;
+        p.logtheta[r] = log(di);
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const int dst = s.rk[j];
+        for (int i = t; i < n; i += BT) p.V[i + (int64_t)dst * ld] = Z[i + (int64_t)j * n];
+    }
+    __syncthreads();
+    return 0;
+}
+
+__global__ __launch_bounds__(BT) void batched_eig_kernel(const BProb* __restrict__ probs, const int* __restrict__ order,
+                                                         int count, unsigned* next, int64_t* status) {
+    __shared__ Lds s;
+    for (;;) {
+        if (threadIdx.x == 0) s.ival[0] = (int)atomicAdd(next, 1u);
+        __syncthreads();
+        const int q = s.ival[0];
+        __syncthreads();
+        if (q >= count) break;
+        const int pi = order[q];
+        const int64_t st = solve_one(probs[pi], s);
+        if (threadIdx.x == 0) status[pi] = st;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* ops, int precision,
+                                     fl_eig_info* infos) {
+    if (!ctx) return FL_EINVAL;
+    if (count < 0 || (count > 0 && !ops)) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: bad arguments");
+    if (precision != FL_FP64)
+        return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: the batched solver runs in FP64 only");
+    if (count == 0) return FL_OK;
+    if (count > (int64_t)1 << 30) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: too many problems");
+    for (int64_t i = 0; i < count; ++i) {
+        const fl_op* op = ops[i];
+        if (!op || op->device != ctx->device)
+            return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: null operator or operator of another device");
+        if (op->n < 1 || op->n > NMAX)
+            return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: each n must be in [1, 1024]");
+        for (int64_t j = 0; j < i; ++j)
+            if (ops[j] == op) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: an operator appears twice");
+    }
+    FL_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    // workspace: L, W, A, Z and tau per problem, 256-byte aligned
+    std::vector<int64_t> off(count);
+    int64_t tot = 0;
+    auto al = [](int64_t x) { return (x + 31) / 32 * 32; };
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t n = ops[i]->n;
+        const int64_t wsz = std::max<int64_t>(n * n, 3 * (int64_t)PB * n + PB * PB);
+        off[i] = tot;
+        tot += al(n * n) * 3 + al(wsz) + al(n);
+    }
+    DevBuf bws, bprobs, border, bnext, bstat;
+    FL_HIP(ctx, bws.alloc(sizeof(double) * tot));
+    std::vector<BProb> hp(count);
+    for (int64_t i = 0; i < count; ++i) {
+        fl_op* op = ops[i];
+        const int64_t n = op->n;
+        if (!op->theta) FL_HIP(ctx, hipMalloc(&op->theta, sizeof(double) * n));
+        if (!op->logtheta) FL_HIP(ctx, hipMalloc(&op->logtheta, sizeof(double) * n));
+        if (!op->V) FL_HIP(ctx, hipMalloc(&op->V, sizeof(double) * op->ld * n));
+        op->has_eig = 0;
+        double* w = bws.as<double>() + off[i];
+        const int64_t wsz = std::max<int64_t>(n * n, 3 * (int64_t)PB * n + PB * PB);
+        BProb& b = hp[i];
+        b.n = n;
+        b.ld = op->ld;
+        b.K = op->K;
+        b.M = op->M;
+        b.V = op->V;
+        b.theta = op->theta;
+        b.logtheta = op->logtheta;
+        b.L = w;
+        b.A = w + al(n * n);
+        b.Z = w + 2 * al(n * n);
+        b.W = w + 3 * al(n * n);
+        b.tau = b.W + al(wsz);
+    }
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ops[a]->n > ops[b]->n; });
+    FL_HIP(ctx, bprobs.alloc(sizeof(BProb) * count));
+    FL_HIP(ctx, border.alloc(sizeof(int) * count));
+    FL_HIP(ctx, bnext.alloc(sizeof(unsigned)));
+    FL_HIP(ctx, bstat.alloc(sizeof(int64_t) * count));
+    FL_HIP(ctx, hipMemcpyAsync(bprobs.p, hp.data(), sizeof(BProb) * count, hipMemcpyHostToDevice, s));
+    FL_HIP(ctx, hipMemcpyAsync(border.p, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    FL_HIP(ctx, hipMemsetAsync(bnext.p, 0, sizeof(unsigned), s));
+    FL_HIP(ctx, hipMemsetAsync(bstat.p, 0, sizeof(int64_t) * count, s));
+    int cus = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    const unsigned grid = (unsigned)std::min<int64_t>(count, 2 * (int64_t)cus);
+    hipEvent_t e0, e1;
+    FL_HIP(ctx, hipEventCreate(&e0));
+    FL_HIP(ctx, hipEventCreate(&e1));
+    FL_HIP(ctx, hipEventRecord(e0, s));
+    {
+        KScope ks("batched_eig", s);
+        batched_eig_kernel<<<grid, BT, 0, s>>>(bprobs.as<BProb>(), border.as<int>(), (int)count, bnext.as<unsigned>(),
+                                               bstat.as<int64_t>());
+    }
+    hipError_t le = hipGetLastError();
+    FL_HIP(ctx, hipEventRecord(e1, s));
+    std::vector<int64_t> st(count);
+    FL_HIP(ctx, hipMemcpyAsync(st.data(), bstat.p, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
+    FL_HIP(ctx, hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    FL_HIP(ctx, le);
+    int rc = FL_OK;
+    for (int64_t i = 0; i < count; ++i) {
+        int code = FL_OK;
+        if (st[i] > 0) code = FL_ENOTSPD;
+        if (st[i] < 0) code = FL_ENOCONV;
+        if (code == FL_OK) ops[i]->has_eig = 1;
+        if (infos) {
+            infos[i] = fl_eig_info{};
+            infos[i].status = code;
+            infos[i].index = st[i] > 0 ? st[i] : (st[i] < 0 ? -st[i] : 0);
+            infos[i].total_ms = ms;
+            const double n = (double)ops[i]->n;
+            infos[i].flops_nominal = 9.0 * n * n * n;
+        }
+        if (code != FL_OK && rc == FL_OK) {
+            rc = code;
+            fl_fail(ctx, code,
+                    std::string("fl_eigensolve_batched: problem ") + std::to_string(i) +
+                        (code == FL_ENOTSPD ? ": M is not positive definite at pivot "
+                                            : ": QL did not converge at eigenvalue ") +
+                        std::to_string(st[i] > 0 ? st[i] : -st[i]));
+        }
+    }
+    return rc;
+}

@@ -1,0 +1,150 @@
+"""Batched eigensolve (one persistent launch over many problems) against the
+closed-form Q1 spectra and the CPU oracle (marker: gpu).
+
+Eigenvectors are checked through basis-free quantities (V^T M V, residuals,
+Sylvester inertia); eigenvalues against the exact discrete spectrum on
+rectangles and against the oracle's Jacobi solve on L-shapes.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_11906_amd import inputs
+from oracle.closed_form import Q1Rectangle
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1911_11906_amd.api import Context
+    return Context(0)
+
+
+def exact(mesh):
+    m = mesh.meta
+    if "mx" in m:
+        return Q1Rectangle(m["mx"], m["my"], m["lx"], m["ly"]).eigenvalues()
+    return None
+
+
+def check_op(op, mesh, oracle_mod=None, rel=1e-11):
+    th, V = op.eigenpairs()
+    K, M = op.matrices()
+    n = op.n
+    assert torch.all(th[1:] >= th[:-1])
+    G = V.T @ (M @ V)
+    G.diagonal().sub_(1.0)
+    assert G.abs().max().item() <= 1e-12 * max(n, 10)
+    R = K @ V - (M @ V) * th[None, :]
+    scale = (th.max() * (M @ V).abs().max()).item()
+    assert R.abs().max().item() <= 1e-12 * max(n, 10) * scale
+    ref = exact(mesh)
+    thn = th.cpu().numpy()
+    if ref is not None:
+        assert np.max(np.abs(thn - ref) / ref) <= rel
+    elif oracle_mod is not None:
+        tho, _ = oracle_mod.eigensolve(K.cpu().numpy(), M.cpu().numpy())
+        assert np.max(np.abs(thn - np.sort(tho)) / np.sort(tho)) <= rel
+    return thn
+
+
+def test_batched_small_mixed_shapes(ctx, oracle_mod):
+    """Rectangles of assorted sizes (n = 1, 2, 6, ... 320, several tiles and
+    ragged tails) and L-shapes, solved together."""
+    from paper_1911_11906_amd.api import Operator
+    meshes = [inputs.q1_rectangle(1, 1), inputs.q1_rectangle(2, 1, ly=2.0 / 3.0), inputs.q1_rectangle(3, 2, ly=0.75),
+              inputs.q1_rectangle(8, 8), inputs.q1_rectangle(13, 5, ly=6.0 / 14.0), inputs.q1_rectangle(33, 2, ly=3.0 / 34),
+              inputs.q1_rectangle(16, 20, ly=21.0 / 17.0), inputs.q1_rectangle(10, 32, ly=33.0 / 11.0),
+              inputs.q1_lshape(2), inputs.q1_lshape(5), inputs.q1_lshape(9)]
+    note("batched small", [m.n_dof for m in meshes])
+    ops = [Operator.assemble(ctx, m) for m in meshes]
+    infos = ctx.eigensolve_batched(ops)
+    assert all(i["status"] == 0 for i in infos)
+    for op, mesh in zip(ops, meshes):
+        check_op(op, mesh, oracle_mod)
+    # the batched basis feeds the spectral application: alpha = 0 gives f,
+    # alpha = 2 gives K u = M f
+    op, mesh = ops[6], meshes[6]
+    F = inputs.polynomial_forcings(mesh, 2, tag=61)
+    U0 = op.apply(F, [0.0]).cpu().numpy()
+    assert np.abs(U0 - F).max() <= 1e-11 * np.abs(F).max()
+    K, M = op.matrices()
+    U2 = op.apply(F, [2.0])
+    Ft = torch.from_numpy(F).to(ctx.device)
+    assert (K @ U2 - M @ Ft).abs().max().item() <= 1e-11 * (M @ Ft).abs().max().item()
+
+
+def test_batched_matches_single_solve(ctx):
+    from paper_1911_11906_amd.api import Operator
+    note("batched vs single")
+    mesh = inputs.q1_lshape(12)
+    a = Operator.assemble(ctx, mesh)
+    b = Operator.assemble(ctx, mesh)
+    ctx.eigensolve_batched([a])
+    b.eigensolve("fp64")
+    ta, _ = a.eigenpairs(want_vectors=False)
+    tb, _ = b.eigenpairs(want_vectors=False)
+    assert ((ta - tb).abs() / tb).max().item() <= 1e-12
+
+
+def test_batched_error_paths(ctx):
+    from paper_1911_11906_amd._lib import FL_EINVAL, FL_ENOTSPD, FraclapError
+    from paper_1911_11906_amd.api import Operator
+    note("batched errors")
+    good = Operator.assemble(ctx, inputs.q1_rectangle(6, 6))
+    with pytest.raises(FraclapError) as e:
+        ctx.eigensolve_batched([good], precision="mixed")
+    assert e.value.status == FL_EINVAL
+    big = Operator.assemble(ctx, inputs.q1_rectangle(33, 32, ly=33.0 / 34.0))
+    with pytest.raises(FraclapError) as e:
+        ctx.eigensolve_batched([good, big])
+    assert e.value.status == FL_EINVAL
+    with pytest.raises(FraclapError) as e:
+        ctx.eigensolve_batched([good, good])
+    assert e.value.status == FL_EINVAL
+    n = 50
+    K = np.eye(n) * 2.0
+    M = np.eye(n)
+    M[20, 20] = -1.0
+    bad = Operator.from_dense(ctx, K, M)
+    other = Operator.assemble(ctx, inputs.q1_rectangle(7, 5, ly=0.75))
+    with pytest.raises(FraclapError) as e:
+        ctx.eigensolve_batched([other, bad])
+    assert e.value.status == FL_ENOTSPD
+    assert bad.info["status"] == FL_ENOTSPD and bad.info["index"] == 21
+    assert other.info["status"] == 0
+    check_op(other, inputs.q1_rectangle(7, 5, ly=0.75))
+
+
+def test_batched_256_problems(ctx, oracle_mod):
+    """The batching workload: 256 seeded rectangles and L-shapes with
+    n ~ U[64, 1024], one launch.  Every problem: ordering, V^T M V = I,
+    residuals; rectangles against the exact spectrum; 6 sampled L-shapes
+    against Sylvester inertia counts of the oracle at midpoints between
+    consecutive eigenvalues."""
+    from paper_1911_11906_amd.api import Operator
+    meshes = inputs.batched_problem_meshes(256, tag=4)
+    ns = [m.n_dof for m in meshes]
+    note("batched 256, n in", min(ns), max(ns))
+    ops = [Operator.assemble(ctx, m) for m in meshes]
+    infos = ctx.eigensolve_batched(ops)
+    assert all(i["status"] == 0 for i in infos)
+    note("batched 256 launch ms", infos[0]["total_ms"])
+    lsh = [i for i, m in enumerate(meshes) if "mx" not in m.meta]
+    for op, mesh in zip(ops, meshes):
+        check_op(op, mesh)
+    rng = np.random.default_rng(0)
+    for i in rng.choice(lsh, size=min(6, len(lsh)), replace=False):
+        th, _ = ops[i].eigenpairs(want_vectors=False)
+        th = th.cpu().numpy()
+        K, M = oracle_mod.assemble(meshes[i])
+        for k in rng.choice(len(th) - 1, size=3, replace=False):
+            if th[k + 1] - th[k] <= 1e-9 * th[k + 1]:
+                continue
+            sigma = 0.5 * (th[k] + th[k + 1])
+            assert oracle_mod.inertia_count(K, M, sigma) == k + 1
