@@ -8,8 +8,10 @@ resident in HBM:
     back-transforms, V = L^-T Z, and in mixed mode (the default) FP32
     back-transforms followed by one FP64 refinement step;
   * the fractional solutions v(alpha_i, f_j) for 1024 seeded random cubic
-    polynomial forcings x 32 orders alpha ~ U(0, 2) (32768 solutions).
-value = solutions per second of the whole step (eigensolve included).
+    polynomial forcings x 32 orders alpha ~ U(0, 2) (32768 solutions);
+  * the batched FP64 eigensolve of 256 seeded Q1 rectangles / L-shapes with
+    n ~ U[64, 1024] (one persistent launch).
+value = solutions per second of the whole step (both eigensolves included).
 
 Extra fields: eigensolve seconds and nominal TFLOP/s (9 n^3) of the timed
 precision and of the other one (timed once, outside the timed region), the
@@ -32,7 +34,7 @@ METRIC = "eigensolve s & TFLOP/s at n=16384, mixed vs FP64; fractional solves/se
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-KERNELS = ("q2_apply", "sb2st", "scaled_gemm")
+KERNELS = ("q2_apply", "sb2st", "scaled_gemm", "batched_eig")
 
 
 def parse():
@@ -44,6 +46,7 @@ def parse():
     p.add_argument("--nf", type=int, default=1024)
     p.add_argument("--na", type=int, default=32)
     p.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    p.add_argument("--nbatch", type=int, default=256, help="problems of the batched eigensolve (0 = skip)")
     p.add_argument("--no-compare", action="store_true", help="skip the other precision's eigensolve")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
@@ -168,13 +171,19 @@ def main():
     F = colmajor(inputs.polynomial_forcings(mesh, args.nf, tag=4), dev)
     alpha = inputs.alphas_uniform(args.na, tag=4)
     U = empty_colmajor(n, args.nf * args.na, dev)
+    bmeshes = inputs.batched_problem_meshes(args.nbatch, tag=4) if args.nbatch > 0 else []
+    bops = [Operator.assemble(ctx, m) for m in bmeshes]
+    bflops = sum(9.0 * m.n_dof ** 3 for m in bmeshes)
     torch.cuda.synchronize()
     prec = args.precision
     other = "mixed" if prec == "fp64" else "fp64"
+    binfos = []
 
     def step():
         info = op.eigensolve(prec)
         op.apply(F, alpha, out=U)
+        if bops:
+            binfos.append(ctx.eigensolve_batched(bops)[0])
         return info
 
     if args.calibrate_copy > 0:
@@ -213,6 +222,7 @@ def main():
         "q2_apply": q2_flops(n, b),
         "sb2st": sb2st_flops(n, b),
         "scaled_gemm": 2.0 * n * n * nsol,
+        "batched_eig": bflops,
     }
     kernels = {}
     for k, (cnt, ms) in ktime.items():
@@ -220,7 +230,7 @@ def main():
             continue
         fl = per_step_flops[k] * args.steps
         ach = fl / (ms / 1e3) / 1e12
-        bound, peak = ("alu", PEAK_FP64_TFLOPS) if k == "sb2st" else (
+        bound, peak = ("alu", PEAK_FP64_TFLOPS) if k in ("sb2st", "batched_eig") else (
             "mfma", peak_mm if k == "q2_apply" else PEAK_FP64_TFLOPS)
         kernels[k] = {"launches": cnt, "total_ms": ms, "avg_ms": ms / cnt, "flops_per_launch": fl / cnt,
                       "bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
@@ -245,14 +255,20 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"Q1 unit square {args.m}x{args.m} (n={n}): {prec} full generalized eigensolve + "
-                               f"{args.nf} cubic forcings x {args.na} alpha", "n": n, "nf": args.nf,
-                   "na": args.na, "precision": prec},
+                               f"{args.nf} cubic forcings x {args.na} alpha + batched FP64 eigensolve of "
+                               f"{args.nbatch} seeded rectangles/L-shapes (n in [64, 1024])", "n": n,
+                   "nf": args.nf, "na": args.na, "precision": prec, "nbatch": args.nbatch},
         "eigensolve_s": eig_s,
         "eigensolve_tflops_nominal": flops_eig / eig_s / 1e12,
         "eigensolve_stage_ms": stages,
         "refine_iters": infos[0]["refine_iters"],
         "scaled_gemm_tflops": (2.0 * n * n * nsol) / (apply_ms / 1e3) / 1e12 if apply_ms else None,
         "roofline": roofline,
+        "batched_eigensolve": None if not bops else {
+            "problems": len(bops), "n_min": min(m.n_dof for m in bmeshes), "n_max": max(m.n_dof for m in bmeshes),
+            "launch_ms": float(np.median([b["total_ms"] for b in binfos[-args.steps:]])),
+            "problems_per_s": len(bops) / (float(np.median([b["total_ms"] for b in binfos[-args.steps:]])) / 1e3),
+            "tflops_nominal": bflops / (float(np.median([b["total_ms"] for b in binfos[-args.steps:]])) / 1e3) / 1e12},
         "kernels": kernels,
     }
     if info_other is not None:

@@ -30,6 +30,12 @@ constexpr int PB = 32;                    // panel / reflector block width
 constexpr int TM = 64, TN = 64, TK = 16;  // GEMM tile (4 x 4 outputs per thread)
 constexpr double EPS = 2.220446049250313e-16;
 
+// The workgroup routines below are kept as separate (noinline) functions:
+// fully inlined into the one persistent kernel, the register pressure (256
+// VGPRs plus spills) produced wrong results in the blocked triangular solve
+// at n > 32, while the same code called as functions, or in a small kernel,
+// is exact.
+
 struct BProb {
     int64_t n, ld;                                      // ld: of K, M and V
     const double* K;
@@ -54,6 +60,18 @@ struct Lds {
     int ival[4];
 };
 
+// Barrier for data handed between the waves of the workgroup through global
+// memory: drain this wave's stores, barrier, then drop stale vector-L1 lines.
+// (A plain workgroup barrier on gfx950 waits for LDS traffic only: a store
+// still in flight, or an L1 line fetched before another wave's store, could
+// otherwise be read after it.)
+__device__ inline void gsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 __device__ double wg_sum(double v, Lds& s) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     __syncthreads();
@@ -66,7 +84,7 @@ __device__ double wg_sum(double v, Lds& s) {
 
 // C (m x n) = alpha op(A) op(B) + beta C, column-major, op = transpose when
 // ta / tb.  C must not overlap A or B.
-__device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int64_t lda,
+__device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int64_t lda,
                         const double* B, int64_t ldb, double beta, double* C, int64_t ldc, Lds& s) {
     if (m <= 0 || n <= 0) return;
     const int t = threadIdx.x;
@@ -137,12 +155,12 @@ __device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, con
             }
         }
     }
-    __syncthreads();
+    gsync();
 }
 
 // Cholesky of the leading n x n of A (lower triangle used and overwritten).
 // Returns 0, or the 1-based index of the first non-positive pivot.
-__device__ int wg_potrf(int n, double* A, int64_t lda, Lds& s) {
+__device__ __attribute__((noinline)) int wg_potrf(int n, double* A, int64_t lda, Lds& s) {
     const int t = threadIdx.x;
     for (int j0 = 0; j0 < n; j0 += PB) {
         const int jb = min(PB, n - j0);
@@ -195,13 +213,13 @@ __device__ int wg_potrf(int n, double* A, int64_t lda, Lds& s) {
                 }
             }
         }
-        __syncthreads();
+        gsync();
     }
     return 0;
 }
 
 // Solve L X = B in place (L lower, n x n; B n x nrhs).
-__device__ void wg_trsm_ln(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
+__device__ __attribute__((noinline)) void wg_trsm_ln(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
     for (int i0 = 0; i0 < n; i0 += PB) {
         const int ib = min(PB, n - i0);
@@ -225,7 +243,7 @@ __device__ void wg_trsm_ln(int n, int nrhs, const double* L, int64_t ldl, double
                 }
             }
         }
-        __syncthreads();
+        gsync();
         if (i0 + ib < n)
             wg_gemm(false, false, n - i0 - ib, nrhs, ib, -1.0, L + i0 + ib + (int64_t)i0 * ldl, ldl, B + i0, ldb,
                     1.0, B + i0 + ib, ldb, s);
@@ -233,7 +251,7 @@ __device__ void wg_trsm_ln(int n, int nrhs, const double* L, int64_t ldl, double
 }
 
 // Solve L^T X = B in place.
-__device__ void wg_trsm_lt(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
+__device__ __attribute__((noinline)) void wg_trsm_lt(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
     const int nblk = (n + PB - 1) / PB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -259,7 +277,7 @@ __device__ void wg_trsm_lt(int n, int nrhs, const double* L, int64_t ldl, double
                 }
             }
         }
-        __syncthreads();
+        gsync();
         if (i0 > 0) wg_gemm(true, false, i0, nrhs, ib, -1.0, L + i0, ldl, B + i0, ldb, 1.0, B, ldb, s);
     }
 }
@@ -267,7 +285,7 @@ __device__ void wg_trsm_lt(int n, int nrhs, const double* L, int64_t ldl, double
 // Householder tridiagonalisation of the symmetric A (full storage, lower
 // reflectors): reflector k has v = (1, A[k+2:n, k]) on rows k+1..n-1 and tau[k].
 // d and e (e[i] couples i and i+1) are left in s.dd, s.ee.
-__device__ void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
+__device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
     const int t = threadIdx.x;
     for (int k = 0; k < n - 2; ++k) {
         const int m = n - k - 1;
@@ -294,7 +312,6 @@ __device__ void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
             s.dd[k] = A[k + (int64_t)k * lda];
             s.ee[k] = beta;
             tau[k] = tk;
-            x[0] = beta;
         }
         __syncthreads();
         if (tk != 0.0) {
@@ -318,7 +335,7 @@ __device__ void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
                     *a = __dsub_rn(*a, __dadd_rn(p1, p2));
                 }
             }
-            __syncthreads();
+            gsync();
         }
     }
     if (t == 0) {
@@ -336,7 +353,7 @@ __device__ void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
 // entry) accumulates the rotations.  One thread runs each sweep's scalar
 // recurrence and stages its rotations in LDS; then every thread applies them
 // to its rows of Z.  Returns 0, or l+1 if eigenvalue l took over 60 sweeps.
-__device__ int wg_steql(int n, double* Z, int64_t ldz, Lds& s) {
+__device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz, Lds& s) {
     const int t = threadIdx.x;
     for (int l = 0; l < n; ++l) {
         int iter = 0;
@@ -413,7 +430,7 @@ __device__ int wg_steql(int n, double* Z, int64_t ldz, Lds& s) {
 // Z := Q Z with Q = H_0 H_1 ... H_{n-3} from wg_sytrd, applied as block
 // reflectors of PB consecutive H (forward, columnwise: I - V T V^T), last
 // block first.  work: >= 3 PB n + PB PB doubles.
-__device__ void wg_ormtr(int n, const double* A, int64_t lda, const double* tau, double* Z, int64_t ldz,
+__device__ __attribute__((noinline)) void wg_ormtr(int n, const double* A, int64_t lda, const double* tau, double* Z, int64_t ldz,
                          double* work, Lds& s) {
     const int t = threadIdx.x;
     const int nref = n - 2;
@@ -430,7 +447,7 @@ __device__ void wg_ormtr(int n, const double* A, int64_t lda, const double* tau,
             for (int rr = t; rr < rows; rr += BT)
                 Vb[rr + (int64_t)c * rows] =
                     rr < c ? 0.0 : (rr == c ? 1.0 : A[(k0 + 1 + rr) + (int64_t)(k0 + c) * lda]);
-        __syncthreads();
+        gsync();
         // G = V^T V (in Wt), then T column by column: T[c][c] = tau_c,
         // T[0:c, c] = -tau_c T[0:c, 0:c] G[0:c, c]
         wg_gemm(true, false, nb, nb, rows, 1.0, Vb, rows, Vb, rows, 0.0, Wt, PB, s);
@@ -448,7 +465,7 @@ __device__ void wg_ormtr(int n, const double* A, int64_t lda, const double* tau,
             __syncthreads();
         }
         for (int e = t; e < PB * PB; e += BT) Tm[e] = s.D[e % PB][e / PB];
-        __syncthreads();
+        gsync();
         wg_gemm(true, false, nb, n, rows, 1.0, Vb, rows, Z + k0 + 1, ldz, 0.0, Wt, nb, s);
         wg_gemm(false, false, nb, n, nb, 1.0, Tm, PB, Wt, nb, 0.0, Wt2, nb, s);
         wg_gemm(false, false, rows, n, nb, -1.0, Vb, rows, Wt2, nb, 1.0, Z + k0 + 1, ldz, s);
@@ -465,13 +482,13 @@ __device__ int64_t solve_one(const BProb& p, Lds& s) {
             L[i + (int64_t)j * n] = p.M[i + j * ld];
             W[i + (int64_t)j * n] = p.K[i + j * ld];
         }
-    __syncthreads();
+    gsync();
     const int piv = wg_potrf(n, L, n, s);
     if (piv) return piv;
     wg_trsm_ln(n, n, L, n, W, n, s);  // W = L^-1 K
     for (int j = 0; j < n; ++j)
         for (int i = t; i < n; i += BT) A[i + (int64_t)j * n] = W[j + (int64_t)i * n];
-    __syncthreads();
+    gsync();
     wg_trsm_ln(n, n, L, n, A, n, s);  // A = L^-1 K L^-T
     for (int j = 0; j < n; ++j)
         for (int i = j + 1 + t; i < n; i += BT) {
@@ -479,12 +496,13 @@ __device__ int64_t solve_one(const BProb& p, Lds& s) {
             A[i + (int64_t)j * n] = v;
             A[j + (int64_t)i * n] = v;
         }
-    __syncthreads();
+    gsync();
     wg_sytrd(n, A, n, p.tau, s);
     for (int j = 0; j < n; ++j)
         for (int i = t; i < n; i += BT) Z[i + (int64_t)j * n] = (i == j) ? 1.0 : 0.0;
-    __syncthreads();
+    gsync();
     const int ql = wg_steql(n, Z, n, s);
+    gsync();
     if (ql) return -(int64_t)ql;
     wg_ormtr(n, A, n, p.tau, Z, n, W, s);
     wg_trsm_lt(n, n, L, n, Z, n, s);  // V = L^-T Z

@@ -54,7 +54,8 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                 if (i > 0) {
                     int need = (int)((j + 3 < ntp) ? (j + 3) : ntp);
                     long spins = 0;
-                    while (__hip_atomic_load(&prog[i - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    // poll relaxed (no cache invalidation per poll), acquire once
+                    while (__hip_atomic_load(&prog[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         __builtin_amdgcn_s_sleep(2);
                         if (++spins > SPIN_CAP || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                             __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                             break;
                         }
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
             }
             __syncthreads();
@@ -194,9 +196,12 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
             double* vout = V2 + (i * maxt + j) * (int64_t)b;
             for (int r = t; r < b; r += NTH) vout[r] = (r < L) ? vv[r] : 0.0;
             if (t == 0) tau2[i * maxt + j] = tauc;
-            // ---- publish progress: the barrier orders every wave's stores before
-            // thread 0's agent-scope release (which writes the L2 back)
-            __syncthreads();
+            // ---- publish progress: every wave first waits for its own stores
+            // (a plain workgroup barrier waits for LDS traffic only), then
+            // thread 0's agent-scope release writes the L2 back and sets the flag
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_s_barrier();
             if (t == 0) __hip_atomic_store(&prog[i], (int)(j + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             // the block below becomes the next off-diagonal block
             double* tmp = Boff;

@@ -282,6 +282,12 @@ def paper_alpha_sweep() -> np.ndarray:
     return np.linspace(0.0, 2.0, 11)
 
 
+def _lshape_ndof(m: int) -> int:
+    """Interior nodes of q1_lshape(m): the (2m+1)^2 interior grid minus the
+    (m+1)^2 nodes of the removed quadrant (its re-entrant edges included)."""
+    return (2 * m + 1) ** 2 - (m + 1) ** 2
+
+
 def batched_problem_meshes(count: int = 256, tag: int = 4, nmin: int = 64, nmax: int = 1024):
     """Rectangles (aspect U(0.5,2)) and L-shapes with interior size near
     n_target ~ U{nmin..nmax}."""
@@ -293,11 +299,23 @@ def batched_problem_meshes(count: int = 256, tag: int = 4, nmin: int = 64, nmax:
             aspect = rng.uniform(0.5, 2.0)
             mx = max(2, int(round(np.sqrt(nt * aspect))))
             my = max(2, int(round(nt / mx)))
+            while mx * my > nmax:          # keep n inside [nmin, nmax]
+                if mx >= my:
+                    mx -= 1
+                else:
+                    my -= 1
+            while mx * my < nmin:
+                if mx <= my:
+                    mx += 1
+                else:
+                    my += 1
             out.append(q1_rectangle(mx, my, lx=1.0, ly=float(my + 1) / float(mx + 1)))
         else:
             best = None
             for m in range(1, 40):
-                nn = q1_lshape(m).n_dof
+                nn = _lshape_ndof(m)
+                if nn < nmin or nn > nmax:
+                    continue
                 if best is None or abs(nn - nt) < abs(best[1] - nt):
                     best = (m, nn)
             out.append(q1_lshape(best[0]))
