@@ -24,10 +24,12 @@
 
 namespace {
 
-constexpr int BT = 256;                   // threads per workgroup (4 waves)
-constexpr int NMAX = 1024;                // largest problem
-constexpr int PB = 32;                    // panel / reflector block width
-constexpr int TM = 64, TN = 64, TK = 16;  // GEMM tile (4 x 4 outputs per thread)
+constexpr int BT = 512;                    // threads per workgroup (8 waves)
+constexpr int NMAX = 1024;                 // largest problem
+constexpr int PB = 32;                     // panel / reflector block width
+constexpr int TM = 64, TN = 128, TK = 16;  // GEMM tile (4 x 4 outputs per thread)
+constexpr int RPT = NMAX / BT;             // rows per thread in the tridiagonalisation
+static_assert(TM * TN == 16 * BT, "one 4 x 4 register tile per thread");
 constexpr double EPS = 2.220446049250313e-16;
 
 // The workgroup routines below are kept as separate (noinline) functions:
@@ -52,12 +54,13 @@ struct Lds {
     double Bs[TK][TN + 1];
     double D[PB][PB + 1];
     double red[BT / 64];
-    double vv[NMAX];  // Householder vector, QL cosines
-    double pp[NMAX];  // symv result, QL sines
+    double va[2][NMAX];  // Householder vectors (two in flight), QL cosines
+    double wa[2][NMAX];  // their w = p - (tau/2)(p^T v) v, QL sines
     double dd[NMAX];  // diagonal of T, then theta
     double ee[NMAX];  // off-diagonal of T
     int rk[NMAX];     // ranks of theta
     int ival[4];
+    double dval[4];
 };
 
 // Barrier for data handed between the waves of the workgroup through global
@@ -114,6 +117,10 @@ __device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n
                 double a = 0.0;
                 if (gi < m && gk < k) a = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
                 s.As[kk][i] = a;
+            }
+#pragma unroll
+            for (int q = 0; q < (TN * TK) / BT; ++q) {
+                const int e = t + BT * q;
                 int j, kb;
                 if (!tb) {
                     kb = e % TK;
@@ -282,71 +289,187 @@ __device__ __attribute__((noinline)) void wg_trsm_lt(int n, int nrhs, const doub
     }
 }
 
-// Householder tridiagonalisation of the symmetric A (full storage, lower
-// reflectors): reflector k has v = (1, A[k+2:n, k]) on rows k+1..n-1 and tau[k].
-// d and e (e[i] couples i and i+1) are left in s.dd, s.ee.
-__device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
+// In the tridiagonalisation thread t owns the global rows g = t + q BT
+// (q < RPT) of A for the whole reduction, so every element of A is read and
+// written by one thread only and only LDS carries data between threads.
+
+// Householder reflector of x = A[g0 : g0 + m, c] (x[0] = alpha at row g0):
+// x[1:] is scaled in place into v[1:] (also copied to the LDS vector v,
+// indexed from row g0).  Returns tau; beta goes to *beta.
+__device__ double wg_house(int n, int64_t g0, int m, double* col, double alpha, double* v, double* beta,
+                           Lds& s) {
     const int t = threadIdx.x;
-    for (int k = 0; k < n - 2; ++k) {
-        const int m = n - k - 1;
-        double* x = A + (k + 1) + (int64_t)k * lda;
-        double loc = 0.0;
-        for (int r = 1 + t; r < m; r += BT) loc += x[r] * x[r];
-        const double xn2 = wg_sum(loc, s);
-        const double alpha = x[0];
-        double tk = 0.0, beta = alpha;
-        if (xn2 > 0.0) {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            tk = (beta - alpha) / beta;
-            const double sc = 1.0 / (alpha - beta);
-            for (int r = 1 + t; r < m; r += BT) {
-                const double v = x[r] * sc;
-                x[r] = v;
-                s.vv[r] = v;
-            }
-        } else {
-            for (int r = 1 + t; r < m; r += BT) s.vv[r] = 0.0;
-        }
-        if (t == 0) {
-            s.vv[0] = 1.0;
-            s.dd[k] = A[k + (int64_t)k * lda];
-            s.ee[k] = beta;
-            tau[k] = tk;
-        }
-        __syncthreads();
-        if (tk != 0.0) {
-            double* A22 = A + (k + 1) + (int64_t)(k + 1) * lda;
-            for (int i = t; i < m; i += BT) {
-                double acc = 0.0;
-                for (int j = 0; j < m; ++j) acc = fma(A22[i + (int64_t)j * lda], s.vv[j], acc);
-                s.pp[i] = tk * acc;
-            }
-            double loc2 = 0.0;
-            for (int i = t; i < m; i += BT) loc2 += s.pp[i] * s.vv[i];
-            const double hc = 0.5 * tk * wg_sum(loc2, s);
-            for (int i = t; i < m; i += BT) s.pp[i] -= hc * s.vv[i];
-            __syncthreads();
-            // A22 -= v w^T + w v^T, rounded identically for (i, j) and (j, i)
-            for (int j = 0; j < m; ++j) {
-                const double vj = s.vv[j], wj = s.pp[j];
-                for (int i = t; i < m; i += BT) {
-                    const double p1 = __dmul_rn(s.vv[i], wj), p2 = __dmul_rn(s.pp[i], vj);
-                    double* a = A22 + i + (int64_t)j * lda;
-                    *a = __dsub_rn(*a, __dadd_rn(p1, p2));
-                }
-            }
-            gsync();
+    double loc = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t g = t + q * BT;
+        const int64_t r = g - g0;
+        if (g < n && r >= 1 && r < m) loc += col[g] * col[g];
+    }
+    const double xn2 = wg_sum(loc, s);
+    double tk = 0.0, bt = alpha;
+    const double sc = (xn2 > 0.0) ? 1.0 / (alpha - (-copysign(sqrt(alpha * alpha + xn2), alpha))) : 0.0;
+    if (xn2 > 0.0) {
+        bt = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tk = (bt - alpha) / bt;
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t g = t + q * BT;
+        const int64_t r = g - g0;
+        if (g < n && r >= 1 && r < m) {
+            const double vr = col[g] * sc;
+            col[g] = vr;
+            v[r] = vr;
         }
     }
-    if (t == 0) {
-        if (n >= 2) {
-            s.dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * lda];
-            s.ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
-        }
-        s.dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * lda];
-        s.ee[n - 1] = 0.0;
+    if (t == 0) v[0] = 1.0;
+    *beta = bt;
+    return tk;
+}
+
+// w = p - (tau/2)(p^T v) v with p = tau acc; acc[q] belongs to global row
+// t + q BT = trailing row i + g0.
+__device__ void wg_make_w(int n, int64_t g0, int m, double tk, const double (&acc)[RPT], const double* v, double* w,
+                          Lds& s) {
+    const int t = threadIdx.x;
+    double loc = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = t + q * BT - g0;
+        if (i >= 0 && i < m) loc += tk * acc[q] * v[i];
+    }
+    const double hc = 0.5 * tk * wg_sum(loc, s);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = t + q * BT - g0;
+        if (i >= 0 && i < m) w[i] = tk * acc[q] - hc * v[i];
     }
     __syncthreads();
+}
+
+// Householder tridiagonalisation of the symmetric A (full storage, kept
+// exactly symmetric), lower reflectors: reflector k has v = (1, A[k+2:n, k])
+// on rows k+1..n-1 and tau[k]; d and e (e[i] couples i and i+1) are left in
+// s.dd and s.ee.  One pass over the trailing matrix per step: the rank-2
+// update of step k, A22 -= v w^T + w v^T, is fused with the product
+// A22' v' of step k+1 (A22' = A22 without its first row and column).
+__device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
+    const int t = threadIdx.x;
+    if (n <= 2) {
+        if (t == 0) {
+            s.dd[0] = A[0];
+            if (n == 2) {
+                s.dd[1] = A[1 + lda];
+                s.ee[0] = A[1];
+            }
+            s.ee[n - 1] = 0.0;
+        }
+        __syncthreads();
+        return;
+    }
+    // reflector 0 (column 0, rows 1..n-1) and acc = A[1:, 1:] v
+    {
+        double beta;
+        if (t == 0) s.dval[1] = A[1];
+        __syncthreads();
+        const double tk = wg_house(n, 1, n - 1, A, s.dval[1], s.va[0], &beta, s);
+        if (t == 0) {
+            s.dd[0] = A[0];
+            s.ee[0] = beta;
+            tau[0] = tk;
+        }
+        __syncthreads();
+        double acc[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+        for (int j = 1; j < n; ++j) {
+            const double vj = s.va[0][j - 1];
+            const double* col = A + (int64_t)j * lda;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int g = t + q * BT;
+                if (g >= 1 && g < n) acc[q] = fma(col[g], vj, acc[q]);
+            }
+        }
+        wg_make_w(n, 1, n - 1, tk, acc, s.va[0], s.wa[0], s);
+    }
+    for (int k = 0; k < n - 2; ++k) {
+        const int cur = k & 1, nxt = cur ^ 1;
+        const double* v = s.va[cur];  // step k, indexed by trailing row: global row k+1+i
+        const double* w = s.wa[cur];
+        const int64_t g0 = k + 1;      // first global row (and column) of A22
+        const int m = n - k - 1;       // order of A22
+        if (k + 1 < n - 2) {
+            // (a) column g0 (rows g0..n-1) with step k's update: d[k+1], and x of step k+1
+            double* c0 = A + g0 * lda;
+            const double v0 = v[0], w0 = w[0];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t g = t + q * BT;
+                const int64_t i = g - g0;
+                if (g < n && i >= 0) {
+                    const double p1 = __dmul_rn(v[i], w0), p2 = __dmul_rn(w[i], v0);
+                    c0[g] = __dsub_rn(c0[g], __dadd_rn(p1, p2));
+                    if (i == 0) s.dval[0] = c0[g];
+                    if (i == 1) s.dval[1] = c0[g];
+                }
+            }
+            __syncthreads();
+            // (b) reflector k+1 from rows g0+1.. of that column
+            double beta;
+            const double tk = wg_house(n, g0 + 1, m - 1, c0, s.dval[1], s.va[nxt], &beta, s);
+            if (t == 0) {
+                s.dd[k + 1] = s.dval[0];
+                s.ee[k + 1] = beta;
+                tau[k + 1] = tk;
+            }
+            __syncthreads();
+            // (c) rows/columns g0+1.. : A -= v w^T + w v^T, fused with acc = A v'
+            const double* v2 = s.va[nxt];  // indexed from global row g0+1
+            double acc[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+            for (int j = 1; j < m; ++j) {
+                const double vj = v[j], wj = w[j], v2j = v2[j - 1];
+                double* col = A + (g0 + j) * lda;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int64_t g = t + q * BT;
+                    const int64_t i = g - g0;
+                    if (g < n && i >= 1) {
+                        const double p1 = __dmul_rn(v[i], wj), p2 = __dmul_rn(w[i], vj);
+                        const double a = __dsub_rn(col[g], __dadd_rn(p1, p2));
+                        col[g] = a;
+                        acc[q] = fma(a, v2j, acc[q]);
+                    }
+                }
+            }
+            // (d) w of step k+1
+            wg_make_w(n, g0 + 1, m - 1, tk, acc, v2, s.wa[nxt], s);
+        } else {
+            // last step (m == 2): the remaining 2 x 2 block, rows n-2 and n-1
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t g = t + q * BT;
+                const int64_t i = g - g0;
+                if (g < n && i >= 0) {
+                    for (int j = 0; j <= i; ++j) {
+                        const double p1 = __dmul_rn(v[i], w[j]), p2 = __dmul_rn(w[i], v[j]);
+                        double* a = A + g + (g0 + j) * lda;
+                        *a = __dsub_rn(*a, __dadd_rn(p1, p2));
+                    }
+                    if (i == 0) s.dd[n - 2] = A[g + g0 * lda];
+                    if (i == 1) {
+                        s.ee[n - 2] = A[g + g0 * lda];
+                        s.dd[n - 1] = A[g + (g0 + 1) * lda];
+                    }
+                }
+            }
+            if (t == 0) s.ee[n - 1] = 0.0;
+            __syncthreads();
+        }
+    }
 }
 
 // Implicit QL with Wilkinson shifts on (s.dd, s.ee); Z (n x n, identity on
@@ -396,8 +519,8 @@ __device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz,
                     p = sn * r;
                     s.dd[i + 1] = g + p;
                     g = c * r - b;
-                    s.vv[i] = c;
-                    s.pp[i] = sn;
+                    s.va[0][i] = c;
+                    s.wa[0][i] = sn;
                 }
                 if (!early) {
                     s.dd[l] -= p;
@@ -411,15 +534,28 @@ __device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz,
             }
             __syncthreads();
             const int lo = s.ival[2], hi = s.ival[3];
+            // each row is independent; its elements are read in groups of 8
+            // before the dependent rotation chain runs over them
             for (int row = t; row < n; row += BT) {
-                double carry = Z[row + (int64_t)(hi + 1) * ldz];
-                for (int i = hi; i >= lo; --i) {
-                    const double c = s.vv[i], sn = s.pp[i];
-                    const double zi = Z[row + (int64_t)i * ldz];
-                    Z[row + (int64_t)(i + 1) * ldz] = sn * zi + c * carry;
-                    carry = c * zi - sn * carry;
+                double* zr = Z + row;
+                double carry = zr[(int64_t)(hi + 1) * ldz];
+                int i = hi;
+                while (i >= lo) {
+                    const int cnt = min(8, i - lo + 1);
+                    double zc[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) zc[q] = (q < cnt) ? zr[(int64_t)(i - q) * ldz] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        if (q < cnt) {
+                            const double c = s.va[0][i - q], sn = s.wa[0][i - q];
+                            zr[(int64_t)(i - q + 1) * ldz] = sn * zc[q] + c * carry;
+                            carry = c * zc[q] - sn * carry;
+                        }
+                    }
+                    i -= cnt;
                 }
-                Z[row + (int64_t)lo * ldz] = carry;
+                zr[(int64_t)lo * ldz] = carry;
             }
             __syncthreads();
         }
