@@ -29,6 +29,7 @@ constexpr int NMAX = 1024;                 // largest problem
 constexpr int PB = 32;                     // panel / reflector block width
 constexpr int TM = 64, TN = 128, TK = 16;  // GEMM tile (4 x 4 outputs per thread)
 constexpr int RPT = NMAX / BT;             // rows per thread in the tridiagonalisation
+constexpr int QS = 4;                      // QL sweeps applied to Z per pass
 static_assert(TM * TN == 16 * BT, "one 4 x 4 register tile per thread");
 constexpr double EPS = 2.220446049250313e-16;
 
@@ -58,8 +59,11 @@ struct Lds {
     double wa[2][NMAX];  // their w = p - (tau/2)(p^T v) v, QL sines
     double dd[NMAX];  // diagonal of T, then theta
     double ee[NMAX];  // off-diagonal of T
+    double qx[2][NMAX];  // rotations of two more buffered QL sweeps
+    double qy[2][NMAX];
     int rk[NMAX];     // ranks of theta
     int ival[4];
+    int qlo[4], qhi[4];
     double dval[4];
 };
 
@@ -472,12 +476,90 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
     }
 }
 
+__device__ inline double* ql_cos(Lds& s, int b) { return b < 2 ? s.va[b] : s.qx[b - 2]; }
+__device__ inline double* ql_sin(Lds& s, int b) { return b < 2 ? s.wa[b] : s.qy[b - 2]; }
+
+// Apply nb <= QS buffered QL sweeps to the rows of Z in one pass.  Sweep b
+// applies its rotations (i, i+1), i = hi_b .. lo_b, in that order.  Each row is
+// walked downwards with a register window of 2 QS columns: at position c,
+// sweep b rotates columns (c + 2b, c + 2b + 1).  Sweep b at i needs sweep b-1
+// to have rotated (i-1, i), which happened at position c + 1, and nothing
+// touches column c + 2 QS - 1 after position c, so it is written back then.
+__device__ void ql_apply(int n, double* Z, int64_t ldz, int nb, Lds& s) {
+    const int t = threadIdx.x;
+    int lo[QS], hi[QS];
+    const double* C[QS];
+    const double* S[QS];
+    int cstart = -(1 << 30), cend = 1 << 30;
+#pragma unroll
+    for (int b = 0; b < QS; ++b) {
+        lo[b] = (b < nb) ? s.qlo[b] : 1;
+        hi[b] = (b < nb) ? s.qhi[b] : 0;
+        C[b] = ql_cos(s, b);
+        S[b] = ql_sin(s, b);
+        if (lo[b] <= hi[b]) {
+            cstart = max(cstart, hi[b] - 2 * b);
+            cend = min(cend, lo[b] - 2 * b);
+        }
+    }
+    if (cstart < cend) return;  // no rotations (uniform: every thread read the same LDS)
+    for (int row = t; row < n; row += BT) {
+        double* zr = Z + row;
+        double win[2 * QS];
+#pragma unroll
+        for (int k = 0; k < 2 * QS; ++k) {
+            const int col = cstart + k;
+            win[k] = (col >= 0 && col < n) ? zr[(int64_t)col * ldz] : 0.0;
+        }
+        int c = cstart;
+        while (c >= cend) {
+            const int cnt = min(8, c - cend + 1);
+            double pre[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int col = c - 1 - q;
+                pre[q] = (q < cnt && col >= 0) ? zr[(int64_t)col * ldz] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (q < cnt) {
+                    const int cc = c - q;
+#pragma unroll
+                    for (int b = 0; b < QS; ++b) {
+                        const int i = cc + 2 * b;
+                        if (lo[b] <= i && i <= hi[b]) {
+                            const double cs = C[b][i], sn = S[b][i];
+                            const double x = win[2 * b], y = win[2 * b + 1];
+                            win[2 * b] = cs * x - sn * y;
+                            win[2 * b + 1] = sn * x + cs * y;
+                        }
+                    }
+                    const int col_out = cc + 2 * QS - 1;
+                    if (col_out < n) zr[(int64_t)col_out * ldz] = win[2 * QS - 1];
+#pragma unroll
+                    for (int k = 2 * QS - 1; k > 0; --k) win[k] = win[k - 1];
+                    win[0] = pre[q];
+                }
+            }
+            c -= cnt;
+        }
+        // the window now holds columns cend-1 .. cend-1 + 2QS-1
+#pragma unroll
+        for (int k = 0; k < 2 * QS; ++k) {
+            const int col = cend - 1 + k;
+            if (col >= 0 && col < n) zr[(int64_t)col * ldz] = win[k];
+        }
+    }
+}
+
 // Implicit QL with Wilkinson shifts on (s.dd, s.ee); Z (n x n, identity on
 // entry) accumulates the rotations.  One thread runs each sweep's scalar
-// recurrence and stages its rotations in LDS; then every thread applies them
-// to its rows of Z.  Returns 0, or l+1 if eigenvalue l took over 60 sweeps.
+// recurrence and stages its rotations in LDS; every QS sweeps all threads
+// apply them to their rows of Z in one pass.  Returns 0, or l+1 if
+// eigenvalue l took over 60 sweeps.
 __device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz, Lds& s) {
     const int t = threadIdx.x;
+    int nb = 0;  // buffered sweeps (the same in every thread)
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         for (;;) {
@@ -495,6 +577,8 @@ __device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz,
             if (m == l) break;
             if (++iter > 60) return l + 1;
             if (t == 0) {
+                double* qc = ql_cos(s, nb);
+                double* qs = ql_sin(s, nb);
                 // shift from the leading 2 x 2 of the unreduced block [l, m]
                 double g = (s.dd[l + 1] - s.dd[l]) / (2.0 * s.ee[l]);
                 double r = hypot(g, 1.0);
@@ -519,47 +603,29 @@ __device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz,
                     p = sn * r;
                     s.dd[i + 1] = g + p;
                     g = c * r - b;
-                    s.va[0][i] = c;
-                    s.wa[0][i] = sn;
+                    qc[i] = c;
+                    qs[i] = sn;
                 }
                 if (!early) {
                     s.dd[l] -= p;
                     s.ee[l] = g;
                     s.ee[m] = 0.0;
-                    s.ival[2] = l;
+                    s.qlo[nb] = l;
                 } else {
-                    s.ival[2] = i + 1;
+                    s.qlo[nb] = i + 1;
                 }
-                s.ival[3] = m - 1;
+                s.qhi[nb] = m - 1;
             }
             __syncthreads();
-            const int lo = s.ival[2], hi = s.ival[3];
-            // each row is independent; its elements are read in groups of 8
-            // before the dependent rotation chain runs over them
-            for (int row = t; row < n; row += BT) {
-                double* zr = Z + row;
-                double carry = zr[(int64_t)(hi + 1) * ldz];
-                int i = hi;
-                while (i >= lo) {
-                    const int cnt = min(8, i - lo + 1);
-                    double zc[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) zc[q] = (q < cnt) ? zr[(int64_t)(i - q) * ldz] : 0.0;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        if (q < cnt) {
-                            const double c = s.va[0][i - q], sn = s.wa[0][i - q];
-                            zr[(int64_t)(i - q + 1) * ldz] = sn * zc[q] + c * carry;
-                            carry = c * zc[q] - sn * carry;
-                        }
-                    }
-                    i -= cnt;
-                }
-                zr[(int64_t)lo * ldz] = carry;
+            if (++nb == QS) {
+                ql_apply(n, Z, ldz, nb, s);
+                nb = 0;
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
+    if (nb) ql_apply(n, Z, ldz, nb, s);
+    __syncthreads();
     return 0;
 }
 
