@@ -586,25 +586,35 @@ __device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz,
                 double sn = 1.0, c = 1.0, p = 0.0;
                 int i = m - 1;
                 bool early = false;
+                // the chain is latency bound: d and e of the next step are read
+                // ahead, and one square root and one reciprocal replace hypot and
+                // two divisions (|f|, |g| stay far from overflow for these pencils)
+                double ei = s.ee[i], di = s.dd[i], di1 = s.dd[i + 1];
                 for (; i >= l; --i) {
-                    const double f = sn * s.ee[i], b = c * s.ee[i];
-                    r = hypot(f, g);
+                    const double ein = (i > l) ? s.ee[i - 1] : 0.0;
+                    const double din = (i > l) ? s.dd[i - 1] : 0.0;
+                    const double f = sn * ei, b = c * ei;
+                    r = sqrt(f * f + g * g);
                     s.ee[i + 1] = r;
                     if (r == 0.0) {  // the block splits: restart on it
-                        s.dd[i + 1] -= p;
+                        s.dd[i + 1] = di1 - p;
                         s.ee[m] = 0.0;
                         early = true;
                         break;
                     }
-                    sn = f / r;
-                    c = g / r;
-                    g = s.dd[i + 1] - p;
-                    r = (s.dd[i] - g) * sn + 2.0 * c * b;
+                    const double inv = 1.0 / r;
+                    sn = f * inv;
+                    c = g * inv;
+                    g = di1 - p;
+                    r = (di - g) * sn + 2.0 * c * b;
                     p = sn * r;
                     s.dd[i + 1] = g + p;
                     g = c * r - b;
                     qc[i] = c;
                     qs[i] = sn;
+                    ei = ein;
+                    di1 = di;
+                    di = din;
                 }
                 if (!early) {
                     s.dd[l] -= p;
