@@ -54,6 +54,8 @@ def lib():
         L.or_grad.argtypes = [i64, P, P, P, i64, P, P, P, P, P]
         L.or_inertia_negative.argtypes = [i64, P]
         L.or_inertia_negative.restype = i64
+        L.or_inertia_negative_band.argtypes = [i64, i64, P]
+        L.or_inertia_negative_band.restype = i64
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -157,3 +159,25 @@ def inertia_count(K, M, sigma: float) -> int:
     if r < 0:
         raise ZeroDivisionError("zero pivot")
     return int(r)
+
+
+def inertia_count_banded(K, M, sigma: float) -> int:
+    """# of eigenvalues of K - theta M below sigma, for sparse K and M of any
+    size: reverse Cuthill-McKee ordering (a congruence, so the inertia is
+    unchanged), then the banded LDL^T count."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    A = sp.csr_matrix(K - sigma * M)
+    perm = reverse_cuthill_mckee(A, symmetric_mode=True)
+    A = A[perm][:, perm].tocoo()
+    n = A.shape[0]
+    low = A.row >= A.col
+    r, c, v = A.row[low], A.col[low], A.data[low]
+    bw = int((r - c).max()) if r.size else 0
+    AB = np.zeros((n, bw + 1), dtype=np.float64)   # row c holds column c of the band
+    AB[c, r - c] = v
+    AB = np.ascontiguousarray(AB)
+    res = lib().or_inertia_negative_band(n, bw, _p(AB))
+    if res < 0:
+        raise ZeroDivisionError("zero pivot")
+    return int(res)

@@ -520,3 +520,25 @@ int64_t or_inertia_negative(int64_t n, double *A) {
     }
     return neg;
 }
+
+/* The same count for a symmetric band matrix: AB holds the lower band,
+ * AB[(r - c) + c * (bw + 1)] = A(r, c) for 0 <= r - c <= bw (destroyed).
+ * LDL^T without pivoting keeps the band, so the cost is about n bw^2 / 2.
+ * Returns -1 on a zero pivot. */
+int64_t or_inertia_negative_band(int64_t n, int64_t bw, double *AB) {
+    const int64_t ld = bw + 1;
+    int64_t neg = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double d = AB[(size_t)j * ld];
+        if (d == 0.0) return -1;
+        if (d < 0.0) ++neg;
+        int64_t last = j + bw < n - 1 ? j + bw : n - 1;
+        for (int64_t c = j + 1; c <= last; ++c) {
+            double l = AB[(size_t)(c - j) + (size_t)j * ld] / d;
+            if (l == 0.0) continue;
+            for (int64_t r = c; r <= last; ++r)
+                AB[(size_t)(r - c) + (size_t)c * ld] -= l * AB[(size_t)(r - j) + (size_t)j * ld];
+        }
+    }
+    return neg;
+}

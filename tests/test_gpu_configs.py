@@ -1,0 +1,142 @@
+"""The named workloads at their full sizes (marker: gpu).
+
+Each runs in the configuration bench.py times and is checked against what
+the CPU side can compute independently at that size: the exact discrete Q1
+spectrum and the separable sine-transform solution on rectangles, and, for
+the P1 mesh (no closed form; the Jacobi oracle would take hours at n =
+16384), basis-free properties plus Sylvester inertia counts from the
+oracle's banded LDL^T at sampled shifts (index completeness).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.closed_form import Q1Rectangle
+from paper_1911_11906_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1911_11906_amd.api import Context
+    return Context(0)
+
+
+def orth_and_residual(op, th, V):
+    K, M = op.matrices()
+    MV = M @ V
+    G = V.T @ MV
+    G.diagonal().sub_(1.0)
+    orth = G.abs().max().item()
+    R = K @ V - MV * th[None, :]
+    res = (R.abs().max() / (th.max() * MV.abs().max())).item()
+    return orth, res, M
+
+
+def m_norm_rel(U, Uref, M):
+    D = U - Uref
+    num = torch.sqrt((D * (M @ D)).sum(0))
+    den = torch.sqrt((Uref * (M @ Uref)).sum(0))
+    return (num / den).max().item()
+
+
+def test_c2_fp64_q1_96(ctx):
+    """Q1 96 x 96 (n = 9216), FP64 path: every eigenvalue against the exact
+    discrete spectrum, V^T M V = I, and 64 cubic forcings x 16 orders
+    against the closed-form solution."""
+    from paper_1911_11906_amd.api import Operator
+    note("c2 n=9216 fp64")
+    mesh = inputs.q1_rectangle(96, 96)
+    op = Operator.assemble(ctx, mesh)
+    op.eigensolve("fp64")
+    th, V = op.eigenpairs()
+    cf = Q1Rectangle(96, 96)
+    ref = cf.eigenvalues()
+    # plain FP64 (no refinement): a normwise-stable solver sits near
+    # eps * cond = 2.5e-12 for the smallest eigenvalue at this n
+    assert np.max(np.abs(th.cpu().numpy() - ref) / ref) <= 2.5e-12
+    orth, res, M = orth_and_residual(op, th, V)
+    assert orth <= 1e-11 and res <= 1e-12
+    del V
+    F = inputs.polynomial_forcings(mesh, 64, tag=2)
+    al = inputs.alphas_uniform(16, tag=2)
+    U = op.apply(F, al)
+    Uref = torch.from_numpy(cf.apply(F, al)).to(ctx.device)
+    assert m_norm_rel(U, Uref, M) <= 1e-10
+
+
+def test_c4_apply_n16384_mixed(ctx):
+    """Q1 128 x 128 (n = 16384), mixed-precision eigensolve, then the full
+    1024 x 32 application exactly as bench.py launches it; every eigenvalue
+    against the exact spectrum and 96 sampled solutions against the
+    closed-form transform."""
+    from paper_1911_11906_amd.api import Operator, colmajor, empty_colmajor
+    note("c4 apply n=16384 mixed")
+    mesh = inputs.q1_rectangle(128, 128)
+    n = mesh.n_dof
+    op = Operator.assemble(ctx, mesh)
+    info = op.eigensolve("mixed")
+    assert info["refine_iters"] == 1
+    th, _ = op.eigenpairs(want_vectors=False)
+    cf = Q1Rectangle(128, 128)
+    ref = cf.eigenvalues()
+    assert np.max(np.abs(th.cpu().numpy() - ref) / ref) <= 1e-12
+    nf, na = 1024, 32
+    Fh = inputs.polynomial_forcings(mesh, nf, tag=4)
+    al = inputs.alphas_uniform(na, tag=4)
+    F = colmajor(Fh, ctx.device)
+    U = empty_colmajor(n, nf * na, ctx.device)
+    op.apply(F, al, out=U)
+    torch.cuda.synchronize()
+    _, M = op.matrices()
+    rng = np.random.default_rng(44)
+    cols = rng.choice(nf * na, 96, replace=False)
+    for i in np.unique(cols // nf):
+        js = cols[cols // nf == i] % nf
+        Uref = torch.from_numpy(cf.apply(Fh[:, js], [al[i]])).to(ctx.device)
+        assert m_norm_rel(U[:, i * nf + js], Uref, M) <= 1e-10
+
+
+def test_c3_p1_mixed_and_fp64(ctx, oracle_mod):
+    """P1 on the seeded polygon with two holes (n = 16384): mixed and FP64
+    eigensolves.  V^T M V = I and residuals for the mixed basis; the two
+    spectra agree; Sylvester inertia counts of the oracle's banded LDL^T at
+    6 shifts between consecutive eigenvalues equal the index."""
+    import scipy.sparse as sp
+    from paper_1911_11906_amd.api import Operator
+    note("c3 P1 n=16384")
+    mesh = inputs.p1_polygon_with_holes(16384)
+    op = Operator.assemble(ctx, mesh)
+    assert op.n == 16384
+    op.eigensolve("fp64")
+    th64, _ = op.eigenpairs(want_vectors=False)
+    th64 = th64.cpu().numpy()
+    info = op.eigensolve("mixed")
+    assert info["refine_iters"] == 1
+    th, V = op.eigenpairs()
+    orth, res, M = orth_and_residual(op, th, V)
+    assert orth <= 1e-11 and res <= 1e-12
+    th = th.cpu().numpy()
+    assert np.all(np.diff(th) >= 0)
+    assert np.max(np.abs(th - th64) / th64) <= 1e-11
+    del V, M
+    torch.cuda.empty_cache()
+    K, Mh = oracle_mod.assemble(mesh)
+    Ks, Ms = sp.csr_matrix(K), sp.csr_matrix(Mh)
+    del K, Mh
+    rng = np.random.default_rng(33)
+    picked = 0
+    for k in rng.permutation(np.arange(1, th.size - 1)):
+        if th[k + 1] - th[k] <= 1e-6 * th[k + 1]:
+            continue
+        sigma = 0.5 * (th[k] + th[k + 1])
+        assert oracle_mod.inertia_count_banded(Ks, Ms, sigma) == k + 1
+        picked += 1
+        if picked == 6:
+            break
+    assert picked == 6

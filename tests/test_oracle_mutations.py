@@ -36,6 +36,7 @@ MUTANTS = {
     "grad_log_weight": ("ga += sp * sc * w * (-0.5 * log(theta[k]));", "ga += sp * sc * w * (-log(theta[k]));"),
     "grad_mass_dropped": ("for (int64_t q = 0; q < n; ++q) s += M[IDX(r, q, n)] * y[q];",
                           "for (int64_t q = 0; q < n; ++q) s += (r == q) * y[q];"),
+    "band_ldl_index": ("-= l * AB[(size_t)(r - j) + (size_t)j * ld];", "-= l * AB[(size_t)(c - j) + (size_t)j * ld];"),
 }
 
 
@@ -112,6 +113,12 @@ def failing_pins():
             D = np.random.default_rng(0).standard_normal(F.shape)
             fd = (loss(F + hh * D, al) - loss(F - hh * D, al)) / (2 * hh)
             check("grad_f_fd", abs(np.sum(GF * D) - fd) < 1e-6 * max(1.0, abs(fd)))
+            # Sylvester counts of the banded LDL^T against LAPACK
+            ok = True
+            for k in (5, 40, 90):
+                sig = 0.5 * (w[k] + w[k + 1])
+                ok = ok and oracle.inertia_count_banded(Kr, Mr, sig) == k + 1
+            check("band_inertia", ok)
         except Exception as e:  # a mutant may also break the pipeline outright
             bad.append(f"raised:{type(e).__name__}")
     return bad

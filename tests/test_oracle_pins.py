@@ -144,6 +144,25 @@ def test_inertia_counts_index_completeness(oracle_mod):
         assert oracle_mod.inertia_count(K, M, sigma) == k + 1
 
 
+@pytest.mark.parametrize("which", ["p1", "lshape"])
+def test_banded_inertia_matches_dense_and_lapack(oracle_mod, which):
+    """The banded count (reverse Cuthill-McKee, banded LDL^T) equals the dense
+    count and the number of LAPACK eigenvalues below sigma."""
+    import scipy.linalg
+    m = inputs.p1_polygon_with_holes(260, seed=5) if which == "p1" else inputs.q1_lshape(7)
+    K, M = oracle_mod.assemble(m)
+    w = scipy.linalg.eigh(K, M, eigvals_only=True)
+    rng = np.random.default_rng(1)
+    for k in sorted(rng.choice(w.size - 1, 6, replace=False)):
+        if w[k + 1] - w[k] < 1e-8 * w[k + 1]:
+            continue
+        sigma = 0.5 * (w[k] + w[k + 1])
+        nb = oracle_mod.inertia_count_banded(K, M, sigma)
+        assert nb == oracle_mod.inertia_count(K, M, sigma) == k + 1
+    assert oracle_mod.inertia_count_banded(K, M, 0.5 * w[0]) == 0
+    assert oracle_mod.inertia_count_banded(K, M, 2.0 * w[-1]) == w.size
+
+
 def test_jacobi_on_a_textbook_matrix(oracle_mod):
     """Tridiagonal (2,-1) of size m has eigenvalues 2 - 2 cos(j pi/(m+1))."""
     mm = 31
