@@ -6,7 +6,7 @@ resident in HBM:
     128 x 128 interior-node unit-square grid (n = 16384): Cholesky, standard
     form, band reduction, bulge chasing, divide and conquer, both
     back-transforms, V = L^-T Z, and in mixed mode (the default) FP32
-    back-transforms followed by one FP64 refinement step;
+    back-transforms followed by two FP64 refinement steps;
   * the fractional solutions v(alpha_i, f_j) for 1024 seeded random cubic
     polynomial forcings x 32 orders alpha ~ U(0, 2) (32768 solutions);
   * the batched FP64 eigensolve of 256 seeded Q1 rectangles / L-shapes with

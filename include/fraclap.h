@@ -71,7 +71,7 @@ enum {
 typedef struct fl_eig_opts {
     int32_t band;             /* band width of the two-stage reduction (0 = default 64) */
     int32_t leaf;             /* divide-and-conquer leaf size (0 = default 32) */
-    int32_t refine_max_iters; /* refinement steps (-1 = default: 0 in FP64 mode; in mixed mode 1,
+    int32_t refine_max_iters; /* refinement steps (-1 = default: 0 in FP64 mode; in mixed mode 2,
                                  or 3 with FL_MIXED_FP32_BAND) */
     double refine_tol;        /* stop refining when max |(I - V^T M V)_ij| is below this
                                  (0 = default 1e-13) */

@@ -284,11 +284,14 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     }
     FL_HIP(ctx, tm.mark(FL_STAGE_TRSM));
     FL_HIP(ctx, fl_trsm_llt(s, n, n, L, ld, blinv.as<double>(), op->V, ld, bwork.as<double>()));
-    // refinement: by default one step after FP32 back-transforms, three after
-    // an FP32 band reduction (early exit at tol), none in FP64 mode
+    // refinement: by default two steps after FP32 back-transforms (the first
+    // meets the eigenvalue and orthonormality targets; the second removes the
+    // second-order error between close low modes, which dominates the
+    // fractional solutions), three after an FP32 band reduction (early exit
+    // at tol), none in FP64 mode
     const bool fp32_band = opts && (opts->mixed_flags & FL_MIXED_FP32_BAND);
     int iters = (opts && opts->refine_max_iters >= 0) ? opts->refine_max_iters
-                                                      : (precision == FL_MIXED ? (fp32_band ? 3 : 1) : 0);
+                                                      : (precision == FL_MIXED ? (fp32_band ? 3 : 2) : 0);
     double tol = (opts && opts->refine_tol > 0.0) ? opts->refine_tol : 1e-13;
     if (iters > 0) {
         FL_HIP(ctx, hipStreamSynchronize(s));  // the TRSM above still reads L
