@@ -20,7 +20,7 @@
 
 namespace {
 
-constexpr int BMAX = 64;
+constexpr int BMAX = 64;  // (index arithmetic below uses BMAX = 64 = 1 << 6)
 constexpr int LDB = BMAX + 1;
 constexpr int NTH = 256;
 
@@ -36,8 +36,8 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                                                     double* tau2, int64_t maxt, int* prog, int* abort) {
     __shared__ double bufA[BMAX * LDB], bufB[BMAX * LDB];  // off-diagonal / below blocks (rotate roles)
     __shared__ double S[BMAX * LDB];                        // symmetric diagonal block (full)
-    __shared__ double vv[BMAX], pv[BMAX], wv[BMAX];
-    __shared__ double red[4][BMAX];
+    __shared__ double vv[BMAX], pv[BMAX], wv[BMAX], pb[BMAX];
+    __shared__ double red[4][BMAX], redS[4][BMAX], redB[4][BMAX];
     __shared__ double sc[4];
     __shared__ int quit;
     const int t = threadIdx.x;
@@ -73,125 +73,104 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
             const int64_t q0 = r0 + L;
             const int Lb = (int)(q0 < n ? ((n - q0) < b ? (n - q0) : b) : 0);  // rows of R_{j+1}
             const int64_t c0 = r0 - b;                                   // first column of R_{j-1}
-            // ---- load: x (j == 0: column i), S = A[R_j, R_j], Bbl = A[R_{j+1}, R_j]
-            if (j == 0) {
-                for (int r = t; r < L; r += NTH) Boff[r] = band_get(AB, ldab, r0 + r, i);
-            }
-            for (int e = t; e < L * L; e += NTH) {
-                int r = e % L, c = e / L;
-                if (r >= c) {
-                    double v = band_get(AB, ldab, r0 + r, r0 + c);
-                    S[r + c * LDB] = v;
-                    S[c + r * LDB] = v;
+            // ---- load: x (j == 0: column i), S = A[R_j, R_j], Bbl = A[R_{j+1}, R_j].
+            // All global loads of the task are issued into registers before any
+            // LDS store, so their latencies overlap instead of adding up.
+            {
+                constexpr int PER = (BMAX * BMAX + NTH - 1) / NTH;  // elements per thread per block
+                double sv[PER], bv[PER];
+                double xv = 0.0;
+                if (j == 0 && t < L) xv = band_get(AB, ldab, r0 + t, i);
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = t + q * NTH;
+                    const int r = e % BMAX, c = e / BMAX;
+                    sv[q] = (r < L && c < L && r >= c) ? band_get(AB, ldab, r0 + r, r0 + c) : 0.0;
+                    bv[q] = (r < Lb && c < L) ? band_get(AB, ldab, q0 + r, r0 + c) : 0.0;
+                }
+                if (j == 0 && t < L) Boff[t] = xv;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = t + q * NTH;
+                    const int r = e % BMAX, c = e / BMAX;
+                    if (r < L && c < L && r >= c) {
+                        S[r + c * LDB] = sv[q];
+                        S[c + r * LDB] = sv[q];
+                    }
+                    if (r < Lb && c < L) Bbl[r + c * LDB] = bv[q];
                 }
             }
-            for (int e = t; e < Lb * L; e += NTH) {
-                int r = e % Lb, c = e / Lb;
-                Bbl[r + c * LDB] = band_get(AB, ldab, q0 + r, r0 + c);
-            }
             __syncthreads();
-            // ---- Householder of x = Boff[:, 0] (length L)
+            // ---- Householder of x = Boff[:, 0] (length L), by wave 0, which
+            // also writes v and replaces x by (beta, 0, ..., 0)
             if (t < 64) {
-                double s2 = 0.0;
-                for (int r = 1 + t; r < L; r += 64) s2 += Boff[r] * Boff[r];
-                for (int off = 32; off > 0; off >>= 1) s2 += __shfl_down(s2, off, 64);
-                if (t == 0) {
-                    double x0 = Boff[0];
-                    double beta, tauc, scale;
-                    if (s2 == 0.0 || L < 2) {
-                        beta = x0;
-                        tauc = 0.0;
-                        scale = 0.0;
-                    } else {
-                        double nrm = sqrt(x0 * x0 + s2);
-                        beta = (x0 >= 0.0) ? -nrm : nrm;
-                        tauc = (beta - x0) / beta;
-                        scale = 1.0 / (x0 - beta);
-                    }
-                    sc[0] = scale;
-                    sc[1] = tauc;
-                    sc[2] = beta;
+                const double xr = (t < L) ? Boff[t] : 0.0;
+                double s2 = (t >= 1) ? xr * xr : 0.0;
+                for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+                const double x0 = __shfl(xr, 0, 64);
+                double beta, tauc, scale;
+                if (s2 == 0.0 || L < 2) {
+                    beta = x0;
+                    tauc = 0.0;
+                    scale = 0.0;
+                } else {
+                    const double nrm = sqrt(x0 * x0 + s2);
+                    beta = (x0 >= 0.0) ? -nrm : nrm;
+                    tauc = (beta - x0) / beta;
+                    scale = 1.0 / (x0 - beta);
                 }
+                vv[t] = (t == 0) ? 1.0 : (t < L ? xr * scale : 0.0);
+                if (t < L) Boff[t] = (t == 0) ? beta : 0.0;
+                if (t == 0) sc[1] = tauc;
             }
             __syncthreads();
-            const double scale = sc[0], tauc = sc[1], beta = sc[2];
-            for (int r = t; r < BMAX; r += NTH) vv[r] = (r == 0) ? 1.0 : (r < L ? Boff[r] * scale : 0.0);
-            __syncthreads();
-            if (t == 0) Boff[0] = beta;
-            for (int r = 1 + t; r < L; r += NTH) Boff[r] = 0.0;
-            // ---- left-apply to the remaining columns of the off-diagonal block (j >= 1)
-            if (j > 0 && tauc != 0.0) {
-                // w_c = v^T Boff[:, c], c = 1..b-1 ; thread (grp, col)
-                const int col = t & 63, grp = t >> 6;
-                double s = 0.0;
-                if (col >= 1 && col < b)
-                    for (int r = grp; r < L; r += 4) s += vv[r] * Boff[r + col * LDB];
-                red[grp][col] = s;
-                __syncthreads();
-                if (t < 64) wv[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-                __syncthreads();
-                for (int e = t; e < L * b; e += NTH) {
-                    int r = e % L, c = e / L;
-                    if (c >= 1) Boff[r + c * LDB] -= tauc * vv[r] * wv[c];
-                }
-            }
-            __syncthreads();
-            // ---- two-sided update of S: p = tau S v, w = p - (tau/2)(v^T p) v, S -= v w^T + w v^T
+            const double tauc = sc[1];
             if (tauc != 0.0) {
-                const int row = t & 63, grp = t >> 6;
-                double s = 0.0;
-                if (row < L)
-                    for (int c = grp; c < L; c += 4) s += S[row + c * LDB] * vv[c];
-                red[grp][row] = s;
-                __syncthreads();
-                if (t < 64) pv[t] = (t < L) ? tauc * (red[0][t] + red[1][t] + red[2][t] + red[3][t]) : 0.0;
-                __syncthreads();
-                if (t < 64) {
-                    double a = (t < L) ? vv[t] * pv[t] : 0.0;
-                    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
-                    if (t == 0) sc[3] = 0.5 * tauc * a;
-                }
-                __syncthreads();
-                const double al = sc[3];
-                if (t < 64) wv[t] = pv[t] - al * vv[t];
-                __syncthreads();
-                for (int e = t; e < L * L; e += NTH) {
-                    int r = e % L, c = e / L;
-                    S[r + c * LDB] -= vv[r] * wv[c] + wv[r] * vv[c];
-                }
-                // ---- right-apply to the block below: Bbl -= tau (Bbl v) v^T
+                // ---- the three products with v, one phase (4 row groups x 64 lanes):
+                // left  wv_c = v^T Boff[:, c] (c >= 1, j >= 1)
+                // sym   pv = S v
+                // right pb = Bbl v
+                const int lane = t & 63, grp = t >> 6;
                 {
-                    double y = 0.0;
-                    const int rr = t & 63;
-                    if (rr < Lb)
-                        for (int c = grp; c < L; c += 4) y += Bbl[rr + c * LDB] * vv[c];
-                    red[grp][rr] = y;
-                    __syncthreads();
-                    if (t < 64) pv[t] = tauc * (red[0][t] + red[1][t] + red[2][t] + red[3][t]);
-                    __syncthreads();
-                    for (int e = t; e < Lb * L; e += NTH) {
-                        int r = e % Lb, c = e / Lb;
-                        Bbl[r + c * LDB] -= pv[r] * vv[c];
-                    }
+                    double sl = 0.0, ss = 0.0, sb = 0.0;
+                    if (j > 0 && lane >= 1 && lane < b)
+                        for (int r = grp; r < L; r += 4) sl += vv[r] * Boff[r + lane * LDB];
+                    if (lane < L)
+                        for (int c = grp; c < L; c += 4) ss += S[lane + c * LDB] * vv[c];
+                    if (lane < Lb)
+                        for (int c = grp; c < L; c += 4) sb += Bbl[lane + c * LDB] * vv[c];
+                    red[grp][lane] = sl;
+                    redS[grp][lane] = ss;
+                    redB[grp][lane] = sb;
+                }
+                __syncthreads();
+                // ---- combine (wave 0): wv, w = p - (tau/2)(v^T p) v with p = tau S v, pb
+                if (t < 64) {
+                    wv[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+                    const double p = (t < L) ? tauc * (redS[0][t] + redS[1][t] + redS[2][t] + redS[3][t]) : 0.0;
+                    double a = vv[t] * p;
+                    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+                    pv[t] = p - 0.5 * tauc * a * vv[t];
+                    pb[t] = tauc * (redB[0][t] + redB[1][t] + redB[2][t] + redB[3][t]);
+                }
+                __syncthreads();
+                // ---- the three updates
+                // (r, c) = (e mod 64, e / 64): power-of-two indexing, no runtime divisions
+                for (int e = t; e < BMAX * BMAX; e += NTH) {
+                    const int r = e & (BMAX - 1), c = e >> 6;
+                    if (j > 0 && r < L && c >= 1 && c < b) Boff[r + c * LDB] -= tauc * vv[r] * wv[c];
+                    if (r < L && c < L) S[r + c * LDB] -= vv[r] * pv[c] + pv[r] * vv[c];
+                    if (r < Lb && c < L) Bbl[r + c * LDB] -= pb[r] * vv[c];
                 }
             }
             __syncthreads();
             // ---- write back
-            if (j == 0) {
-                for (int r = t; r < L; r += NTH) AB[(r0 + r - i) + i * ldab] = Boff[r];
-            } else {
-                for (int e = t; e < L * b; e += NTH) {
-                    int r = e % L, c = e / L;
-                    AB[(r0 + r - (c0 + c)) + (c0 + c) * ldab] = Boff[r + c * LDB];
-                }
-            }
-            for (int e = t; e < L * L; e += NTH) {
-                int r = e % L, c = e / L;
-                if (r >= c) AB[(r - c) + (r0 + c) * ldab] = S[r + c * LDB];
-            }
-            for (int e = t; e < Lb * L; e += NTH) {
-                int r = e % Lb, c = e / Lb;
-                AB[(q0 + r - (r0 + c)) + (r0 + c) * ldab] = Bbl[r + c * LDB];
+            if (j == 0 && t < L) AB[(r0 + t - i) + i * ldab] = Boff[t];
+            for (int e = t; e < BMAX * BMAX; e += NTH) {
+                const int r = e & (BMAX - 1), c = e >> 6;
+                if (j > 0 && r < L && c < b) AB[(r0 + r - (c0 + c)) + (c0 + c) * ldab] = Boff[r + c * LDB];
+                if (r < L && c < L && r >= c) AB[(r - c) + (r0 + c) * ldab] = S[r + c * LDB];
+                if (r < Lb && c < L) AB[(q0 + r - (r0 + c)) + (r0 + c) * ldab] = Bbl[r + c * LDB];
             }
             double* vout = V2 + (i * maxt + j) * (int64_t)b;
             for (int r = t; r < b; r += NTH) vout[r] = (r < L) ? vv[r] : 0.0;
