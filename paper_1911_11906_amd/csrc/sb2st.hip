@@ -22,7 +22,7 @@ namespace {
 
 constexpr int BMAX = 64;  // (index arithmetic below uses BMAX = 64 = 1 << 6)
 constexpr int LDB = BMAX + 1;
-constexpr int NTH = 256;
+constexpr int NTH = 512;
 
 __device__ inline int64_t ntasks(int64_t n, int b, int64_t i) { return 1 + (n - 3 - i) / b; }
 
@@ -37,7 +37,8 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
     __shared__ double bufA[BMAX * LDB], bufB[BMAX * LDB];  // off-diagonal / below blocks (rotate roles)
     __shared__ double S[BMAX * LDB];                        // symmetric diagonal block (full)
     __shared__ double vv[BMAX], pv[BMAX], wv[BMAX], pb[BMAX];
-    __shared__ double red[4][BMAX], redS[4][BMAX], redB[4][BMAX];
+    constexpr int NG = NTH / 64;  // row groups of the products
+    __shared__ double red[NG][BMAX], redS[NG][BMAX], redB[NG][BMAX];
     __shared__ double sc[4];
     __shared__ int quit;
     const int t = threadIdx.x;
@@ -134,11 +135,11 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                 {
                     double sl = 0.0, ss = 0.0, sb = 0.0;
                     if (j > 0 && lane >= 1 && lane < b)
-                        for (int r = grp; r < L; r += 4) sl += vv[r] * Boff[r + lane * LDB];
+                        for (int r = grp; r < L; r += NG) sl += vv[r] * Boff[r + lane * LDB];
                     if (lane < L)
-                        for (int c = grp; c < L; c += 4) ss += S[lane + c * LDB] * vv[c];
+                        for (int c = grp; c < L; c += NG) ss += S[lane + c * LDB] * vv[c];
                     if (lane < Lb)
-                        for (int c = grp; c < L; c += 4) sb += Bbl[lane + c * LDB] * vv[c];
+                        for (int c = grp; c < L; c += NG) sb += Bbl[lane + c * LDB] * vv[c];
                     red[grp][lane] = sl;
                     redS[grp][lane] = ss;
                     redB[grp][lane] = sb;
@@ -146,12 +147,19 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                 __syncthreads();
                 // ---- combine (wave 0): wv, w = p - (tau/2)(v^T p) v with p = tau S v, pb
                 if (t < 64) {
-                    wv[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-                    const double p = (t < L) ? tauc * (redS[0][t] + redS[1][t] + redS[2][t] + redS[3][t]) : 0.0;
+                    double sl = 0.0, ss = 0.0, sb = 0.0;
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        sl += red[g][t];
+                        ss += redS[g][t];
+                        sb += redB[g][t];
+                    }
+                    wv[t] = sl;
+                    const double p = (t < L) ? tauc * ss : 0.0;
                     double a = vv[t] * p;
                     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
                     pv[t] = p - 0.5 * tauc * a * vv[t];
-                    pb[t] = tauc * (redB[0][t] + redB[1][t] + redB[2][t] + redB[3][t]);
+                    pb[t] = tauc * sb;
                 }
                 __syncthreads();
                 // ---- the three updates
