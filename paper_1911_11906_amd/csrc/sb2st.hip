@@ -22,7 +22,7 @@ namespace {
 
 constexpr int BMAX = 64;  // (index arithmetic below uses BMAX = 64 = 1 << 6)
 constexpr int LDB = BMAX + 1;
-constexpr int NTH = 512;
+constexpr int NTH = 1024;
 
 __device__ inline int64_t ntasks(int64_t n, int b, int64_t i) { return 1 + (n - 3 - i) / b; }
 
