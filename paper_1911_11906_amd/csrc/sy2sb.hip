@@ -89,8 +89,10 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         }
         __syncthreads();
         if (t < 64) part[(size_t)par * G * 64 + (size_t)blockIdx.x * 64 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-        // (all threads) release the partials, then wait for every workgroup
-        __threadfence();
+        // every wave waits for its own stores (partials, published row); the
+        // barrier's single agent-scope release then writes the L2 back once
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);
         if (!grid_barrier(counter, (unsigned)(c + 1) * G, abort)) return;
         // reduce the partials of all workgroups (fixed order)
         if (t < 64) {
