@@ -202,6 +202,259 @@ __global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t
     }
 }
 
+// ---- band width 64: one launch, Z windows resident in registers ----------
+//
+// Block (g, j) is viewed in a 128-row frame starting at row g + 64 j (one row
+// above its first reflector row), so that consecutive blocks of a group move
+// by exactly half a frame and every frame starts on a 64-row boundary.  In
+// frame coordinates reflector s has its entries at rows s+1 .. s+64, so V is
+// nonzero only on 16 x 16 tile pairs (frame tile rt, reflector tile wt) with
+// wt <= rt <= wt + 4, and T is upper triangular; products over the other
+// tile pairs are skipped.
+//
+// A workgroup owns 64 columns of Z, a wave 16 of them.  Each wave holds the
+// current 128 x 16 window of its columns in MFMA accumulator registers:
+// lane (lr, lc), register r of frame tile rt is row 16 rt + 4 lr + r of
+// column lc.  That layout is at the same time the B-operand layout of
+// W = V^T Z (any order of the reduction index is allowed, and V is read from
+// LDS to match it) and, up to a permutation inside each 16-row tile, the
+// output layout of Z -= V (T W).  After a block the upper half of the window
+// is final for the group and goes to memory; the lower half becomes the
+// upper half of the next block.  V of the next block (read straight from
+// the bulge-chasing output) and its T factor are fetched into registers
+// while the current block computes.
+constexpr int FB = 64;       // band width of this path
+constexpr int FR = 2 * FB;   // frame rows
+constexpr int LDF = FB + 4;  // LDS stride of the V frame (spreads banks for both read patterns)
+
+__host__ __device__ inline int64_t q2_block_base(int64_t gi, int64_t n0) { return gi * n0 - gi * (gi - 1) / 2; }
+
+// Frame-row offset, inside a 16-row tile, of MFMA output index p when lane
+// (lr, lc) register r holds row 4 lr + r.
+template <class T> __device__ inline int q2_sigma(int p);
+template <> __device__ inline int q2_sigma<double>(int p) { return 4 * (p & 3) + (p >> 2); }  // p = lr + 4 r
+template <> __device__ inline int q2_sigma<float>(int p) { return p; }                        // p = 4 lr + r
+
+// Forward T factor of every block (g = 64 gi, j): T upper triangular with
+// H(g, j) ... H(g+63, j) = I - V T V^T.  T[t][jj] = -tau_jj sum_k T[t][k] G[k][jj]
+// over t <= k < jj, with G = V^T V.  Output column-major 64 x 64 per block,
+// blocks of group gi from q2_block_base(gi, n0).
+template <class OT>
+__global__ __launch_bounds__(256) void q2_tfactor_kernel(int64_t n, int64_t maxt, int64_t n0,
+                                                         const double* __restrict__ V2,
+                                                         const double* __restrict__ tau2, OT* __restrict__ TB) {
+    const int64_t gi = blockIdx.y, j = blockIdx.x;
+    if (j >= n0 - gi) return;
+    constexpr int LC = FB + 1;
+    __shared__ double Vc[FB * LC];  // Vc[s*LC + i]: entry i of reflector s
+    __shared__ double Gs[FB * LC];  // Gs[k + jj*LC] = G[k][jj], k < jj
+    __shared__ double tv[FB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t g = gi * FB, nsw = n - 2;
+    for (int s = wave; s < FB; s += 4) {
+        const int64_t sw = g + s;
+        const bool ex = sw < nsw && j < 1 + (n - 3 - sw) / FB;
+        const int64_t r0 = g + 1 + j * FB + s;
+        const int L = ex ? (int)((n - r0) < FB ? (n - r0) : FB) : 0;
+        Vc[s * LC + lane] = lane < L ? V2[(sw * maxt + j) * FB + lane] : 0.0;
+        if (lane == 0) tv[s] = ex ? tau2[sw * maxt + j] : 0.0;
+    }
+    __syncthreads();
+    // G[k][jj] (k < jj): rows s.t. both reflectors are nonzero; thread -> (jj, k mod 4)
+    {
+        const int jj = lane, q = wave;
+        for (int k = q; k < FB - 1; k += 4) {
+            if (k < jj) {
+                const int d = jj - k, len = FB - d;
+                double acc = 0.0;
+                for (int i = 0; i < len; ++i) acc += Vc[k * LC + i + d] * Vc[jj * LC + i];
+                Gs[k + jj * LC] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double Tr[FB];  // row t of T
+#pragma unroll
+    for (int k = 0; k < FB; ++k) Tr[k] = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < FB; ++jj) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < jj; ++k) acc += Tr[k] * Gs[k + jj * LC];  // Tr[k] = 0 for k < t
+        const double tau = tv[jj];
+        Tr[jj] = lane < jj ? -tau * acc : (lane == jj ? tau : 0.0);
+    }
+    OT* out = TB + (q2_block_base(gi, n0) + j) * (int64_t)(FB * FB);
+#pragma unroll
+    for (int k = 0; k < FB; ++k) out[lane + k * FB] = (OT)Tr[k];
+}
+
+template <class T, bool VEC>
+__device__ inline void q2_load4(const T* zc, int64_t row0, int64_t n, bool cok, typename fl_tile::Mfma<T>::acc& a) {
+    if (VEC && cok && row0 + 3 < n) {
+        if constexpr (sizeof(T) == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(zc + row0);
+            a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+        } else {
+            const double2 v0 = *reinterpret_cast<const double2*>(zc + row0);
+            const double2 v1 = *reinterpret_cast<const double2*>(zc + row0 + 2);
+            a[0] = v0.x; a[1] = v0.y; a[2] = v1.x; a[3] = v1.y;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = (cok && row0 + r < n) ? zc[row0 + r] : T(0);
+    }
+}
+
+template <class T, bool VEC>
+__device__ inline void q2_store4(T* zc, int64_t row0, int64_t n, bool cok, const typename fl_tile::Mfma<T>::acc& a) {
+    if (!cok) return;
+    if (VEC && row0 + 3 < n) {
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(zc + row0) = make_float4(a[0], a[1], a[2], a[3]);
+        } else {
+            *reinterpret_cast<double2*>(zc + row0) = make_double2(a[0], a[1]);
+            *reinterpret_cast<double2*>(zc + row0 + 2) = make_double2(a[2], a[3]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (row0 + r < n) zc[row0 + r] = a[r];
+    }
+}
+
+template <class T, bool VEC>
+__global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t maxt, int64_t n0,
+                                                         const double* __restrict__ V2, const T* __restrict__ TB,
+                                                         T* __restrict__ Z, int64_t ldz, int64_t ncols) {
+    typedef fl_tile::Mfma<T> MM;
+    typedef typename MM::acc acc_t;
+    __shared__ __attribute__((aligned(16))) T Vf[FR * LDF];  // Vf[k*LDF + s] = V[k][s], frame row k
+    __shared__ __attribute__((aligned(16))) T Ts[FB * FB];   // Ts[i + k*FB] = T[i][k]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int lr = lane >> 4, lc = lane & 15;
+    const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + lc;
+    const bool cok = col < ncols;
+    T* zc = Z + (cok ? col : 0) * ldz;
+    const int64_t nsw = n - 2;
+    for (int e = t; e < FR * LDF; e += 256) Vf[e] = T(0);  // off-staircase entries stay zero
+
+    T pv[16], pt[16];
+    // block (g, j): reflector s = wave + 4 q, entry i = lane -> frame row s + 1 + i
+    auto fetch = [&](int64_t gi, int64_t j) {
+        const int64_t g = gi * FB;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int s = wave + 4 * q;
+            const int64_t sw = g + s;
+            const bool ex = sw < nsw && j < 1 + (n - 3 - sw) / FB;
+            const int64_t r0 = g + 1 + j * FB + s;
+            const int64_t L = ex ? ((n - r0) < FB ? (n - r0) : FB) : 0;
+            pv[q] = lane < L ? (T)V2[(sw * maxt + j) * FB + lane] : T(0);
+        }
+        const T* tb = TB + (q2_block_base(gi, n0) + j) * (int64_t)(FB * FB);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) pt[q] = tb[t + 256 * q];
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int s = wave + 4 * q;
+            Vf[(s + 1 + lane) * LDF + s] = pv[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Ts[t + 256 * q] = pt[q];
+    };
+
+    acc_t zt[4], zb[4], zn[4], w[4], w2[4];
+    const int lrow = 4 * lr;
+    const int vsig = q2_sigma<T>(lc);
+    for (int64_t gi = n0 - 1; gi >= 0; --gi) {
+        const int64_t g = gi * FB, nt = n0 - gi;
+        fetch(gi, 0);
+        __syncthreads();  // the previous group's last block is done with the LDS
+        stage();
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            q2_load4<T, VEC>(zc, g + 16 * rt + lrow, n, cok, zt[rt]);
+            q2_load4<T, VEC>(zc, g + FB + 16 * rt + lrow, n, cok, zb[rt]);
+        }
+        __syncthreads();
+        for (int64_t j = 0; j < nt; ++j) {
+            const int64_t F = g + j * FB;
+            const bool more = j + 1 < nt;
+            if (more) {
+                fetch(gi, j + 1);
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) q2_load4<T, VEC>(zc, F + 2 * FB + 16 * rt + lrow, n, cok, zn[rt]);
+            }
+            // W = V^T Z over tile pairs wt <= rt <= wt + 4
+#pragma unroll
+            for (int wt = 0; wt < 4; ++wt) w[wt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < 5; ++d)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int wt = 0; wt < 4; ++wt) {
+                        const int rt = wt + d;
+                        const T a = Vf[(16 * rt + lrow + r) * LDF + 16 * wt + lc];
+                        const T bz = rt < 4 ? zt[rt & 3][r] : zb[rt & 3][r];
+                        w[wt] = MM::mma(a, bz, w[wt]);
+                    }
+            // W2 = T W (T upper triangular)
+#pragma unroll
+            for (int wt = 0; wt < 4; ++wt) w2[wt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int wt2 = 0; wt2 < 4; ++wt2) {
+                        const int wt = wt2 + d;
+                        if (wt < 4) {
+                            const T a = Ts[(16 * wt2 + lc) + (16 * wt + MM::row(lr, r)) * FB];
+                            w2[wt2] = MM::mma(a, w[wt][r], w2[wt2]);
+                        }
+                    }
+#pragma unroll
+            for (int wt = 0; wt < 4; ++wt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w2[wt][r] = -w2[wt][r];
+            // Z -= V W2
+#pragma unroll
+            for (int d = 0; d < 5; ++d)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int wt = 0; wt < 4; ++wt) {
+                        const int rt = wt + d;
+                        const T a = Vf[(16 * rt + vsig) * LDF + 16 * wt + MM::row(lr, r)];
+                        if (rt < 4)
+                            zt[rt & 3] = MM::mma(a, w2[wt][r], zt[rt & 3]);
+                        else
+                            zb[rt & 3] = MM::mma(a, w2[wt][r], zb[rt & 3]);
+                    }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC>(zc, F + 16 * rt + lrow, n, cok, zt[rt]);
+            if (more) {
+                __syncthreads();  // every wave is done with this block's V and T
+                stage();
+                __syncthreads();
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    zt[rt] = zb[rt];
+                    zb[rt] = zn[rt];
+                }
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC>(zc, F + FB + 16 * rt + lrow, n, cok, zb[rt]);
+            }
+        }
+    }
+}
+
 }  // namespace
 int64_t fl_sy2sb_panels(int64_t n, int b);
 namespace {
@@ -212,6 +465,20 @@ hipError_t q2_apply_t(hipStream_t s, int64_t n, int b, const double* V2, const d
     static_assert((VBLK * sizeof(float)) % 16 == 0 && (TBLK * sizeof(float)) % 16 == 0, "16-byte blocks");
     if (n < 3 || b < 2) return hipSuccess;
     const int64_t nsw = n - 2;
+    if (b == FB) {
+        const int64_t n0 = 1 + (n - 3) / FB;  // groups, and tasks of the first sweep of group 0
+        q2_tfactor_kernel<T><<<dim3((unsigned)n0, (unsigned)n0), 256, 0, s>>>(n, maxt, n0, V2, tau2, work);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const bool vec = (reinterpret_cast<uintptr_t>(Z) % 16 == 0) && ((ldz * (int64_t)sizeof(T)) % 16 == 0);
+        const unsigned grid = (unsigned)FL_DIV_UP(ncols, 64);
+        KScope ks("q2_apply", s);
+        if (vec)
+            q2_apply64_kernel<T, true><<<grid, 256, 0, s>>>(n, maxt, n0, V2, work, Z, ldz, ncols);
+        else
+            q2_apply64_kernel<T, false><<<grid, 256, 0, s>>>(n, maxt, n0, V2, work, Z, ldz, ncols);
+        return hipGetLastError();
+    }
     T* VB = work;
     T* TB = work + maxt * VBLK;
     hipError_t e;
@@ -252,8 +519,15 @@ hipError_t q1_apply_t(hipStream_t s, int64_t n, int b, const T* V1, int64_t ldv,
 
 }  // namespace
 
-// Packed blocks of one group: maxt V blocks and maxt T blocks (elements).
-int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) { (void)n; (void)b; return maxt * (VBLK + TBLK) + 4; }
+// Work elements: with b = 64 the T factors of every block, otherwise the
+// packed V and T blocks of one group.
+int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) {
+    if (b == FB && n >= 3) {
+        const int64_t n0 = 1 + (n - 3) / FB;
+        return q2_block_base(n0, n0) * FB * FB + 4;  // T factors of every block
+    }
+    return maxt * (VBLK + TBLK) + 4;
+}
 
 // Z (n x ncols) := Q2 Z with the reflectors of fl_sb2st.  work: fl_q2_t_elems elements.
 hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* work,
