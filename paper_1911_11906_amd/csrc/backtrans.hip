@@ -290,9 +290,16 @@ __global__ __launch_bounds__(256) void q2_tfactor_kernel(int64_t n, int64_t maxt
     for (int k = 0; k < FB; ++k) out[lane + k * FB] = (OT)Tr[k];
 }
 
-template <class T, bool VEC>
-__device__ inline void q2_load4(const T* zc, int64_t row0, int64_t n, bool cok, typename fl_tile::Mfma<T>::acc& a) {
-    if (VEC && cok && row0 + 3 < n) {
+// Rows row0 .. row0+3 of column zc.  Loads are unconditional: with CLAMP
+// (a window reaching past row n-1) the indices are clamped into the matrix,
+// so rows at or beyond n hold copies of row n-1, which is harmless since V
+// is zero there and those rows are never stored.
+template <class T, bool VEC, bool CLAMP>
+__device__ inline void q2_load4(const T* zc, int64_t row0, int64_t n, typename fl_tile::Mfma<T>::acc& a) {
+    if (CLAMP) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = zc[row0 + r < n ? row0 + r : n - 1];
+    } else if (VEC) {
         if constexpr (sizeof(T) == 4) {
             const float4 v = *reinterpret_cast<const float4*>(zc + row0);
             a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
@@ -303,14 +310,18 @@ __device__ inline void q2_load4(const T* zc, int64_t row0, int64_t n, bool cok, 
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = (cok && row0 + r < n) ? zc[row0 + r] : T(0);
+        for (int r = 0; r < 4; ++r) a[r] = zc[row0 + r];
     }
 }
 
-template <class T, bool VEC>
+template <class T, bool VEC, bool MASK>
 __device__ inline void q2_store4(T* zc, int64_t row0, int64_t n, bool cok, const typename fl_tile::Mfma<T>::acc& a) {
     if (!cok) return;
-    if (VEC && row0 + 3 < n) {
+    if (MASK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (row0 + r < n) zc[row0 + r] = a[r];
+    } else if (VEC) {
         if constexpr (sizeof(T) == 4) {
             *reinterpret_cast<float4*>(zc + row0) = make_float4(a[0], a[1], a[2], a[3]);
         } else {
@@ -319,8 +330,7 @@ __device__ inline void q2_store4(T* zc, int64_t row0, int64_t n, bool cok, const
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (row0 + r < n) zc[row0 + r] = a[r];
+        for (int r = 0; r < 4; ++r) zc[row0 + r] = a[r];
     }
 }
 
@@ -340,18 +350,24 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t maxt
     const int64_t nsw = n - 2;
     for (int e = t; e < FR * LDF; e += 256) Vf[e] = T(0);  // off-staircase entries stay zero
 
-    T pv[16], pt[16];
-    // block (g, j): reflector s = wave + 4 q, entry i = lane -> frame row s + 1 + i
+    double pv[16];  // raw reflector entries; masked and converted when staged
+    unsigned pmask = 0;
+    T pt[16];
+    // block (g, j): reflector s = wave + 4 q, entry i = lane -> frame row s + 1 + i.
+    // The loads are unconditional (absent entries read V2[0]); the mask is
+    // applied when the values are staged after the block's products.
     auto fetch = [&](int64_t gi, int64_t j) {
         const int64_t g = gi * FB;
+        pmask = 0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int s = wave + 4 * q;
             const int64_t sw = g + s;
             const bool ex = sw < nsw && j < 1 + (n - 3 - sw) / FB;
             const int64_t r0 = g + 1 + j * FB + s;
-            const int64_t L = ex ? ((n - r0) < FB ? (n - r0) : FB) : 0;
-            pv[q] = lane < L ? (T)V2[(sw * maxt + j) * FB + lane] : T(0);
+            const bool ok = ex && lane < n - r0;
+            pv[q] = V2[ok ? (sw * maxt + j) * FB + lane : 0];
+            pmask |= (ok ? 1u : 0u) << q;
         }
         const T* tb = TB + (q2_block_base(gi, n0) + j) * (int64_t)(FB * FB);
 #pragma unroll
@@ -361,15 +377,100 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t maxt
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int s = wave + 4 * q;
-            Vf[(s + 1 + lane) * LDF + s] = pv[q];
+            Vf[(s + 1 + lane) * LDF + s] = ((pmask >> q) & 1u) ? (T)pv[q] : T(0);
         }
 #pragma unroll
         for (int q = 0; q < 16; ++q) Ts[t + 256 * q] = pt[q];
     };
 
-    acc_t zt[4], zb[4], zn[4], w[4], w2[4];
     const int lrow = 4 * lr;
     const int vsig = q2_sigma<T>(lc);
+    acc_t zt[4], zb[4], zn[4];
+    // One block on the window (zt, zb): products, zt to memory, then the
+    // window moves down by half; the lower half of the next window is loaded
+    // into zn meanwhile.  TAIL: the window or the rows loaded reach past n-1.
+    auto block = [&](auto tail, int64_t gi, int64_t j, int64_t nt) {
+        constexpr bool TAIL = decltype(tail)::value;
+        const int64_t F = gi * FB + j * FB;
+        const bool more = j + 1 < nt;
+        if (more) {
+            fetch(gi, j + 1);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) q2_load4<T, VEC, TAIL>(zc, F + 2 * FB + 16 * rt + lrow, n, zn[rt]);
+        }
+        acc_t w[4], w2[4];
+        // W = V^T Z over tile pairs wt <= rt <= wt + 4
+#pragma unroll
+        for (int wt = 0; wt < 4; ++wt) w[wt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int wt = 0; wt < 4; ++wt) {
+                    const int rt = wt + d;
+                    const T a = Vf[(16 * rt + lrow + r) * LDF + 16 * wt + lc];
+                    const T bz = rt < 4 ? zt[rt & 3][r] : zb[rt & 3][r];
+                    w[wt] = MM::mma(a, bz, w[wt]);
+                }
+        // W2 = T W (T upper triangular)
+#pragma unroll
+        for (int wt = 0; wt < 4; ++wt) w2[wt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int wt2 = 0; wt2 < 4; ++wt2) {
+                    const int wt = wt2 + d;
+                    if (wt < 4) {
+                        const T a = Ts[(16 * wt2 + lc) + (16 * wt + MM::row(lr, r)) * FB];
+                        w2[wt2] = MM::mma(a, w[wt][r], w2[wt2]);
+                    }
+                }
+#pragma unroll
+        for (int wt = 0; wt < 4; ++wt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w2[wt][r] = -w2[wt][r];
+        // Z -= V W2
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int wt = 0; wt < 4; ++wt) {
+                    const int rt = wt + d;
+                    const T a = Vf[(16 * rt + vsig) * LDF + 16 * wt + MM::row(lr, r)];
+                    if (rt < 4)
+                        zt[rt & 3] = MM::mma(a, w2[wt][r], zt[rt & 3]);
+                    else
+                        zb[rt & 3] = MM::mma(a, w2[wt][r], zb[rt & 3]);
+                }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC, TAIL>(zc, F + 16 * rt + lrow, n, cok, zt[rt]);
+        if (more) {
+            // keep the prefetched rows out of the products: without this
+            // ordering point the compiler may move the copy into zb (and the
+            // wait for those loads) in among the matrix instructions
+            T last = zb[3][3];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) asm volatile("" : "+v"(zn[rt][r]) : "v"(last));
+            __syncthreads();  // every wave is done with this block's V and T
+            stage();
+            __syncthreads();
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                zt[rt] = zb[rt];
+                zb[rt] = zn[rt];
+            }
+        } else {
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC, true>(zc, F + FB + 16 * rt + lrow, n, cok, zb[rt]);
+        }
+    };
+
     for (int64_t gi = n0 - 1; gi >= 0; --gi) {
         const int64_t g = gi * FB, nt = n0 - gi;
         fetch(gi, 0);
@@ -377,81 +478,15 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t maxt
         stage();
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-            q2_load4<T, VEC>(zc, g + 16 * rt + lrow, n, cok, zt[rt]);
-            q2_load4<T, VEC>(zc, g + FB + 16 * rt + lrow, n, cok, zb[rt]);
+            q2_load4<T, VEC, true>(zc, g + 16 * rt + lrow, n, zt[rt]);
+            q2_load4<T, VEC, true>(zc, g + FB + 16 * rt + lrow, n, zb[rt]);
         }
         __syncthreads();
-        for (int64_t j = 0; j < nt; ++j) {
-            const int64_t F = g + j * FB;
-            const bool more = j + 1 < nt;
-            if (more) {
-                fetch(gi, j + 1);
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt) q2_load4<T, VEC>(zc, F + 2 * FB + 16 * rt + lrow, n, cok, zn[rt]);
-            }
-            // W = V^T Z over tile pairs wt <= rt <= wt + 4
-#pragma unroll
-            for (int wt = 0; wt < 4; ++wt) w[wt] = acc_t{0, 0, 0, 0};
-#pragma unroll
-            for (int d = 0; d < 5; ++d)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int wt = 0; wt < 4; ++wt) {
-                        const int rt = wt + d;
-                        const T a = Vf[(16 * rt + lrow + r) * LDF + 16 * wt + lc];
-                        const T bz = rt < 4 ? zt[rt & 3][r] : zb[rt & 3][r];
-                        w[wt] = MM::mma(a, bz, w[wt]);
-                    }
-            // W2 = T W (T upper triangular)
-#pragma unroll
-            for (int wt = 0; wt < 4; ++wt) w2[wt] = acc_t{0, 0, 0, 0};
-#pragma unroll
-            for (int d = 0; d < 4; ++d)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int wt2 = 0; wt2 < 4; ++wt2) {
-                        const int wt = wt2 + d;
-                        if (wt < 4) {
-                            const T a = Ts[(16 * wt2 + lc) + (16 * wt + MM::row(lr, r)) * FB];
-                            w2[wt2] = MM::mma(a, w[wt][r], w2[wt2]);
-                        }
-                    }
-#pragma unroll
-            for (int wt = 0; wt < 4; ++wt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) w2[wt][r] = -w2[wt][r];
-            // Z -= V W2
-#pragma unroll
-            for (int d = 0; d < 5; ++d)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int wt = 0; wt < 4; ++wt) {
-                        const int rt = wt + d;
-                        const T a = Vf[(16 * rt + vsig) * LDF + 16 * wt + MM::row(lr, r)];
-                        if (rt < 4)
-                            zt[rt & 3] = MM::mma(a, w2[wt][r], zt[rt & 3]);
-                        else
-                            zb[rt & 3] = MM::mma(a, w2[wt][r], zb[rt & 3]);
-                    }
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC>(zc, F + 16 * rt + lrow, n, cok, zt[rt]);
-            if (more) {
-                __syncthreads();  // every wave is done with this block's V and T
-                stage();
-                __syncthreads();
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt) {
-                    zt[rt] = zb[rt];
-                    zb[rt] = zn[rt];
-                }
-            } else {
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC>(zc, F + FB + 16 * rt + lrow, n, cok, zb[rt]);
-            }
-        }
+        // blocks whose window and prefetched rows lie inside the matrix
+        const int64_t nfull = n - g >= 3 * FB ? (n - g - 3 * FB) / FB + 1 : 0;
+        int64_t j = 0;
+        for (; j < nt && j < nfull; ++j) block(std::false_type{}, gi, j, nt);
+        for (; j < nt; ++j) block(std::true_type{}, gi, j, nt);
     }
 }
 
