@@ -7,9 +7,9 @@
 //   M = L L^T                      blocked Cholesky (32-column panels)
 //   C = L^-1 (L^-1 K)^T            two blocked triangular solves
 //   C = Q T Q^T                    Householder tridiagonalisation
-//   T = Z_T diag(theta) Z_T^T      implicit QL with Wilkinson shifts; the
-//                                  rotations of each sweep are staged in LDS
-//                                  and applied to Z row-parallel
+//   T = Z_T diag(theta) Z_T^T      divide and conquer: leaves of <= 32 by
+//                                  implicit QL (one wave each, in LDS), merges
+//                                  by secular equations and two GEMMs
 //   Z = Q Z_T                      block reflectors (I - V T V^T), 32 at a time
 //   V = L^-T Z                     blocked triangular solve
 // then theta ascending and V = [phi_1 .. phi_n], M-orthonormal.  The dense
@@ -29,7 +29,8 @@ constexpr int NMAX = 1024;                 // largest problem
 constexpr int PB = 32;                     // panel / reflector block width
 constexpr int TM = 64, TN = 128, TK = 16;  // GEMM tile (4 x 4 outputs per thread)
 constexpr int RPT = NMAX / BT;             // rows per thread in the tridiagonalisation
-constexpr int QS = 4;                      // QL sweeps applied to Z per pass
+constexpr int DCL = 32;                    // largest leaf of the divide and conquer
+constexpr int SU = 8;                      // columns per chunk in the tridiagonalisation's update
 static_assert(TM * TN == 16 * BT, "one 4 x 4 register tile per thread");
 constexpr double EPS = 2.220446049250313e-16;
 
@@ -47,6 +48,8 @@ struct BProb {
     double* theta;
     double* logtheta;
     double *L, *W, *A, *Z;                               // workspaces, ld n
+    double *U, *Y;                                      // divide and conquer work, n x n
+    double* R;                                          // 4 n
     double* tau;                                        // n
 };
 
@@ -55,13 +58,16 @@ struct Lds {
     double Bs[TK][TN + 1];
     double D[PB][PB + 1];
     double red[BT / 64];
-    double va[2][NMAX];  // Householder vectors (two in flight), QL cosines
-    double wa[2][NMAX];  // their w = p - (tau/2)(p^T v) v, QL sines
+    double va[2][NMAX];  // Householder vectors (two in flight); divide and conquer scratch
+    double wa[2][NMAX];  // their w = p - (tau/2)(p^T v) v
     double dd[NMAX];  // diagonal of T, then theta
     double ee[NMAX];  // off-diagonal of T
-    double qx[2][NMAX];  // rotations of two more buffered QL sweeps
+    double qx[2][NMAX];  // divide and conquer scratch
     double qy[2][NMAX];
     int rk[NMAX];     // ranks of theta
+    int ix[NMAX];     // divide and conquer: deflated columns
+    double lq[BT / 64][4][DCL];  // divide and conquer leaves: d, e, cosines, sines per wave
+    int lb[NMAX / DCL + 2];      // leaf boundaries
     int ival[4];
     int qlo[4], qhi[4];
     double dval[4];
@@ -358,6 +364,19 @@ __device__ void wg_make_w(int n, int64_t g0, int m, double tk, const double (&ac
 // s.dd and s.ee.  One pass over the trailing matrix per step: the rank-2
 // update of step k, A22 -= v w^T + w v^T, is fused with the product
 // A22' v' of step k+1 (A22' = A22 without its first row and column).
+// Rows t + q BT (q < RPT) of columns g0 + j0 .. g0 + j0 + SU - 1 (j < m).
+__device__ inline void sytrd_load_chunk(const double* A, int64_t lda, int64_t g0, int j0, int m, int n,
+                                        const bool (&own)[RPT], double (&buf)[SU][RPT]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const int j = j0 + u;
+        const double* col = A + (g0 + j) * lda;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) buf[u][q] = (j < m && own[q]) ? col[t + q * BT] : 0.0;
+    }
+}
+
 __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda, double* tau, Lds& s) {
     const int t = threadIdx.x;
     if (n <= 2) {
@@ -387,6 +406,7 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
         double acc[RPT];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+#pragma unroll 16
         for (int j = 1; j < n; ++j) {
             const double vj = s.va[0][j - 1];
             const double* col = A + (int64_t)j * lda;
@@ -429,25 +449,46 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
                 tau[k + 1] = tk;
             }
             __syncthreads();
-            // (c) rows/columns g0+1.. : A -= v w^T + w v^T, fused with acc = A v'
+            // (c) rows/columns g0+1.. : A -= v w^T + w v^T, fused with acc = A v'.
+            // Columns are streamed in chunks of SU; the next chunk is loaded
+            // before the current one is updated and stored, so each chunk
+            // waits for one memory round trip instead of each column.
             const double* v2 = s.va[nxt];  // indexed from global row g0+1
-            double acc[RPT];
+            double acc[RPT], vi[RPT], wi[RPT];
+            bool own[RPT];
 #pragma unroll
-            for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
-            for (int j = 1; j < m; ++j) {
-                const double vj = v[j], wj = w[j], v2j = v2[j - 1];
-                double* col = A + (g0 + j) * lda;
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t g = t + q * BT, i = g - g0;
+                own[q] = g < n && i >= 1;
+                vi[q] = own[q] ? v[i] : 0.0;
+                wi[q] = own[q] ? w[i] : 0.0;
+                acc[q] = 0.0;
+            }
+            double cur[SU][RPT], nx[SU][RPT];
+            sytrd_load_chunk(A, lda, g0, 1, m, n, own, cur);
+            for (int j0 = 1; j0 < m; j0 += SU) {
+                if (j0 + SU < m) sytrd_load_chunk(A, lda, g0, j0 + SU, m, n, own, nx);
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int64_t g = t + q * BT;
-                    const int64_t i = g - g0;
-                    if (g < n && i >= 1) {
-                        const double p1 = __dmul_rn(v[i], wj), p2 = __dmul_rn(w[i], vj);
-                        const double a = __dsub_rn(col[g], __dadd_rn(p1, p2));
-                        col[g] = a;
-                        acc[q] = fma(a, v2j, acc[q]);
+                for (int u = 0; u < SU; ++u) {
+                    const int j = j0 + u;
+                    if (j < m) {
+                        const double vj = v[j], wj = w[j], v2j = v2[j - 1];
+                        double* col = A + (g0 + j) * lda;
+#pragma unroll
+                        for (int q = 0; q < RPT; ++q) {
+                            if (own[q]) {
+                                const double p1 = __dmul_rn(vi[q], wj), p2 = __dmul_rn(wi[q], vj);
+                                const double a = __dsub_rn(cur[u][q], __dadd_rn(p1, p2));
+                                col[t + q * BT] = a;
+                                acc[q] = fma(a, v2j, acc[q]);
+                            }
+                        }
                     }
                 }
+#pragma unroll
+                for (int u = 0; u < SU; ++u)
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) cur[u][q] = nx[u][q];
             }
             // (d) w of step k+1
             wg_make_w(n, g0 + 1, m - 1, tk, acc, v2, s.wa[nxt], s);
@@ -474,169 +515,6 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
             __syncthreads();
         }
     }
-}
-
-__device__ inline double* ql_cos(Lds& s, int b) { return b < 2 ? s.va[b] : s.qx[b - 2]; }
-__device__ inline double* ql_sin(Lds& s, int b) { return b < 2 ? s.wa[b] : s.qy[b - 2]; }
-
-// Apply nb <= QS buffered QL sweeps to the rows of Z in one pass.  Sweep b
-// applies its rotations (i, i+1), i = hi_b .. lo_b, in that order.  Each row is
-// walked downwards with a register window of 2 QS columns: at position c,
-// sweep b rotates columns (c + 2b, c + 2b + 1).  Sweep b at i needs sweep b-1
-// to have rotated (i-1, i), which happened at position c + 1, and nothing
-// touches column c + 2 QS - 1 after position c, so it is written back then.
-__device__ void ql_apply(int n, double* Z, int64_t ldz, int nb, Lds& s) {
-    const int t = threadIdx.x;
-    int lo[QS], hi[QS];
-    const double* C[QS];
-    const double* S[QS];
-    int cstart = -(1 << 30), cend = 1 << 30;
-#pragma unroll
-    for (int b = 0; b < QS; ++b) {
-        lo[b] = (b < nb) ? s.qlo[b] : 1;
-        hi[b] = (b < nb) ? s.qhi[b] : 0;
-        C[b] = ql_cos(s, b);
-        S[b] = ql_sin(s, b);
-        if (lo[b] <= hi[b]) {
-            cstart = max(cstart, hi[b] - 2 * b);
-            cend = min(cend, lo[b] - 2 * b);
-        }
-    }
-    if (cstart < cend) return;  // no rotations (uniform: every thread read the same LDS)
-    for (int row = t; row < n; row += BT) {
-        double* zr = Z + row;
-        double win[2 * QS];
-#pragma unroll
-        for (int k = 0; k < 2 * QS; ++k) {
-            const int col = cstart + k;
-            win[k] = (col >= 0 && col < n) ? zr[(int64_t)col * ldz] : 0.0;
-        }
-        int c = cstart;
-        while (c >= cend) {
-            const int cnt = min(8, c - cend + 1);
-            double pre[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int col = c - 1 - q;
-                pre[q] = (q < cnt && col >= 0) ? zr[(int64_t)col * ldz] : 0.0;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (q < cnt) {
-                    const int cc = c - q;
-#pragma unroll
-                    for (int b = 0; b < QS; ++b) {
-                        const int i = cc + 2 * b;
-                        if (lo[b] <= i && i <= hi[b]) {
-                            const double cs = C[b][i], sn = S[b][i];
-                            const double x = win[2 * b], y = win[2 * b + 1];
-                            win[2 * b] = cs * x - sn * y;
-                            win[2 * b + 1] = sn * x + cs * y;
-                        }
-                    }
-                    const int col_out = cc + 2 * QS - 1;
-                    if (col_out < n) zr[(int64_t)col_out * ldz] = win[2 * QS - 1];
-#pragma unroll
-                    for (int k = 2 * QS - 1; k > 0; --k) win[k] = win[k - 1];
-                    win[0] = pre[q];
-                }
-            }
-            c -= cnt;
-        }
-        // the window now holds columns cend-1 .. cend-1 + 2QS-1
-#pragma unroll
-        for (int k = 0; k < 2 * QS; ++k) {
-            const int col = cend - 1 + k;
-            if (col >= 0 && col < n) zr[(int64_t)col * ldz] = win[k];
-        }
-    }
-}
-
-// Implicit QL with Wilkinson shifts on (s.dd, s.ee); Z (n x n, identity on
-// entry) accumulates the rotations.  One thread runs each sweep's scalar
-// recurrence and stages its rotations in LDS; every QS sweeps all threads
-// apply them to their rows of Z in one pass.  Returns 0, or l+1 if
-// eigenvalue l took over 60 sweeps.
-__device__ __attribute__((noinline)) int wg_steql(int n, double* Z, int64_t ldz, Lds& s) {
-    const int t = threadIdx.x;
-    int nb = 0;  // buffered sweeps (the same in every thread)
-    for (int l = 0; l < n; ++l) {
-        int iter = 0;
-        for (;;) {
-            if (t == 0) {
-                int mm = l;
-                for (; mm < n - 1; ++mm) {
-                    const double dd = fabs(s.dd[mm]) + fabs(s.dd[mm + 1]);
-                    if (fabs(s.ee[mm]) <= EPS * dd) break;
-                }
-                s.ival[1] = mm;
-            }
-            __syncthreads();
-            const int m = s.ival[1];
-            __syncthreads();
-            if (m == l) break;
-            if (++iter > 60) return l + 1;
-            if (t == 0) {
-                double* qc = ql_cos(s, nb);
-                double* qs = ql_sin(s, nb);
-                // shift from the leading 2 x 2 of the unreduced block [l, m]
-                double g = (s.dd[l + 1] - s.dd[l]) / (2.0 * s.ee[l]);
-                double r = hypot(g, 1.0);
-                g = s.dd[m] - s.dd[l] + s.ee[l] / (g + copysign(r, g));
-                double sn = 1.0, c = 1.0, p = 0.0;
-                int i = m - 1;
-                bool early = false;
-                // the chain is latency bound: d and e of the next step are read
-                // ahead, and one square root and one reciprocal replace hypot and
-                // two divisions (|f|, |g| stay far from overflow for these pencils)
-                double ei = s.ee[i], di = s.dd[i], di1 = s.dd[i + 1];
-                for (; i >= l; --i) {
-                    const double ein = (i > l) ? s.ee[i - 1] : 0.0;
-                    const double din = (i > l) ? s.dd[i - 1] : 0.0;
-                    const double f = sn * ei, b = c * ei;
-                    r = sqrt(f * f + g * g);
-                    s.ee[i + 1] = r;
-                    if (r == 0.0) {  // the block splits: restart on it
-                        s.dd[i + 1] = di1 - p;
-                        s.ee[m] = 0.0;
-                        early = true;
-                        break;
-                    }
-                    const double inv = 1.0 / r;
-                    sn = f * inv;
-                    c = g * inv;
-                    g = di1 - p;
-                    r = (di - g) * sn + 2.0 * c * b;
-                    p = sn * r;
-                    s.dd[i + 1] = g + p;
-                    g = c * r - b;
-                    qc[i] = c;
-                    qs[i] = sn;
-                    ei = ein;
-                    di1 = di;
-                    di = din;
-                }
-                if (!early) {
-                    s.dd[l] -= p;
-                    s.ee[l] = g;
-                    s.ee[m] = 0.0;
-                    s.qlo[nb] = l;
-                } else {
-                    s.qlo[nb] = i + 1;
-                }
-                s.qhi[nb] = m - 1;
-            }
-            __syncthreads();
-            if (++nb == QS) {
-                ql_apply(n, Z, ldz, nb, s);
-                nb = 0;
-                __syncthreads();
-            }
-        }
-    }
-    if (nb) ql_apply(n, Z, ldz, nb, s);
-    __syncthreads();
-    return 0;
 }
 
 // Z := Q Z with Q = H_0 H_1 ... H_{n-3} from wg_sytrd, applied as block
@@ -684,6 +562,492 @@ __device__ __attribute__((noinline)) void wg_ormtr(int n, const double* A, int64
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tridiagonal eigensolver: Cuppen's divide and conquer inside one workgroup.
+//
+// T = diag(T1, T2) + |beta| u u^T, u = e_s + sign(beta) e_{s+1} (beta the
+// coupling entry at the split s; the last diagonal entry of T1 and the first
+// of T2 are reduced by |beta|).  With T1 = Q1 D1 Q1^T, T2 = Q2 D2 Q2^T the
+// merged problem is D + rho z z^T, z = Q^T u / sqrt 2, rho = 2 |beta|.  Poles
+// with rho |z_j| <= tol, or made to share one z by a Givens rotation whose
+// residue is <= tol, deflate; each remaining root is found by one thread in
+// coordinates shifted to its nearer pole; z is recomputed from the roots
+// (Gu and Eisenstat) and the merged vectors are Q times the normalised
+// columns zhat / (d - lambda_k), with Q's block structure (columns living in
+// one half only) used by the two GEMMs.  Leaves (<= DCL) use implicit QL,
+// one wave per leaf, in LDS.
+
+__device__ inline void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS tile of wave w: va[0..1], wa[0..1] (contiguous) for w < 4, qx, qy for w >= 4.
+__device__ inline double* dc_tile(Lds& s, int w) {
+    static_assert(sizeof(s.va) + sizeof(s.wa) == 4 * NMAX * sizeof(double), "va, wa contiguous");
+    return w < 4 ? &s.va[0][0] + w * NMAX : &s.qx[0][0] + (w - 4) * NMAX;
+}
+
+// Leaves: wave w solves leaves w, w + 8, ...  Returns 0 or 1 (QL failed).
+__device__ __attribute__((noinline)) int dc_leaves(int nleaf, double* Z, int64_t ldz, Lds& s) {
+    static_assert(BT / 64 == 8 && DCL * DCL <= NMAX, "eight leaf tiles of DCL x DCL in LDS");
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double* zt = dc_tile(s, w);
+    double* ld = s.lq[w][0];
+    double* le = s.lq[w][1];
+    double* rc = s.lq[w][2];
+    double* rs = s.lq[w][3];
+    int failed = 0;
+    for (int li = w; li < nleaf; li += BT / 64) {
+        const int lo = s.lb[li], m = s.lb[li + 1] - lo;
+        if (lane < m) {
+            for (int c = 0; c < m; ++c) zt[lane + DCL * c] = (lane == c) ? 1.0 : 0.0;
+            ld[lane] = s.dd[lo + lane];
+            le[lane] = (lane < m - 1) ? s.ee[lo + lane] : 0.0;
+        }
+        wsync();
+        for (int l = 0; l < m && !failed; ++l) {
+            int iter = 0;
+            for (;;) {
+                int go = 0, rlo = 0, rhi = -1;
+                if (lane == 0) {
+                    int mm = l;
+                    while (mm < m - 1) {
+                        if (fabs(le[mm]) <= EPS * (fabs(ld[mm]) + fabs(ld[mm + 1]))) break;
+                        ++mm;
+                    }
+                    if (mm != l) {
+                        if (++iter > 90) {
+                            go = -1;
+                        } else {
+                            go = 1;
+                            double g = (ld[l + 1] - ld[l]) / (2.0 * le[l]);
+                            double r = hypot(g, 1.0);
+                            g = ld[mm] - ld[l] + le[l] / (g + (g >= 0.0 ? r : -r));
+                            double sn = 1.0, c = 1.0, p = 0.0;
+                            int i = mm - 1;
+                            bool early = false;
+                            for (; i >= l; --i) {
+                                const double f = sn * le[i], b = c * le[i];
+                                r = hypot(f, g);
+                                le[i + 1] = r;
+                                if (r == 0.0) {
+                                    ld[i + 1] -= p;
+                                    le[mm] = 0.0;
+                                    early = true;
+                                    break;
+                                }
+                                sn = f / r;
+                                c = g / r;
+                                g = ld[i + 1] - p;
+                                r = (ld[i] - g) * sn + 2.0 * c * b;
+                                p = sn * r;
+                                ld[i + 1] = g + p;
+                                g = c * r - b;
+                                rc[i] = c;
+                                rs[i] = sn;
+                            }
+                            rlo = early ? i + 1 : l;
+                            rhi = mm - 1;
+                            if (!early) {
+                                ld[l] -= p;
+                                le[l] = g;
+                                le[mm] = 0.0;
+                            }
+                        }
+                    }
+                }
+                go = __shfl(go, 0, 64);
+                rlo = __shfl(rlo, 0, 64);
+                rhi = __shfl(rhi, 0, 64);
+                wsync();
+                if (go < 0) failed = 1;
+                if (go <= 0) break;
+                if (lane < m) {
+                    for (int i = rhi; i >= rlo; --i) {
+                        const double c = rc[i], sn = rs[i];
+                        const double f = zt[lane + (i + 1) * DCL], a = zt[lane + i * DCL];
+                        zt[lane + (i + 1) * DCL] = sn * a + c * f;
+                        zt[lane + i * DCL] = c * a - sn * f;
+                    }
+                }
+                wsync();
+            }
+        }
+        if (lane < m) {
+            s.dd[lo + lane] = ld[lane];
+            for (int c = 0; c < m; ++c) Z[(lo + lane) + (int64_t)(lo + c) * ldz] = zt[lane + DCL * c];
+        }
+        wsync();
+    }
+    return failed;
+}
+
+// WG-wide max of v >= 0.
+__device__ double wg_max(double v, Lds& s) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < BT / 64; ++w) r = fmax(r, s.red[w]);
+    __syncthreads();
+    return r;
+}
+
+// Secular equation root k of 1 + rho sum_j z_j^2 / (d_j - lambda) = 0 (d
+// ascending, K poles): returns tau with lambda = d[org] + tau; false if the
+// iteration did not converge.
+__device__ bool dc_root(int K, int k, const double* d, const double* z, double rho, int* org_out, double* tau_out) {
+    int org;
+    double lo, hi;
+    if (k < K - 1) {
+        const double mid = 0.5 * (d[k + 1] - d[k]);
+        double f = 1.0;
+        for (int j = 0; j < K; ++j) f += rho * z[j] * z[j] / ((d[j] - d[k]) - mid);
+        if (f >= 0.0) {
+            org = k;
+            lo = 0.0;
+            hi = mid;
+        } else {
+            org = k + 1;
+            lo = -mid;
+            hi = 0.0;
+        }
+    } else {
+        org = k;
+        double zz = 0.0;
+        for (int j = 0; j < K; ++j) zz += z[j] * z[j];
+        lo = 0.0;
+        hi = rho * zz;
+    }
+    const double dorg = d[org];
+    const double Dk = d[k] - dorg;
+    const double Dk1 = (k < K - 1) ? d[k + 1] - dorg : 0.0;
+    double x = 0.5 * (lo + hi);
+    bool conv = false;
+    for (int it = 0; it < 400; ++it) {
+        double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
+        for (int j = 0; j <= k; ++j) {
+            const double dl = (d[j] - dorg) - x;
+            const double tq = rho * z[j] * z[j] / dl;
+            psi += tq;
+            dpsi += tq / dl;
+        }
+        for (int j = k + 1; j < K; ++j) {
+            const double dl = (d[j] - dorg) - x;
+            const double tq = rho * z[j] * z[j] / dl;
+            phi += tq;
+            dphi += tq / dl;
+        }
+        const double f = 1.0 + psi + phi;
+        if (f < 0.0)
+            lo = x;
+        else
+            hi = x;
+        if (fabs(f) <= 8.0 * EPS * (1.0 + fabs(psi) + fabs(phi)) || hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi))) {
+            conv = true;
+            break;
+        }
+        // two-pole rational model through f, f' (poles d_k, d_k+1), safeguarded by the bracket
+        const double dlk = Dk - x;
+        const double bb = dpsi * dlk * dlk;
+        double a2, a1, a0;
+        if (k < K - 1) {
+            const double dlk1 = Dk1 - x;
+            const double BB = dphi * dlk1 * dlk1;
+            const double c = f - dpsi * dlk - dphi * dlk1;
+            a2 = c;
+            a1 = -(c * (Dk + Dk1) + bb + BB);
+            a0 = c * Dk * Dk1 + bb * Dk1 + BB * Dk;
+        } else {
+            const double c = f - dpsi * dlk;
+            a2 = 0.0;
+            a1 = -c;
+            a0 = c * Dk + bb;
+        }
+        double xn = 0.5 * (lo + hi);
+        if (a2 == 0.0) {
+            if (a1 != 0.0) {
+                const double cnd = -a0 / a1;
+                if (cnd > lo && cnd < hi) xn = cnd;
+            }
+        } else {
+            const double disc = a1 * a1 - 4.0 * a2 * a0;
+            if (disc >= 0.0) {
+                const double sq = sqrt(disc);
+                const double q = -0.5 * (a1 + (a1 >= 0.0 ? sq : -sq));
+                const double c1 = q / a2;
+                const double c2 = (q != 0.0) ? a0 / q : c1;
+                if (c1 > lo && c1 < hi)
+                    xn = c1;
+                else if (c2 > lo && c2 < hi)
+                    xn = c2;
+            }
+        }
+        x = xn;
+    }
+    *org_out = org;
+    *tau_out = x;
+    return conv;
+}
+
+// Merge of the blocks [o, o+n1) and [o+n1, o+N) (eigenpairs in s.dd and the
+// diagonal blocks of Z).  X (N x N), U (K x K), Y (N x K): global work, R:
+// rotations (4 N doubles).  Returns 0 or 2 (a root did not converge).
+__device__ __attribute__((noinline)) int dc_merge(int o, int N, int n1, double* Z, int64_t ldz, double* X, double* U,
+                                                  double* Y, double* R, Lds& s) {
+    const int t = threadIdx.x;
+    double* ds = s.va[0];   // sorted poles, then the root offsets tau
+    double* zs = s.va[1];   // sorted z, then zhat
+    double* dk = s.wa[0];   // kept poles
+    double* zk = s.wa[1];   // their z
+    double* dvl = s.qx[0];  // deflated values
+    double* aux = s.qx[1];  // 1 / column norms of U, then the merged values
+    int* perm = reinterpret_cast<int*>(s.qy[0]);  // sorted -> child column, then ranks
+    int* typ = perm + NMAX;                        // 1 top only, 2 both, 3 bottom only
+    int* kcol = reinterpret_cast<int*>(s.qy[1]);   // kept columns
+    int* tpos = kcol + NMAX;                       // position of kept column k in type order
+    int* rorg = s.rk;                              // pole each root is measured from
+    int* dcol = s.ix;                              // deflated columns
+    int* ra = reinterpret_cast<int*>(R + 2 * N);
+    int* rb = ra + N;
+    double* rcs = R;
+    double* rsn = R + N;
+    const double beta = s.ee[o + n1 - 1];
+    const double sgn = beta >= 0.0 ? 1.0 : -1.0;
+    const double rho = 2.0 * fabs(beta);
+    const double isq2 = 0.70710678118654752440;
+    // (a) z from the last row of Q1 and the first row of Q2; sort the poles
+    double mx = 0.0;
+    for (int i = t; i < N; i += BT) {
+        const double vi = s.dd[o + i];
+        int r = 0;
+        for (int j = 0; j < N; ++j) {
+            const double vj = s.dd[o + j];
+            r += (vj < vi || (vj == vi && j < i)) ? 1 : 0;
+        }
+        const double zi = (i < n1 ? Z[(o + n1 - 1) + (int64_t)(o + i) * ldz] : sgn * Z[(o + n1) + (int64_t)(o + i) * ldz]) * isq2;
+        ds[r] = vi;
+        zs[r] = zi;
+        perm[r] = i;
+        typ[i] = i < n1 ? 1 : 3;
+        mx = fmax(mx, fmax(fabs(vi), rho * fabs(zi)));
+    }
+    const double tol = 8.0 * EPS * wg_max(mx, s);
+    // (b) deflation scan (one thread)
+    if (t == 0) {
+        int K = 0, nd = 0, nr = 0, cand = -1, ccol = -1;
+        double cd = 0.0, cz = 0.0;
+        for (int q = 0; q < N; ++q) {
+            const double dj = ds[q], zj = zs[q];
+            const int col = perm[q];
+            if (rho * fabs(zj) <= tol) {
+                dvl[nd] = dj;
+                dcol[nd] = col;
+                ++nd;
+                continue;
+            }
+            if (cand < 0) {
+                cand = q;
+                ccol = col;
+                cd = dj;
+                cz = zj;
+                continue;
+            }
+            const double r = hypot(cz, zj);
+            const double c = zj / r, sn = cz / r;
+            if (fabs((dj - cd) * c * sn) <= tol) {
+                // rotate columns (ccol, col): the candidate deflates, the new pole carries z = r
+                ra[nr] = ccol;
+                rb[nr] = col;
+                rcs[nr] = c;
+                rsn[nr] = sn;
+                ++nr;
+                if (typ[ccol] != typ[col]) {
+                    typ[ccol] = 2;
+                    typ[col] = 2;
+                }
+                dvl[nd] = c * c * cd + sn * sn * dj;
+                dcol[nd] = ccol;
+                ++nd;
+                cand = q;
+                ccol = col;
+                cd = sn * sn * cd + c * c * dj;
+                cz = r;
+            } else {
+                dk[K] = cd;
+                zk[K] = cz;
+                kcol[K] = ccol;
+                ++K;
+                cand = q;
+                ccol = col;
+                cd = dj;
+                cz = zj;
+            }
+        }
+        if (cand >= 0) {
+            dk[K] = cd;
+            zk[K] = cz;
+            kcol[K] = ccol;
+            ++K;
+        }
+        int c1 = 0, c2 = 0, c3 = 0;
+        for (int k = 0; k < K; ++k) {
+            const int ty = typ[kcol[k]];
+            c1 += ty == 1;
+            c2 += ty == 2;
+            c3 += ty == 3;
+        }
+        int p1 = 0, p2 = c1, p3 = c1 + c2;
+        for (int k = 0; k < K; ++k) {
+            const int ty = typ[kcol[k]];
+            tpos[k] = (ty == 1) ? p1++ : (ty == 2) ? p2++ : p3++;
+        }
+        s.ival[1] = K;
+        s.ival[2] = nr;
+        s.qlo[0] = c1;
+        s.qlo[1] = c2;
+        s.qlo[2] = c3;
+        s.ival[3] = 0;
+    }
+    gsync();
+    const int K = s.ival[1], nr = s.ival[2];
+    const int c1 = s.qlo[0], c2 = s.qlo[1], c3 = s.qlo[2];
+    // (c) deflation rotations on the columns of the merged block, one row per thread
+    if (nr > 0) {
+        for (int r = t; r < N; r += BT) {
+            double* zr = Z + (o + r);
+            for (int q = 0; q < nr; ++q) {
+                const int64_t a = o + ra[q], b = o + rb[q];
+                const double c = rcs[q], sn = rsn[q];
+                const double x = zr[a * ldz], y = zr[b * ldz];
+                zr[a * ldz] = c * x - sn * y;
+                zr[b * ldz] = sn * x + c * y;
+            }
+        }
+    }
+    // (d) roots, one thread each: tau into ds, origin into rorg
+    for (int k = t; k < K; k += BT) {
+        int org;
+        double tau;
+        if (!dc_root(K, k, dk, zk, rho, &org, &tau)) s.ival[3] = 2;
+        rorg[k] = org;
+        ds[k] = tau;
+    }
+    __syncthreads();
+    // (e) zhat_j from the roots (factors paired so that each lies in (0, 1])
+    for (int j = t; j < K; j += BT) {
+        const double dj = dk[j];
+        double p = (ds[K - 1] - (dj - dk[rorg[K - 1]])) / rho;
+        for (int k = 0; k < j; ++k) p *= (ds[k] - (dj - dk[rorg[k]])) / (dk[k] - dj);
+        for (int k = j; k < K - 1; ++k) p *= (ds[k] - (dj - dk[rorg[k]])) / (dk[k + 1] - dj);
+        zs[j] = copysign(sqrt(fabs(p)), zk[j]);
+    }
+    __syncthreads();
+    // (f) U: column k = zhat / (d - lambda_k), normalised; rows in type order
+    for (int k = t; k < K; k += BT) {
+        const double dorg = dk[rorg[k]], tau = ds[k];
+        double ss = 0.0;
+        for (int j = 0; j < K; ++j) {
+            const double u = zs[j] / ((dk[j] - dorg) - tau);
+            ss += u * u;
+        }
+        aux[k] = 1.0 / sqrt(ss);
+    }
+    __syncthreads();
+    for (int j = t; j < K; j += BT) {
+        const double zj = zs[j], dj = dk[j];
+        double* ur = U + tpos[j];
+        for (int k = 0; k < K; ++k) ur[(int64_t)k * K] = zj / ((dj - dk[rorg[k]]) - ds[k]) * aux[k];
+    }
+    // (g) kept columns of Q in type order, deflated columns after them
+    for (int r = t; r < N; r += BT) {
+        const double* zr = Z + (o + r);
+        for (int k = 0; k < K; ++k) X[r + (int64_t)tpos[k] * N] = zr[(int64_t)(o + kcol[k]) * ldz];
+        for (int q = 0; q < N - K; ++q) X[r + (int64_t)(K + q) * N] = zr[(int64_t)(o + dcol[q]) * ldz];
+    }
+    gsync();
+    // (h) Y = Q U, top rows from the type 1|2 columns, bottom rows from type 2|3
+    if (K > 0) {
+        wg_gemm(false, false, n1, K, c1 + c2, 1.0, X, N, U, K, 0.0, Y, N, s);
+        wg_gemm(false, false, N - n1, K, c2 + c3, 1.0, X + n1 + (int64_t)c1 * N, N, U + c1, K, 0.0, Y + n1, N, s);
+    }
+    // (i) merged values (roots, then deflated poles) and their ranks
+    for (int c = t; c < N; c += BT) aux[c] = c < K ? dk[rorg[c]] + ds[c] : dvl[c - K];
+    __syncthreads();
+    for (int c = t; c < N; c += BT) {
+        const double vc = aux[c];
+        int r = 0;
+        for (int j = 0; j < N; ++j) {
+            const double vj = aux[j];
+            r += (vj < vc || (vj == vc && j < c)) ? 1 : 0;
+        }
+        perm[c] = r;
+    }
+    __syncthreads();
+    // (j) scatter into Z and s.dd in ascending order
+    for (int c = 0; c < N; ++c) {
+        const int64_t dst = o + perm[c];
+        const double* src = (c < K) ? Y + (int64_t)c * N : X + (int64_t)c * N;
+        for (int r = t; r < N; r += BT) Z[(o + r) + dst * ldz] = src[r];
+    }
+    for (int c = t; c < N; c += BT) s.dd[o + perm[c]] = aux[c];
+    gsync();
+    return s.ival[3];
+}
+
+// Eigen-decomposition of the tridiagonal (s.dd, s.ee[0..n-2]) of order n:
+// s.dd := eigenvalues (ascending when n > DCL), Z := eigenvectors.  X, U, Y
+// (n x n) and R (4 n) are global work.  Returns 0, 1 (a leaf's QL did not
+// converge) or 2 (a secular equation did not converge).
+__device__ __attribute__((noinline)) int wg_stedc(int n, double* Z, int64_t ldz, double* X, double* U, double* Y,
+                                                  double* R, Lds& s) {
+    const int t = threadIdx.x;
+    // leaves: halve every block until it has at most DCL rows
+    int depth = 0;
+    while (((n + (1 << depth) - 1) >> depth) > DCL) ++depth;
+    const int nleaf = 1 << depth;
+    if (t == 0) {
+        s.lb[0] = 0;
+        s.lb[nleaf] = n;
+        for (int d = 0; d < depth; ++d) {
+            const int step = nleaf >> d;  // boundaries at depth d are lb[i * step]
+            for (int i = 0; i < (1 << d); ++i) {
+                const int lo = s.lb[i * step], hi = s.lb[(i + 1) * step];
+                s.lb[i * step + step / 2] = lo + (hi - lo) / 2;
+            }
+        }
+        // split adjustment at every boundary
+        for (int i = 1; i < nleaf; ++i) {
+            const int sp = s.lb[i] - 1;
+            const double a = fabs(s.ee[sp]);
+            s.dd[sp] -= a;
+            s.dd[sp + 1] -= a;
+        }
+    }
+    for (int j = 0; j < n; ++j)
+        for (int i = t; i < n; i += BT) Z[i + (int64_t)j * ldz] = 0.0;
+    gsync();
+    const int lf = dc_leaves(nleaf, Z, ldz, s);
+    __syncthreads();
+    if (t == 0) s.ival[2] = 0;
+    __syncthreads();
+    if (lf) s.ival[2] = 1;
+    gsync();
+    if (s.ival[2]) return 1;
+    for (int d = depth - 1; d >= 0; --d) {
+        const int step = nleaf >> d;
+        for (int i = 0; i < (1 << d); ++i) {
+            const int o = s.lb[i * step], N = s.lb[(i + 1) * step] - o, n1 = s.lb[i * step + step / 2] - o;
+            const int rc = dc_merge(o, N, n1, Z, ldz, X, U, Y, R, s);
+            if (rc) return rc;
+        }
+    }
+    return 0;
+}
+
 __device__ int64_t solve_one(const BProb& p, Lds& s) {
     const int t = threadIdx.x;
     const int n = (int)p.n;
@@ -710,12 +1074,9 @@ __device__ int64_t solve_one(const BProb& p, Lds& s) {
         }
     gsync();
     wg_sytrd(n, A, n, p.tau, s);
-    for (int j = 0; j < n; ++j)
-        for (int i = t; i < n; i += BT) Z[i + (int64_t)j * n] = (i == j) ? 1.0 : 0.0;
+    const int dc = wg_stedc(n, Z, n, W, p.U, p.Y, p.R, s);
     gsync();
-    const int ql = wg_steql(n, Z, n, s);
-    gsync();
-    if (ql) return -(int64_t)ql;
+    if (dc) return -(int64_t)dc;
     wg_ormtr(n, A, n, p.tau, Z, n, W, s);
     wg_trsm_lt(n, n, L, n, Z, n, s);  // V = L^-T Z
     for (int i = t; i < n; i += BT) {
@@ -783,7 +1144,7 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         const int64_t n = ops[i]->n;
         const int64_t wsz = std::max<int64_t>(n * n, 3 * (int64_t)PB * n + PB * PB);
         off[i] = tot;
-        tot += al(n * n) * 3 + al(wsz) + al(n);
+        tot += al(n * n) * 5 + al(wsz) + al(4 * n) + al(n);
     }
     DevBuf bws, bprobs, border, bnext, bstat;
     FL_HIP(ctx, bws.alloc(sizeof(double) * tot));
@@ -809,7 +1170,10 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         b.A = w + al(n * n);
         b.Z = w + 2 * al(n * n);
         b.W = w + 3 * al(n * n);
-        b.tau = b.W + al(wsz);
+        b.U = b.W + al(wsz);
+        b.Y = b.U + al(n * n);
+        b.R = b.Y + al(n * n);
+        b.tau = b.R + al(4 * n);
     }
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
@@ -866,7 +1230,7 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
             fl_fail(ctx, code,
                     std::string("fl_eigensolve_batched: problem ") + std::to_string(i) +
                         (code == FL_ENOTSPD ? ": M is not positive definite at pivot "
-                                            : ": QL did not converge at eigenvalue ") +
+                                            : ": the tridiagonal eigensolver did not converge, code ") +
                         std::to_string(st[i] > 0 ? st[i] : -st[i]));
         }
     }
