@@ -532,22 +532,59 @@ hipError_t q2_apply_t(hipStream_t s, int64_t n, int b, const double* V2, const d
     return hipSuccess;
 }
 
+// Q1 = H_0 H_1 ... H_{np-1}, H_p = I - V_p T_p V_p^T.  QG consecutive panels
+// are merged into one block reflector (their V columns are adjacent in V1,
+// and the rows of a later panel above its own first row are zero), with
+//   T = [T_a  -T_a (V_a^T V_b) T_b; 0  T_b]
+// built panel by panel, so that each group costs three GEMMs with inner or
+// outer dimension QG b instead of b.  Groups are applied last first.
+constexpr int QG = 4;
+
 template <class T>
 hipError_t q1_apply_t(hipStream_t s, int64_t n, int b, const T* V1, int64_t ldv, const T* T1, T* Z, int64_t ldz,
                       int64_t ncols, T* work) {
-    int64_t np = fl_sy2sb_panels(n, b);
+    const int64_t np = fl_sy2sb_panels(n, b);
+    const int64_t KM = (int64_t)QG * b;
+    T* Gr = work;          // KM x KM: V^T V of the group
+    T* Tg = Gr + KM * KM;  // KM x KM: merged T
+    T* Yb = Tg + KM * KM;  // KM x b
+    T* W1 = Yb + KM * b;   // KM x ncols
+    T* W2 = W1 + KM * ncols;
     hipError_t e;
-    for (int64_t p = np - 1; p >= 0; --p) {
-        const int64_t c0 = p * b, r0 = c0 + b, m = n - r0;
-        const int kref = (int)std::min<int64_t>(b, m - 1);
-        if (kref <= 0) continue;
-        const T* Vp = V1 + r0 + c0 * ldv;
-        const T* Tp = T1 + p * (int64_t)b * b;
-        T* W1 = work;
-        T* W2 = work + (int64_t)b * ncols;
-        if ((e = fl_gemm_t(s, 1, 0, kref, ncols, m, 1.0, Vp, ldv, Z + r0, ldz, 0.0, W1, b))) return e;
-        if ((e = fl_gemm_t(s, 0, 0, kref, ncols, kref, 1.0, Tp, b, W1, b, 0.0, W2, b))) return e;
-        if ((e = fl_gemm_t(s, 0, 0, m, ncols, kref, -1.0, Vp, ldv, W2, b, 1.0, Z + r0, ldz))) return e;
+    auto kref_of = [&](int64_t p) { return (int)std::min<int64_t>(b, n - (p * b + b) - 1); };
+    for (int64_t gi = FL_DIV_UP(np, QG) - 1; gi >= 0; --gi) {
+        const int64_t p0 = gi * QG, p1 = std::min<int64_t>(np, p0 + QG);
+        const int64_t c0 = p0 * b, r0 = c0 + b, m = n - r0;
+        int64_t K = 0;
+        for (int64_t p = p0; p < p1; ++p) K += kref_of(p);
+        if (K <= 0) continue;
+        const T* V = V1 + r0 + c0 * ldv;
+        const T* Tm = T1 + p0 * (int64_t)b * b;
+        int64_t ldt = b;
+        if (p1 - p0 > 1) {
+            if ((e = fl_gemm_t(s, 1, 0, K, K, m, 1.0, V, ldv, V, ldv, 0.0, Gr, KM))) return e;
+            if ((e = hipMemsetAsync(Tg, 0, sizeof(T) * KM * KM, s))) return e;
+            int64_t off = 0;
+            for (int64_t p = p0; p < p1; ++p) {
+                const int kq = kref_of(p);
+                if ((e = hipMemcpy2DAsync(Tg + off + off * KM, sizeof(T) * KM, T1 + p * (int64_t)b * b, sizeof(T) * b,
+                                          sizeof(T) * kq, kq, hipMemcpyDeviceToDevice, s)))
+                    return e;
+                if (off > 0) {
+                    // Tg[0:off, off:off+kq] = -Tg[0:off, 0:off] (V_a^T V_b) T_b
+                    if ((e = fl_gemm_t(s, 0, 0, off, kq, off, 1.0, Tg, KM, Gr + off * KM, KM, 0.0, Yb, KM))) return e;
+                    if ((e = fl_gemm_t(s, 0, 0, off, kq, kq, -1.0, Yb, KM, Tg + off + off * KM, KM, 0.0, Tg + off * KM,
+                                       KM)))
+                        return e;
+                }
+                off += kq;
+            }
+            Tm = Tg;
+            ldt = KM;
+        }
+        if ((e = fl_gemm_t(s, 1, 0, K, ncols, m, 1.0, V, ldv, Z + r0, ldz, 0.0, W1, KM))) return e;
+        if ((e = fl_gemm_t(s, 0, 0, K, ncols, K, 1.0, Tm, ldt, W1, KM, 0.0, W2, KM))) return e;
+        if ((e = fl_gemm_t(s, 0, 0, m, ncols, K, -1.0, V, ldv, W2, KM, 1.0, Z + r0, ldz))) return e;
     }
     return hipSuccess;
 }
@@ -574,8 +611,16 @@ hipError_t fl_q2_apply_f(hipStream_t s, int64_t n, int b, const double* V2, cons
     return q2_apply_t<float>(s, n, b, V2, tau2, maxt, work, Z, ldz, ncols);
 }
 
-// Z (n x ncols) := Q1 Z, Q1 = prod over panels of (I - V_p T_p V_p^T).
-// work: >= 2 * b * ncols elements.
+// Work elements of fl_q1_apply for ncols columns.
+int64_t fl_q1_work_elems(int64_t n, int b, int64_t ncols) {
+    (void)n;
+    const int64_t KM = (int64_t)QG * b;
+    return 2 * KM * KM + KM * b + 2 * KM * ncols;
+}
+
+// Z (n x ncols) := Q1 Z, Q1 = prod over panels of (I - V_p T_p V_p^T).  V1
+// must be zero above each panel's first reflector row.  work:
+// fl_q1_work_elems(n, b, ncols) elements.
 hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
                        int64_t ldz, int64_t ncols, double* work) {
     return q1_apply_t<double>(s, n, b, V1, ldv, T1, Z, ldz, ncols, work);

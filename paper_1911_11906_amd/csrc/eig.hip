@@ -21,6 +21,7 @@ hipError_t fl_sb2st(hipStream_t s, int64_t n, int b, double* AB, int64_t ldab, d
                     double* tau2, int* prog, int grid, int* abort);
 // backtrans.hip
 int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt);
+int64_t fl_q1_work_elems(int64_t n, int b, int64_t ncols);
 hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt, double* T2,
                        double* Z, int64_t ldz, int64_t ncols);
 hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
@@ -102,9 +103,10 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
     DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
     FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
     FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
+    FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(double) * (size_t)n * n, s));  // Q1 reads above each panel
     FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
     FL_HIP(ctx, btau1.alloc(sizeof(double) * (n + b)));
-    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), fl_q1_work_elems(n, b, n))));
     FL_HIP(ctx, bpart.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
     FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
     FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
@@ -162,9 +164,10 @@ int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int ba
     FL_HIP(ctx, bA.alloc(sizeof(float) * (size_t)n * n));
     FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
     FL_HIP(ctx, bV1.alloc(sizeof(float) * (size_t)n * n));
+    FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(float) * (size_t)n * n, s));  // Q1 reads above each panel
     FL_HIP(ctx, bT1.alloc(sizeof(float) * np * b * b));
     FL_HIP(ctx, btau1.alloc(sizeof(float) * (n + b)));
-    FL_HIP(ctx, bwork.alloc(sizeof(float) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+    FL_HIP(ctx, bwork.alloc(sizeof(float) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), fl_q1_work_elems(n, b, n))));
     FL_HIP(ctx, bpart.alloc(sizeof(float) * fl_sy2sb_part_elems(n)));
     FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
     FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
@@ -186,9 +189,10 @@ int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int ba
         // FP64 band reduction; its block reflectors are rounded to FP32 for Q1
         DevBuf bV1d, bT1d, btau1d, bworkd, bpartd;
         FL_HIP(ctx, bV1d.alloc(sizeof(double) * (size_t)n * n));
+        FL_HIP(ctx, hipMemsetAsync(bV1d.p, 0, sizeof(double) * (size_t)n * n, s));
         FL_HIP(ctx, bT1d.alloc(sizeof(double) * np * b * b));
         FL_HIP(ctx, btau1d.alloc(sizeof(double) * (n + b)));
-        FL_HIP(ctx, bworkd.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+        FL_HIP(ctx, bworkd.alloc(sizeof(double) * fl_sy2sb_work_elems(n, b)));
         FL_HIP(ctx, bpartd.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
         FL_HIP(ctx, fl_sy2sb(s, n, b, C, ldc, bV1d.as<double>(), n, bT1d.as<double>(), btau1d.as<double>(),
                              bworkd.as<double>(), bpartd.as<double>(), bcnt.as<unsigned>(), abort_flag));
@@ -270,9 +274,28 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
         return fl_fail(ctx, FL_ENOTSPD, "fl_eigensolve: M is not positive definite at pivot " + std::to_string(piv));
     }
     FL_HIP(ctx, tm.mark(FL_STAGE_SYGST));
-    FL_HIP(ctx, hipMemcpyAsync(C, op->K, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
-    int rc = fl_sygst_device(ctx, n, L, ld, blinv.as<double>(), C, ld, bwork.as<double>());
-    if (rc) return rc;
+    // With a sparse K: X = L^-1 explicitly (in place of L), Y = K X^T as a
+    // sparse product, and only the lower triangle of C = X Y, skipping X's
+    // zero tiles (about half the work of two dense triangular solves);
+    // V = X^T Z at the end is one GEMM.  Dense K: two triangular solves.
+    const bool sparse = op->rowptr && op->kval && op->nnz <= (n * n) / 64;
+    DevBuf bXt, bY;
+    int rc = FL_OK;
+    if (sparse) {
+        FL_HIP(ctx, bXt.alloc(sizeof(double) * (size_t)n * n));
+        FL_HIP(ctx, bY.alloc(sizeof(double) * (size_t)n * n));
+        double* Xt = bXt.as<double>();
+        double* Y = bY.as<double>();
+        FL_HIP(ctx, fl_trtri_inplace(s, n, L, ld, blinv.as<double>(), Y));
+        FL_HIP(ctx, fl_transpose(s, n, n, L, ld, Xt, n));
+        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->kval, n, Xt, n, Y, n));
+        FL_HIP(ctx, fl_dgemm_tri(s, 0, 0, n, n, n, 1.0, L, ld, Y, n, 0.0, C, ld, 1, FL_KT_A_LOWER));
+        FL_HIP(ctx, fl_mirror_lower(s, n, C, ld));
+    } else {
+        FL_HIP(ctx, hipMemcpyAsync(C, op->K, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
+        rc = fl_sygst_device(ctx, n, L, ld, blinv.as<double>(), C, ld, bwork.as<double>());
+        if (rc) return rc;
+    }
     if (precision == FL_MIXED)
         rc = fl_syevd_mixed_device(ctx, n, C, ld, band, opts ? (opts->mixed_flags & FL_MIXED_FP32_BAND) : 0,
                                    op->theta, op->V, ld, info, leaf, &tm);
@@ -283,7 +306,14 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
         return rc;
     }
     FL_HIP(ctx, tm.mark(FL_STAGE_TRSM));
-    FL_HIP(ctx, fl_trsm_llt(s, n, n, L, ld, blinv.as<double>(), op->V, ld, bwork.as<double>()));
+    if (sparse) {
+        // V = X^T Z (X^T upper triangular)
+        double* Y = bY.as<double>();
+        FL_HIP(ctx, fl_dgemm_tri(s, 1, 0, n, n, n, 1.0, L, ld, op->V, ld, 0.0, Y, n, 0, FL_KT_A_UPPER));
+        FL_HIP(ctx, fl_copy_matrix(s, n, n, Y, n, op->V, ld));
+    } else {
+        FL_HIP(ctx, fl_trsm_llt(s, n, n, L, ld, blinv.as<double>(), op->V, ld, bwork.as<double>()));
+    }
     // refinement: by default two steps after FP32 back-transforms (the first
     // meets the eigenvalue and orthonormality targets; the second removes the
     // second-order error between close low modes, which dominates the
@@ -357,9 +387,10 @@ int fl_dsytrd_2stage(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, d
     DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
     FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
     FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
+    FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(double) * (size_t)n * n, s));  // Q1 reads above each panel
     FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
     FL_HIP(ctx, btau1.alloc(sizeof(double) * (n + b)));
-    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), 2 * (int64_t)b * n)));
+    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), fl_q1_work_elems(n, b, n))));
     FL_HIP(ctx, bpart.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
     FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
     FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
