@@ -213,6 +213,25 @@ hipError_t fl_trsm_llt(hipStream_t s, int64_t k, int64_t m, const double* L, int
     return fl_trsm_llt(s, k1, m, L, ldl, Linv, B, ldb, work);
 }
 
+// In place: L (n x n lower, ld ldl) := L^-1, strict upper triangle zeroed.
+// Linv: the diagonal leaves' inverses from fl_potrf.  With the same
+// 128-aligned splits, [L11 0; L21 L22]^-1 = [X11 0; -X22 L21 X11  X22], the
+// two products skipping the zero tiles of the triangular factors.
+// work: >= n * n / 2 doubles.
+hipError_t fl_trtri_inplace(hipStream_t s, int64_t n, double* L, int64_t ldl, const double* Linv, double* work) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e;
+    if (n <= LB) return fl_copy_matrix(s, n, n, Linv, LB, L, ldl);
+    const int64_t n1 = split_point(n), n2 = n - n1;
+    double* L22 = L + n1 + n1 * ldl;
+    if ((e = fl_trtri_inplace(s, n1, L, ldl, Linv, work))) return e;
+    if ((e = fl_trtri_inplace(s, n2, L22, ldl, Linv + (n1 / LB) * LB * LB, work))) return e;
+    // T = L21 X11 (X11 lower), then X21 = -X22 T (X22 lower)
+    if ((e = fl_dgemm_tri(s, 0, 0, n2, n1, n1, 1.0, L + n1, ldl, L, ldl, 0.0, work, n2, 0, FL_KT_B_LOWER))) return e;
+    if ((e = fl_dgemm_tri(s, 0, 0, n2, n1, n2, -1.0, L22, ldl, work, n2, 0.0, L + n1, ldl, 0, FL_KT_A_LOWER))) return e;
+    return fl_fill(s, n1, n2, 0.0, L + n1 * ldl, ldl);
+}
+
 hipError_t fl_trtri_leaves(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Linv) {
     if (n <= 0) return hipSuccess;
     trtri_leaves_kernel<<<(unsigned)FL_DIV_UP(n, LB), LT, 0, s>>>(n, L, ldl, Linv);

@@ -29,6 +29,14 @@ struct GemmProblem {
 hipError_t fl_dgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                     int64_t ldc, int lower = 0);
+// GEMM with one triangular operand whose zero part is skipped tile by tile:
+// kt = FL_KT_A_LOWER (op(A)[i][k] = 0 for k > i), FL_KT_A_UPPER (for k < i),
+// FL_KT_B_LOWER (op(B)[k][j] = 0 for k < j), FL_KT_NONE (plain).  The zero
+// part must hold zeros (only whole tiles are skipped).  No split-K.
+enum { FL_KT_NONE = 0, FL_KT_A_LOWER = 1, FL_KT_A_UPPER = 2, FL_KT_B_LOWER = 3 };
+hipError_t fl_dgemm_tri(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                        int64_t ldc, int lower, int kt);
 // Batched GEMM over problems held in DEVICE memory; grid sized for the largest
 // (max_m, max_n) and each tile exits early if outside its own problem.
 hipError_t fl_dgemm_batched(hipStream_t s, int ta, int tb, const GemmProblem* dev_probs, int count,
@@ -60,4 +68,6 @@ hipError_t fl_copy_matrix(hipStream_t s, int64_t m, int64_t n, const double* A, 
 hipError_t fl_transpose(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, double* B,
                         int64_t ldb);
 hipError_t fl_fill(hipStream_t s, int64_t m, int64_t n, double v, double* A, int64_t lda);
+// upper triangle of the n x n A := transpose of its strict lower triangle
+hipError_t fl_mirror_lower(hipStream_t s, int64_t n, double* A, int64_t lda);
 hipError_t fl_set_identity(hipStream_t s, int64_t n, double* A, int64_t lda);

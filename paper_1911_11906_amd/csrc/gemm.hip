@@ -34,15 +34,25 @@ struct Prob {
     T alpha, beta;
 };
 
-template <class T, bool TA, bool TB, bool LOWER>
+// KT: zero structure of a triangular operand, used to shorten each tile's k
+// range: FL_KT_A_LOWER op(A)[i][k] = 0 for k > i; FL_KT_A_UPPER for k < i;
+// FL_KT_B_LOWER op(B)[k][j] = 0 for k < j.  (BM = BN is a multiple of the
+// k-step, so the shortened ranges stay aligned.)
+template <class T, bool TA, bool TB, bool LOWER, int KT = FL_KT_NONE>
 __global__ __launch_bounds__(NT) void gemm_kernel(Prob<T> g) {
     __shared__ T As[TileLds<GKB, GNBUF>::A];
     __shared__ T Bs[TileLds<GKB, GNBUF>::B];
     const int64_t bi = blockIdx.x, bj = blockIdx.y;
     if (LOWER && (bi + 1) * BM <= bj * BN) return;  // tile strictly above the diagonal
-    BPlainT<T> bsrc{g.B, g.ldb, TB};
-    tile_gemm<TA, !TB, BPlainT<T>, GKB, GNBUF, T>(g.m, g.n, g.k, g.A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi, bj,
-                                                  As, Bs);
+    int64_t kb = 0, ke = g.k;
+    if (KT == FL_KT_A_LOWER) ke = std::min<int64_t>(g.k, (bi + 1) * BM);
+    if (KT == FL_KT_A_UPPER) kb = std::min<int64_t>(g.k, bi * BM);
+    if (KT == FL_KT_B_LOWER) kb = std::min<int64_t>(g.k, bj * BN);
+    const T* A = TA ? g.A + kb : g.A + kb * g.lda;
+    const T* B = TB ? g.B + kb * g.ldb : g.B + kb;
+    BPlainT<T> bsrc{B, g.ldb, TB};
+    tile_gemm<TA, !TB, BPlainT<T>, GKB, GNBUF, T>(g.m, g.n, ke - kb, A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi,
+                                                  bj, As, Bs);
 }
 
 // Split-K: slice z of the k range into its own partial product P_z (beta = 0).
@@ -133,6 +143,24 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
     return hipGetLastError();
 }
 
+template <int KT, bool TA, bool TB>
+hipError_t launch_tri(hipStream_t s, const Prob<double>& g, int lower) {
+    dim3 grid((unsigned)FL_DIV_UP(g.m, BM), (unsigned)FL_DIV_UP(g.n, BN));
+    if (lower)
+        gemm_kernel<double, TA, TB, true, KT><<<grid, NT, 0, s>>>(g);
+    else
+        gemm_kernel<double, TA, TB, false, KT><<<grid, NT, 0, s>>>(g);
+    return hipGetLastError();
+}
+
+template <int KT>
+hipError_t tri_any(hipStream_t s, int ta, int tb, const Prob<double>& g, int lower) {
+    if (!ta && !tb) return launch_tri<KT, false, false>(s, g, lower);
+    if (!ta && tb) return launch_tri<KT, false, true>(s, g, lower);
+    if (ta && !tb) return launch_tri<KT, true, false>(s, g, lower);
+    return launch_tri<KT, true, true>(s, g, lower);
+}
+
 template <class T>
 hipError_t gemm_any(hipStream_t s, int ta, int tb, const Prob<T>& g, int lower) {
     if (!ta && !tb) return launch<T, false, false>(s, g, lower);
@@ -174,6 +202,23 @@ __global__ void transpose_kernel(int64_t m, int64_t n, const double* __restrict_
     }
 }
 
+// A(i, j) = A(j, i) for i < j (upper from lower), 32 x 32 tiles through LDS.
+__global__ void mirror_lower_kernel(int64_t n, double* A, int64_t lda) {
+    __shared__ double tile[32][33];
+    const int64_t bi = blockIdx.x, bj = blockIdx.y;  // source tile (bi, bj) with bi >= bj
+    if (bi < bj) return;
+    const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bi * 32 + tx, j = bj * 32 + r;
+        if (i < n && j < n) tile[r][tx] = A[i + j * lda];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = bj * 32 + tx, j = bi * 32 + r;  // destination (i, j) = source (j, i)
+        if (i < n && j < n && i < j) A[i + j * lda] = tile[tx][r];
+    }
+}
+
 __global__ void fill_kernel(int64_t m, int64_t n, double v, double* A, int64_t lda) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
@@ -200,6 +245,20 @@ hipError_t fl_dgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t
     if (k <= 0 && beta == 1.0) return hipSuccess;
     Prob<double> g{m, n, k, A, lda, B, ldb, C, ldc, alpha, beta};
     return gemm_any<double>(s, ta, tb, g, lower);
+}
+
+hipError_t fl_dgemm_tri(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                        int64_t ldc, int lower, int kt) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (k <= 0 && beta == 1.0) return hipSuccess;
+    Prob<double> g{m, n, k, A, lda, B, ldb, C, ldc, alpha, beta};
+    switch (kt) {
+        case FL_KT_A_LOWER: return tri_any<FL_KT_A_LOWER>(s, ta, tb, g, lower);
+        case FL_KT_A_UPPER: return tri_any<FL_KT_A_UPPER>(s, ta, tb, g, lower);
+        case FL_KT_B_LOWER: return tri_any<FL_KT_B_LOWER>(s, ta, tb, g, lower);
+        default: return gemm_any<double>(s, ta, tb, g, lower);
+    }
 }
 
 hipError_t fl_dgemm_batched(hipStream_t s, int ta, int tb, const GemmProblem* probs, int count, int64_t max_m,
@@ -249,6 +308,13 @@ hipError_t fl_transpose(hipStream_t s, int64_t m, int64_t n, const double* A, in
     if (m <= 0 || n <= 0) return hipSuccess;
     dim3 grid((unsigned)FL_DIV_UP(m, 32), (unsigned)FL_DIV_UP(n, 32));
     transpose_kernel<<<grid, dim3(32, 8), 0, s>>>(m, n, A, lda, B, ldb);
+    return hipGetLastError();
+}
+
+hipError_t fl_mirror_lower(hipStream_t s, int64_t n, double* A, int64_t lda) {
+    if (n <= 1) return hipSuccess;
+    dim3 grid((unsigned)FL_DIV_UP(n, 32), (unsigned)FL_DIV_UP(n, 32));
+    mirror_lower_kernel<<<grid, dim3(32, 8), 0, s>>>(n, A, lda);
     return hipGetLastError();
 }
 

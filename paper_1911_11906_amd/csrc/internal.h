@@ -117,6 +117,7 @@ hipError_t fl_trsm_lln(hipStream_t s, int64_t k, int64_t m, const double* L, int
 hipError_t fl_trsm_llt(hipStream_t s, int64_t k, int64_t m, const double* L, int64_t ldl, const double* Linv,
                        double* B, int64_t ldb, double* work);
 hipError_t fl_trtri_leaves(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Linv);
+hipError_t fl_trtri_inplace(hipStream_t s, int64_t n, double* L, int64_t ldl, const double* Linv, double* work);
 hipError_t fl_symmetrize(hipStream_t s, int64_t n, double* A, int64_t lda);
 int fl_sygst_device(fl_ctx* ctx, int64_t n, const double* L, int64_t ldl, const double* Linv, double* K,
                     int64_t ldk, double* work);
