@@ -17,6 +17,10 @@ import torch
 from . import _lib
 from ._lib import FlEigInfo, FlEigOpts, FraclapError
 
+# kept at import: module globals (sys included) may already be None when a
+# destructor runs during interpreter shutdown
+_finalizing = sys.is_finalizing
+
 P = ctypes.c_void_p
 
 
@@ -73,7 +77,7 @@ class Context:
 
     def __del__(self):
         # no library calls while the interpreter (and the HIP runtime) shut down
-        if sys.is_finalizing():
+        if _finalizing is None or _finalizing():
             return
         try:
             self.close()
@@ -211,7 +215,7 @@ class Operator:
             self.ptr = P()
 
     def __del__(self):
-        if sys.is_finalizing():
+        if _finalizing is None or _finalizing():
             return
         try:
             self.close()
