@@ -27,11 +27,10 @@ namespace {
 constexpr int BT = 512;                    // threads per workgroup (8 waves)
 constexpr int NMAX = 1024;                 // largest problem
 constexpr int PB = 32;                     // panel / reflector block width
-constexpr int TM = 64, TN = 128, TK = 16;  // GEMM tile (4 x 4 outputs per thread)
+constexpr int TM = 64, TN = 128, TK = 32;  // GEMM tile: eight waves of 32 x 32, k-slab 32
 constexpr int RPT = NMAX / BT;             // rows per thread in the tridiagonalisation
 constexpr int DCL = 32;                    // largest leaf of the divide and conquer
 constexpr int SU = 8;                      // columns per chunk in the tridiagonalisation's update
-static_assert(TM * TN == 16 * BT, "one 4 x 4 register tile per thread");
 constexpr double EPS = 2.220446049250313e-16;
 
 // The workgroup routines below are kept as separate (noinline) functions:
@@ -96,80 +95,95 @@ __device__ double wg_sum(double v, Lds& s) {
 }
 
 // C (m x n) = alpha op(A) op(B) + beta C, column-major, op = transpose when
-// ta / tb.  C must not overlap A or B.
+// ta / tb.  C must not overlap A or B.  Tiles of 64 x 128 on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64): wave w owns the 32 x 32 block
+// (w % 2, w / 2); the MFMA "A" operand is fed from op(B) and "B" from op(A),
+// so accumulator register r of lane l holds C[16 ti + l % 16][16 tj + l / 16
+// + 4 r] and the 16 lanes of a row group store consecutive rows.  The next
+// k-slab is loaded into registers (unconditionally, indices clamped into the
+// operands) while the current one is multiplied from LDS.
 __device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int64_t lda,
                         const double* B, int64_t ldb, double beta, double* C, int64_t ldc, Lds& s) {
     if (m <= 0 || n <= 0) return;
-    const int t = threadIdx.x;
-    const int r0 = (t & 15) * 4, c0 = (t >> 4) * 4;
+    constexpr int NA = TM * TK / BT, NB = TN * TK / BT;
+    static_assert(NA * BT == TM * TK && NB * BT == TN * TK && BT == 512, "eight waves, 64 x 128 tiles");
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int lr = lane >> 4, lc = lane & 15;
+    const int wi = wave & 1, wj = wave >> 1;
     const int tiles_m = (m + TM - 1) / TM, tiles_n = (n + TN - 1) / TN;
     for (int tile = 0; tile < tiles_m * tiles_n; ++tile) {
         const int i0 = (tile % tiles_m) * TM, j0 = (tile / tiles_m) * TN;
-        double acc[4][4];
+        d4_t acc[2][2];
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-        for (int k0 = 0; k0 < k; k0 += TK) {
-            __syncthreads();
+            for (int y = 0; y < 2; ++y) acc[x][y] = d4_t{0, 0, 0, 0};
+        double ra[NA], rb[NB];
+        unsigned okm = 0;  // validity of the loaded elements, applied when staged
+        auto gload = [&](int k0) {
+            okm = 0;
 #pragma unroll
-            for (int q = 0; q < (TM * TK) / BT; ++q) {
+            for (int q = 0; q < NA; ++q) {
                 const int e = t + BT * q;
-                int i, kk;
-                if (!ta) {
-                    i = e % TM;
-                    kk = e / TM;
-                } else {
-                    kk = e % TK;
-                    i = e / TK;
-                }
+                const int i = ta ? e / TK : e % TM, kk = ta ? e % TK : e / TM;
                 const int gi = i0 + i, gk = k0 + kk;
-                double a = 0.0;
-                if (gi < m && gk < k) a = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
-                s.As[kk][i] = a;
+                okm |= (gi < m && gk < k ? 1u : 0u) << q;
+                const int ci = gi < m ? gi : m - 1, ck = gk < k ? gk : k - 1;
+                ra[q] = ta ? A[ck + (int64_t)ci * lda] : A[ci + (int64_t)ck * lda];
             }
 #pragma unroll
-            for (int q = 0; q < (TN * TK) / BT; ++q) {
+            for (int q = 0; q < NB; ++q) {
                 const int e = t + BT * q;
-                int j, kb;
-                if (!tb) {
-                    kb = e % TK;
-                    j = e / TK;
-                } else {
-                    j = e % TN;
-                    kb = e / TN;
-                }
-                const int gj = j0 + j, gk2 = k0 + kb;
-                double b = 0.0;
-                if (gj < n && gk2 < k) b = tb ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb];
-                s.Bs[kb][j] = b;
+                const int j = tb ? e % TN : e / TK, kb = tb ? e / TN : e % TK;
+                const int gj = j0 + j, gk = k0 + kb;
+                okm |= (gj < n && gk < k ? 1u : 0u) << (NA + q);
+                const int cj = gj < n ? gj : n - 1, ck = gk < k ? gk : k - 1;
+                rb[q] = tb ? B[cj + (int64_t)ck * ldb] : B[ck + (int64_t)cj * ldb];
+            }
+        };
+        if (k > 0) gload(0);
+        for (int k0 = 0; k0 < k; k0 += TK) {
+            __syncthreads();  // the previous slab has been consumed
+#pragma unroll
+            for (int q = 0; q < NA; ++q) {
+                const int e = t + BT * q;
+                s.As[ta ? e % TK : e / TM][ta ? e / TK : e % TM] = ((okm >> q) & 1u) ? ra[q] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = t + BT * q;
+                s.Bs[tb ? e / TN : e % TK][tb ? e % TN : e / TK] = ((okm >> (NA + q)) & 1u) ? rb[q] : 0.0;
             }
             __syncthreads();
-#pragma unroll 4
-            for (int kk = 0; kk < TK; ++kk) {
-                double a[4], b[4];
+            if (k0 + TK < k) gload(k0 + TK);
 #pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[x] = s.As[kk][r0 + x];
-                    b[x] = s.Bs[kk][c0 + x];
+            for (int k4 = 0; k4 < TK; k4 += 4) {
+                double fa[2], fb[2];
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    fa[x] = s.Bs[k4 + lr][wj * 32 + 16 * x + lc];
+                    fb[x] = s.As[k4 + lr][wi * 32 + 16 * x + lc];
                 }
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
+                for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+                    for (int tj = 0; tj < 2; ++tj)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[tj], fb[ti], acc[ti][tj], 0, 0, 0);
             }
         }
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int gj = j0 + c0 + y;
-            if (gj >= n) continue;
+        for (int ti = 0; ti < 2; ++ti) {
+            const int gi = i0 + wi * 32 + 16 * ti + lc;
+            if (gi >= m) continue;
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                const int gi = i0 + r0 + x;
-                if (gi >= m) continue;
-                double* cp = C + gi + (int64_t)gj * ldc;
-                *cp = (beta == 0.0) ? alpha * acc[x][y] : alpha * acc[x][y] + beta * *cp;
-            }
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gj = j0 + wj * 32 + 16 * tj + lr + 4 * r;
+                    if (gj >= n) continue;
+                    double* cp = C + gi + (int64_t)gj * ldc;
+                    *cp = (beta == 0.0) ? alpha * acc[ti][tj][r] : alpha * acc[ti][tj][r] + beta * *cp;
+                }
         }
     }
     gsync();
