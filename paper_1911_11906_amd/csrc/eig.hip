@@ -37,7 +37,7 @@ hipError_t fl_q1_apply_f(hipStream_t s, int64_t n, int b, const float* V1, int64
 int fl_stedc_device(fl_ctx* ctx, int64_t n, double* d, const double* e, double* Zout, int64_t ldz, int leaf);
 // refine.hip
 int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t ldx, int max_iters, double tol,
-                     fl_eig_info* info);
+                     fl_eig_info* info, int64_t partial);
 
 namespace {
 
@@ -68,6 +68,8 @@ struct StageTimer {
         if (ev.size() >= 2 && hipEventElapsedTime(&tot, ev.front(), ev.back()) == hipSuccess) info->total_ms = tot;
     }
 };
+
+constexpr int64_t REFINE_LOW = 2048;  // columns of the refinement steps after the first
 
 int clamp_band(int64_t n, int band) {
     int b = band > 0 ? band : 64;
@@ -328,7 +330,11 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
         bL.release();  // L and C are not needed any more: room for the refinement buffers
         bC.release();
         FL_HIP(ctx, tm.mark(FL_STAGE_REFINE));
-        rc = fl_refine_device(ctx, op, op->theta, op->V, ld, iters, tol, info);
+        // after the first (full) step the remaining error that matters for
+        // the fractional solutions sits in the couplings among the low
+        // modes: later steps work on the lowest REFINE_LOW columns only
+        // (after an FP32 band reduction every step is full)
+        rc = fl_refine_device(ctx, op, op->theta, op->V, ld, iters, tol, info, fp32_band ? 0 : REFINE_LOW);
         if (rc) {
             if (info) {
                 info->status = rc;

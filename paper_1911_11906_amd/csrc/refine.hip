@@ -23,6 +23,15 @@
 // used: at large n it would treat most of the upper spectrum as one cluster.
 // After the last step each column is scaled to unit M-norm and the
 // eigenvalues are the Rayleigh quotients of the columns.
+//
+// Partial steps (partial > 0): every step after the first works on the
+// lowest `partial` columns only, X_L <- X_L + X_L E_LL with R, S restricted
+// to those columns.  After one full step the off-diagonal error left between
+// modes i and j is second order, about (first-step error)^2 / gap_ij; in a
+// fractional solution a rotation between i and j enters weighted by
+// |lambda_i^(-a/2) - lambda_j^(-a/2)|, which is large only among the low
+// modes, and a combination of low modes stays orthogonal to the high ones.
+// The partial step costs O(n partial^2) instead of O(n^3).
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -206,7 +215,7 @@ inline dim3 g2(int64_t m, int64_t n) {
 // most; stops early when max |I - X^T M X| <= tol.  theta (n) receives the
 // refined eigenvalues, ascending (columns of X permuted to match).
 int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t ldx, int max_iters, double tol,
-                     fl_eig_info* info) {
+                     fl_eig_info* info, int64_t partial) {
     hipStream_t s = ctx->stream;
     const int64_t n = op->n;
     const int64_t ld = n;
@@ -235,11 +244,13 @@ int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t l
     const bool verbose = getenv("FRACLAP_VERBOSE") != nullptr;
     const dim3 gm((unsigned)FL_DIV_UP(n, 256), (unsigned)std::min<int64_t>(n, 1024));
     std::vector<double> hb((size_t)gm.x * gm.y);
-    auto reduce_max = [&](double* out) -> int {
-        FL_HIP(ctx, hipMemcpyAsync(hb.data(), bmax, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
+    // max over the per-block maxima of a launch on grid g
+    auto reduce_max = [&](const dim3& g, double* out) -> int {
+        const size_t cnt = (size_t)g.x * g.y;
+        FL_HIP(ctx, hipMemcpyAsync(hb.data(), bmax, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
         FL_HIP(ctx, hipStreamSynchronize(s));
         double m = 0.0;
-        for (double v : hb) m = std::max(m, v);
+        for (size_t q = 0; q < cnt; ++q) m = std::max(m, hb[q]);
         *out = m;
         return FL_OK;
     };
@@ -247,23 +258,27 @@ int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t l
     double resid = -1.0;
     bool updated = false;  // X changed since theta was last computed
     for (int it = 0; it < max_iters; ++it) {
-        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->kval, n, X, ldx, KX, ld));
-        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, n, X, ldx, MX, ld));
+        // the first step works on every column; later steps, if partial > 0,
+        // only on the lowest `partial` columns (see the header)
+        const int64_t kc = (it == 0 || partial <= 0) ? n : std::min<int64_t>(n, partial);
+        const dim3 gk((unsigned)FL_DIV_UP(kc, 256), (unsigned)std::min<int64_t>(kc, 1024));
+        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->kval, kc, X, ldx, KX, ld));
+        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, kc, X, ldx, MX, ld));
         // S and X^T M X are symmetric: only their lower triangles are formed
-        FL_HIP(ctx, fl_dgemm(s, 1, 0, n, n, n, 1.0, X, ldx, KX, ld, 0.0, S, ld, 1));
-        FL_HIP(ctx, fl_dgemm(s, 1, 0, n, n, n, 1.0, X, ldx, MX, ld, 0.0, R0, ld, 1));
-        diag_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, S, R0, ld, lam);
+        FL_HIP(ctx, fl_dgemm(s, 1, 0, kc, kc, n, 1.0, X, ldx, KX, ld, 0.0, S, ld, 1));
+        FL_HIP(ctx, fl_dgemm(s, 1, 0, kc, kc, n, 1.0, X, ldx, MX, ld, 0.0, R0, ld, 1));
+        diag_kernel<<<(unsigned)FL_DIV_UP(kc, 256), 256, 0, s>>>(kc, S, R0, ld, lam);
         FL_HIP(ctx, hipGetLastError());
-        FL_HIP(ctx, hipMemcpyAsync(theta, lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        FL_HIP(ctx, hipMemcpyAsync(theta, lam, sizeof(double) * kc, hipMemcpyDeviceToDevice, s));
         updated = false;
-        maxabs_offid_kernel<<<gm, 256, 0, s>>>(n, R0, ld, bmax);
+        maxabs_offid_kernel<<<gk, 256, 0, s>>>(kc, R0, ld, bmax);
         FL_HIP(ctx, hipGetLastError());
         double mr = 0.0, lmax = 0.0;
-        if (int rc = reduce_max(&mr)) return rc;
-        maxabs_kernel<<<gm, 256, 0, s>>>(n, 1, lam, n, bmax);
+        if (int rc = reduce_max(gk, &mr)) return rc;
+        maxabs_kernel<<<gk, 256, 0, s>>>(kc, 1, lam, kc, bmax);
         FL_HIP(ctx, hipGetLastError());
-        if (int rc = reduce_max(&lmax)) return rc;
-        resid = mr;
+        if (int rc = reduce_max(gk, &lmax)) return rc;
+        if (kc == n) resid = mr;
         if (mr <= tol) break;
         // delta: below this gap the rounding of S (about sqrt(n) eps max|lambda|)
         // divided by the gap would rotate by more than tau, so such pairs count
@@ -274,18 +289,19 @@ int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t l
                                       std::sqrt((double)n) * 2.220446049250313e-16 / tau) * lmax;
         const double gnear = 1e-5 * lmax;
         FL_HIP(ctx, hipMemsetAsync(nclus, 0, sizeof(unsigned long long), s));
-        const dim3 ge((unsigned)FL_DIV_UP(n, ET), (unsigned)FL_DIV_UP(n, ET));
-        ebuild_kernel<<<ge, 256, 0, s>>>(n, S, R0, ld, lam, delta, gnear, tau, E, n, nclus);
+        const dim3 ge((unsigned)FL_DIV_UP(kc, ET), (unsigned)FL_DIV_UP(kc, ET));
+        ebuild_kernel<<<ge, 256, 0, s>>>(kc, S, R0, ld, lam, delta, gnear, tau, E, n, nclus);
         FL_HIP(ctx, hipGetLastError());
-        maxabs_kernel<<<gm, 256, 0, s>>>(n, n, E, n, bmax);
+        maxabs_kernel<<<gk, 256, 0, s>>>(kc, kc, E, n, bmax);
         FL_HIP(ctx, hipGetLastError());
         double emax = 0.0;
-        if (int rc = reduce_max(&emax)) return rc;
+        if (int rc = reduce_max(gk, &emax)) return rc;
         if (verbose) {
             unsigned long long nc = 0;
             FL_HIP(ctx, hipMemcpy(&nc, nclus, sizeof(nc), hipMemcpyDeviceToHost));
-            fprintf(stderr, "[fraclap] refine step %d: max|I - X^T M X| %.3e  max|E| %.3e  tau-clustered pairs %llu\n",
-                    it, mr, emax, nc);
+            fprintf(stderr,
+                    "[fraclap] refine step %d on %lld columns: max|I - X^T M X| %.3e  max|E| %.3e  tau-clustered pairs %llu\n",
+                    it, (long long)kc, mr, emax, nc);
         }
         if (emax * 6.0e-8 <= 5e-13) {
             // X += X E on the FP32 matrix cores: the product's rounding,
@@ -293,15 +309,15 @@ int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t l
             // for orthonormality and residual (and enters the eigenvalues
             // only squared)
             float* Ef = reinterpret_cast<float*>(MX);  // M X is consumed: reuse its space
-            FL_HIP(ctx, fl_d2s(s, n, n, X, ldx, Xf, n));
-            FL_HIP(ctx, fl_d2s(s, n, n, E, n, Ef, n));
-            FL_HIP(ctx, fl_sgemm(s, 0, 0, n, n, n, 1.0f, Xf, n, Ef, n, 0.0f, XEf, n));
-            add_f_kernel<<<g2(n, n), 256, 0, s>>>(n, n, XEf, n, X, ldx);
+            FL_HIP(ctx, fl_d2s(s, n, kc, X, ldx, Xf, n));
+            FL_HIP(ctx, fl_d2s(s, kc, kc, E, n, Ef, kc));
+            FL_HIP(ctx, fl_sgemm(s, 0, 0, n, kc, kc, 1.0f, Xf, n, Ef, kc, 0.0f, XEf, n));
+            add_f_kernel<<<g2(n, kc), 256, 0, s>>>(n, kc, XEf, n, X, ldx);
             FL_HIP(ctx, hipGetLastError());
         } else {
             // X += X E in FP64: X_old copied into the (consumed) M X buffer
-            FL_HIP(ctx, hipMemcpy2DAsync(MX, ld * 8, X, ldx * 8, n * 8, n, hipMemcpyDeviceToDevice, s));
-            FL_HIP(ctx, fl_dgemm(s, 0, 0, n, n, n, 1.0, MX, ld, E, n, 1.0, X, ldx));
+            FL_HIP(ctx, hipMemcpy2DAsync(MX, ld * 8, X, ldx * 8, n * 8, kc, hipMemcpyDeviceToDevice, s));
+            FL_HIP(ctx, fl_dgemm(s, 0, 0, n, kc, kc, 1.0, MX, ld, E, n, 1.0, X, ldx));
         }
         updated = true;
         ++iters;

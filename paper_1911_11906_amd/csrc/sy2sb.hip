@@ -94,13 +94,19 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_s_waitcnt(0);
         if (!grid_barrier(counter, (unsigned)(c + 1) * G, abort)) return;
-        // reduce the partials of all workgroups (fixed order)
-        if (t < 64) {
+        // reduce the partials of all workgroups in a fixed order (the same
+        // in every workgroup): row group q sums workgroups q, q+4, ..., the
+        // four sums are added in LDS; the loads are independent, so they are
+        // issued ahead of the additions
+        {
             T acc = T(0);
-            const T* pp = part + (size_t)par * G * 64 + t;
-            for (unsigned w = 0; w < G; ++w) acc += pp[(size_t)w * 64];
-            wv[t] = acc;
+            const T* pp = part + (size_t)par * G * 64 + lane;
+#pragma unroll 8
+            for (unsigned w = (unsigned)grp; w < G; w += 4) acc += pp[(size_t)w * 64];
+            red[grp][lane] = acc;
         }
+        __syncthreads();
+        if (t < 64) wv[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
         __syncthreads();
         if (t == 0) {
             const T x0 = prow[par * 64 + c];
