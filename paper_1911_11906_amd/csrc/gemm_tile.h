@@ -76,10 +76,29 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __res
     const int wi = wave & 1, wj = wave >> 1;
     const int64_t i0 = bi * BM, j0 = bj * BN;
     acc_t acc[4][4];
+    // beta = +-1 with alpha = +-1: C (times beta / alpha, exact) is loaded into
+    // the accumulators before the k loop, so that its read overlaps the first
+    // operand loads instead of following the last product
+    const bool pre = (beta == T(1) || beta == T(-1)) && (alpha == T(1) || alpha == T(-1));
+    {
+        const int plr = (t & 63) >> 4, plc = t & 15;
+        const T f = beta * alpha;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) {
+            const int64_t gi = i0 + wi * 64 + a * 16 + plc;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+            for (int b = 0; b < 4; ++b) {
+                acc[a][b] = acc_t{0, 0, 0, 0};
+                if (pre && gi < m) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t gj = j0 + wj * 64 + b * 16 + Mfma<T>::row(plr, r);
+                        if (gj < n) acc[a][b][r] = f * C[gi + gj * ldc];
+                    }
+                }
+            }
+        }
+    }
     constexpr int NA = BM * KB / NT, NB = BN * KB / NT;
     T ra[NA], rb[NB];
     typename BSrc::H bh[NB];
@@ -186,7 +205,7 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __res
                 if (gj >= n) continue;
                 T* cp = C + gi + gj * ldc;
                 T v = alpha * acc[ib][jb][r];
-                if (beta != T(0)) v += beta * (*cp);
+                if (!pre && beta != T(0)) v += beta * (*cp);
                 *cp = v;
             }
         }
