@@ -38,6 +38,7 @@ int fl_stedc_device(fl_ctx* ctx, int64_t n, double* d, const double* e, double* 
 // refine.hip
 int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t ldx, int max_iters, double tol,
                      fl_eig_info* info, int64_t partial);
+int fl_rayleigh_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t ldx);
 
 namespace {
 
@@ -68,8 +69,6 @@ struct StageTimer {
         if (ev.size() >= 2 && hipEventElapsedTime(&tot, ev.front(), ev.back()) == hipSuccess) info->total_ms = tot;
     }
 };
-
-constexpr int64_t REFINE_LOW = 2048;  // columns of the refinement steps after the first
 
 int clamp_band(int64_t n, int band) {
     int b = band > 0 ? band : 64;
@@ -330,11 +329,25 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
         bL.release();  // L and C are not needed any more: room for the refinement buffers
         bC.release();
         FL_HIP(ctx, tm.mark(FL_STAGE_REFINE));
-        // after the first (full) step the remaining error that matters for
-        // the fractional solutions sits in the couplings among the low
-        // modes: later steps work on the lowest REFINE_LOW columns only
-        // (after an FP32 band reduction every step is full)
-        rc = fl_refine_device(ctx, op, op->theta, op->V, ld, iters, tol, info, fp32_band ? 0 : REFINE_LOW);
+        rc = fl_refine_device(ctx, op, op->theta, op->V, ld, iters, tol, info, 0);
+        if (rc) {
+            if (info) {
+                info->status = rc;
+                info->index = FL_STAGE_REFINE;
+            }
+            return rc;
+        }
+    }
+    if (iters == 0 && op->rowptr && op->kval) {
+        // no refinement: the eigenvalues become the Rayleigh quotients of the
+        // computed vectors with the original pencil (the solver's normwise
+        // error, about eps ||C||, is large relative to the smallest
+        // eigenvalues; the quotients are accurate to second order)
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        bL.release();
+        bC.release();
+        FL_HIP(ctx, tm.mark(FL_STAGE_REFINE));
+        rc = fl_rayleigh_device(ctx, op, op->theta, op->V, ld);
         if (rc) {
             if (info) {
                 info->status = rc;

@@ -26,12 +26,10 @@
 //
 // Partial steps (partial > 0): every step after the first works on the
 // lowest `partial` columns only, X_L <- X_L + X_L E_LL with R, S restricted
-// to those columns.  After one full step the off-diagonal error left between
-// modes i and j is second order, about (first-step error)^2 / gap_ij; in a
-// fractional solution a rotation between i and j enters weighted by
-// |lambda_i^(-a/2) - lambda_j^(-a/2)|, which is large only among the low
-// modes, and a combination of low modes stays orthogonal to the high ones.
-// The partial step costs O(n partial^2) instead of O(n^3).
+// to those columns, at O(n partial^2) instead of O(n^3).  This removes the
+// second-order coupling error among the low modes (which dominates the
+// fractional solutions) but not that of near-degenerate pairs higher in the
+// spectrum, so the library's eigensolve uses full steps (partial = 0).
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -214,6 +212,34 @@ inline dim3 g2(int64_t m, int64_t n) {
 // eigenvectors of (K, M) given by op's CSR matrices.  max_iters steps at
 // most; stops early when max |I - X^T M X| <= tol.  theta (n) receives the
 // refined eigenvalues, ascending (columns of X permuted to match).
+// Eigenvalues of the columns of X as Rayleigh quotients x^T K x / x^T M x
+// with the sparse K and M, columns scaled to unit M-norm, then sorted
+// ascending (O(n^2) work: two sparse products and column reductions).
+int fl_rayleigh_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t ldx) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = op->n;
+    DevBuf bKX, bMX, bv;
+    FL_HIP(ctx, bKX.alloc(sizeof(double) * n * n));
+    FL_HIP(ctx, bMX.alloc(sizeof(double) * n * n));
+    FL_HIP(ctx, bv.alloc(sizeof(double) * n + sizeof(int64_t) * n));
+    double* KX = bKX.as<double>();
+    double* MX = bMX.as<double>();
+    double* lam2 = bv.as<double>();
+    int64_t* rank = reinterpret_cast<int64_t*>(lam2 + n);
+    FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->kval, n, X, ldx, KX, n));
+    FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, n, X, ldx, MX, n));
+    rq_kernel<<<(unsigned)n, 256, 0, s>>>(n, X, ldx, KX, MX, n, theta);
+    FL_HIP(ctx, hipGetLastError());
+    rank_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, theta, rank);
+    FL_HIP(ctx, hipGetLastError());
+    permute_kernel<<<g2(n, n), 256, 0, s>>>(n, rank, theta, X, ldx, lam2, KX, n);
+    FL_HIP(ctx, hipGetLastError());
+    FL_HIP(ctx, hipMemcpy2DAsync(X, ldx * 8, KX, n * 8, n * 8, n, hipMemcpyDeviceToDevice, s));
+    FL_HIP(ctx, hipMemcpyAsync(theta, lam2, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    FL_HIP(ctx, hipStreamSynchronize(s));
+    return FL_OK;
+}
+
 int fl_refine_device(fl_ctx* ctx, fl_op* op, double* theta, double* X, int64_t ldx, int max_iters, double tol,
                      fl_eig_info* info, int64_t partial) {
     hipStream_t s = ctx->stream;

@@ -57,9 +57,10 @@ def test_c2_fp64_q1_96(ctx):
     th, V = op.eigenpairs()
     cf = Q1Rectangle(96, 96)
     ref = cf.eigenvalues()
-    # plain FP64 (no refinement): a normwise-stable solver sits near
-    # eps * cond = 2.5e-12 for the smallest eigenvalue at this n
-    assert np.max(np.abs(th.cpu().numpy() - ref) / ref) <= 2.5e-12
+    # plain FP64 (no refinement): the eigenvalues are the Rayleigh quotients
+    # of the computed vectors with K and M, which meets the 1e-12 target (the
+    # solver's own values sit near eps * cond = 2.5e-12 at this n)
+    assert np.max(np.abs(th.cpu().numpy() - ref) / ref) <= 1e-12
     orth, res, M = orth_and_residual(op, th, V)
     assert orth <= 1e-11 and res <= 1e-12
     del V
