@@ -15,17 +15,30 @@
 namespace {
 using namespace fl_tile;
 
+// Y = A X for CSR A (n x n) and dense X (n x ncols).  A thread takes one row
+// and SPC columns, so each stored entry is read once per SPC columns.
+constexpr int SPC = 8;
 __global__ void spmm_kernel(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
                             const double* __restrict__ val, int64_t ncols, const double* __restrict__ X, int64_t ldx,
                             double* __restrict__ Y, int64_t ldy) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t p0 = rowptr[i], p1 = rowptr[i + 1];
-    for (int64_t c = blockIdx.y; c < ncols; c += gridDim.y) {
-        const double* x = X + c * ldx;
-        double s = 0.0;
-        for (int32_t p = p0; p < p1; ++p) s += val[p] * x[colidx[p]];
-        Y[i + c * ldy] = s;
+    for (int64_t c0 = (int64_t)blockIdx.y * SPC; c0 < ncols; c0 += (int64_t)gridDim.y * SPC) {
+        const int nc = (int)((ncols - c0) < SPC ? (ncols - c0) : SPC);
+        double s[SPC];
+#pragma unroll
+        for (int c = 0; c < SPC; ++c) s[c] = 0.0;
+        for (int32_t p = p0; p < p1; ++p) {
+            const double v = val[p];
+            const double* x = X + colidx[p] + c0 * ldx;
+#pragma unroll
+            for (int c = 0; c < SPC; ++c)
+                if (c < nc) s[c] += v * x[c * ldx];
+        }
+#pragma unroll
+        for (int c = 0; c < SPC; ++c)
+            if (c < nc) Y[i + (c0 + c) * ldy] = s[c];
     }
 }
 
@@ -129,7 +142,8 @@ __global__ void finite_kernel(int64_t m, int64_t n, const double* __restrict__ A
 hipError_t fl_spmm_csr(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* colidx, const double* val,
                        int64_t ncols, const double* X, int64_t ldx, double* Y, int64_t ldy) {
     if (n <= 0 || ncols <= 0) return hipSuccess;
-    dim3 grid((unsigned)FL_DIV_UP(n, 256), (unsigned)(ncols < 65535 ? ncols : 65535));
+    const int64_t cg = FL_DIV_UP(ncols, SPC);
+    dim3 grid((unsigned)FL_DIV_UP(n, 256), (unsigned)(cg < 65535 ? cg : 65535));
     spmm_kernel<<<grid, 256, 0, s>>>(n, rowptr, colidx, val, ncols, X, ldx, Y, ldy);
     return hipGetLastError();
 }

@@ -330,59 +330,99 @@ __global__ __launch_bounds__(256) void merge_rotate_kernel(const MergeDesc* __re
 
 // Secular equation: one thread per root.  Root k is stored as its nearer
 // pole org_k and the offset tau_k, so that d_j - lambda_k = (d_j - d_org) - tau
-// is available to full relative accuracy wherever it is needed.
-__global__ __launch_bounds__(128) void merge_secular_kernel(const MergeDesc* __restrict__ md, const MergeCounts* __restrict__ cnt,
+// is available to full relative accuracy wherever it is needed.  The poles
+// and rho z_j^2 are streamed through LDS in tiles shared by the workgroup;
+// each thread sums in ascending j as a plain loop would, and the workgroup
+// iterates until all its roots have converged.
+constexpr int STILE = 1024;
+constexpr int SNT = 256;
+__global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __restrict__ md, const MergeCounts* __restrict__ cnt,
                                                             const double* __restrict__ dk, const double* __restrict__ zk,
                                                             int64_t* rorg, double* rtau, double* lam, int* fail) {
+    __shared__ double sd[STILE], sw[STILE], sz[STILE];  // d_j, (rho z_j) z_j, z_j
     const MergeDesc g = md[blockIdx.y];
     const int64_t K = cnt[blockIdx.y].K;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
+    if ((int64_t)blockIdx.x * SNT >= K) return;  // uniform over the workgroup
+    const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+    const bool act = k < K;
     const double rho = cnt[blockIdx.y].rho2;
     const double* d = dk + g.o;
     const double* z = zk + g.o;
+    // sum over j of fn(j, d_j, w_j) in ascending j, tile by tile (every thread of the workgroup calls this)
+    auto stream = [&](auto&& fn) {
+        for (int64_t base = 0; base < K; base += STILE) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < STILE; q += SNT) {
+                const int64_t j = base + q;
+                if (j < K) {
+                    sd[q] = d[j];
+                    sw[q] = rho * z[j] * z[j];
+                    sz[q] = z[j];
+                }
+            }
+            __syncthreads();
+            const int lim = (int)((K - base) < STILE ? (K - base) : STILE);
+            fn(base, lim);
+        }
+    };
+    const int64_t kk = act ? k : 0;
+    // bracket: the sign of f at the midpoint between d_k and d_k+1 picks the
+    // nearer pole; the last root lies in (d_K-1, d_K-1 + rho |z|^2).  Both
+    // sums run in the same (workgroup-uniform) pass over the tiles.
+    const bool last = kk >= K - 1;
+    const double dkk = d[kk];
+    const double mid = last ? 0.0 : 0.5 * (d[kk + 1] - dkk);
+    double f0 = 1.0, zz = 0.0;
+    stream([&](int64_t, int lim) {
+        if (!last)
+            for (int q = 0; q < lim; ++q) f0 += sw[q] / ((sd[q] - dkk) - mid);
+        else
+            for (int q = 0; q < lim; ++q) zz += sz[q] * sz[q];
+    });
     int64_t org;
     double lo, hi;
-    if (k < K - 1) {
-        const double gap = d[k + 1] - d[k];
-        const double mid = 0.5 * gap;
-        double f = 1.0;
-        for (int64_t j = 0; j < K; ++j) f += rho * z[j] * z[j] / ((d[j] - d[k]) - mid);
-        if (f >= 0.0) {
-            org = k;
+    if (!last) {
+        if (f0 >= 0.0) {
+            org = kk;
             lo = 0.0;
             hi = mid;
         } else {
-            org = k + 1;
+            org = kk + 1;
             lo = -mid;
             hi = 0.0;
         }
     } else {
-        org = k;
-        double zz = 0.0;
-        for (int64_t j = 0; j < K; ++j) zz += z[j] * z[j];
+        org = kk;
         lo = 0.0;
         hi = rho * zz;
     }
     const double dorg = d[org];
-    const double Dk = d[k] - dorg;
-    const double Dk1 = (k < K - 1) ? d[k + 1] - dorg : 0.0;
+    const double Dk = d[kk] - dorg;
+    const double Dk1 = (kk < K - 1) ? d[kk + 1] - dorg : 0.0;
     double x = 0.5 * (lo + hi);
+    bool done = !act;
     bool converged = false;
     for (int it = 0; it < 400; ++it) {
+        if (!__syncthreads_or(done ? 0 : 1)) break;
         double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
-        for (int64_t j = 0; j <= k; ++j) {
-            double dl = (d[j] - dorg) - x;
-            double tq = rho * z[j] * z[j] / dl;
-            psi += tq;
-            dpsi += tq / dl;
-        }
-        for (int64_t j = k + 1; j < K; ++j) {
-            double dl = (d[j] - dorg) - x;
-            double tq = rho * z[j] * z[j] / dl;
-            phi += tq;
-            dphi += tq / dl;
-        }
+        stream([&](int64_t base, int lim) {
+            if (done) return;
+            // j <= kk contributes to psi, j > kk to phi
+            const int split = (int)std::min<int64_t>(std::max<int64_t>(kk + 1 - base, 0), lim);
+            for (int q = 0; q < split; ++q) {
+                const double dl = (sd[q] - dorg) - x;
+                const double tq = sw[q] / dl;
+                psi += tq;
+                dpsi += tq / dl;
+            }
+            for (int q = split; q < lim; ++q) {
+                const double dl = (sd[q] - dorg) - x;
+                const double tq = sw[q] / dl;
+                phi += tq;
+                dphi += tq / dl;
+            }
+        });
+        if (done) continue;
         const double f = 1.0 + psi + phi;
         if (f < 0.0)
             lo = x;
@@ -391,12 +431,14 @@ __global__ __launch_bounds__(128) void merge_secular_kernel(const MergeDesc* __r
         if (fabs(f) <= 8.0 * EPS * (1.0 + fabs(psi) + fabs(phi)) ||
             hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi))) {
             converged = true;
-            break;
+            done = true;
+            continue;
         }
+        // two-pole rational model through f, f' (poles d_k, d_k+1), safeguarded by the bracket
         const double dlk = Dk - x;
         const double bb = dpsi * dlk * dlk;
         double a2, a1, a0;
-        if (k < K - 1) {
+        if (kk < K - 1) {
             const double dlk1 = Dk1 - x;
             const double BB = dphi * dlk1 * dlk1;
             const double c = f - dpsi * dlk - dphi * dlk1;
@@ -412,16 +454,16 @@ __global__ __launch_bounds__(128) void merge_secular_kernel(const MergeDesc* __r
         double xn = 0.5 * (lo + hi);
         if (a2 == 0.0) {
             if (a1 != 0.0) {
-                double cnd = -a0 / a1;
+                const double cnd = -a0 / a1;
                 if (cnd > lo && cnd < hi) xn = cnd;
             }
         } else {
-            double disc = a1 * a1 - 4.0 * a2 * a0;
+            const double disc = a1 * a1 - 4.0 * a2 * a0;
             if (disc >= 0.0) {
-                double sq = sqrt(disc);
-                double q = -0.5 * (a1 + (a1 >= 0.0 ? sq : -sq));
-                double c1 = q / a2;
-                double c2 = (q != 0.0) ? a0 / q : c1;
+                const double sq = sqrt(disc);
+                const double q = -0.5 * (a1 + (a1 >= 0.0 ? sq : -sq));
+                const double c1 = q / a2;
+                const double c2 = (q != 0.0) ? a0 / q : c1;
                 if (c1 > lo && c1 < hi)
                     xn = c1;
                 else if (c2 > lo && c2 < hi)
@@ -430,6 +472,7 @@ __global__ __launch_bounds__(128) void merge_secular_kernel(const MergeDesc* __r
         }
         x = xn;
     }
+    if (!act) return;
     if (!converged) *fail = 2;
     lam[g.o + k] = dorg + x;
     rorg[g.o + k] = org;
@@ -706,7 +749,7 @@ int fl_stedc_device(fl_ctx* ctx, int64_t n, double* d, const double* e, double* 
         FL_HIP(ctx, hipGetLastError());
         merge_rotate_kernel<<<dim3(bx, nm), 256, 0, s>>>(md, cnt, ra, rb, rc, rs, Z, ldw);
         FL_HIP(ctx, hipGetLastError());
-        merge_secular_kernel<<<dim3((unsigned)FL_DIV_UP(Nmax, 128), nm), 128, 0, s>>>(md, cnt, dk, zk, rorg, rtau,
+        merge_secular_kernel<<<dim3((unsigned)FL_DIV_UP(Nmax, SNT), nm), SNT, 0, s>>>(md, cnt, dk, zk, rorg, rtau,
                                                                                       lam, fail);
         FL_HIP(ctx, hipGetLastError());
         merge_zhat_kernel<<<dim3(bx, nm), 256, 0, s>>>(md, cnt, dk, zk, rorg, rtau, zh);
