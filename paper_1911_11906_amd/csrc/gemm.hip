@@ -55,6 +55,27 @@ __global__ __launch_bounds__(NT) void gemm_kernel(Prob<T> g) {
                                                   bj, As, Bs);
 }
 
+// Products with at most 64 columns: 256 x 64 tiles (four waves along M), so
+// no half of each tile multiplies padding.  Split along k when the tiles are
+// too few to fill the chip.
+constexpr int TKB = 16, TWM = 4, TBM = 64 * TWM, TBN = 64;
+template <class T, bool TA, bool TB>
+__global__ __launch_bounds__(NT) void gemm_thin_kernel(Prob<T> g, int64_t kc, T* P) {
+    __shared__ T As[TileLds<TKB, 1, TWM>::A];
+    __shared__ T Bs[TileLds<TKB, 1, TWM>::B];
+    const int64_t z = blockIdx.z;
+    const int64_t koff = z * kc;
+    const int64_t ks = (g.k - koff) < kc ? (g.k - koff) : kc;
+    const T* A = TA ? g.A + koff : g.A + koff * g.lda;
+    const T* B = TB ? g.B + koff * g.ldb : g.B + koff;
+    BPlainT<T> bsrc{B, g.ldb, TB};
+    // P: partial product of slice z (beta = 0) into the split-K workspace; else C directly
+    const bool split = P != nullptr;
+    tile_gemm<TA, !TB, BPlainT<T>, TKB, 1, T, TWM>(g.m, g.n, split ? (ks > 0 ? ks : 0) : g.k, A, g.lda, bsrc, g.alpha,
+                                                   split ? T(0) : g.beta, split ? P + z * g.m * g.n : g.C,
+                                                   split ? g.m : g.ldc, blockIdx.x, 0, As, Bs);
+}
+
 // Split-K: slice z of the k range into its own partial product P_z (beta = 0).
 template <class T, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void gemm_splitk_kernel(Prob<T> g, int64_t kc, T* P) {
@@ -116,6 +137,30 @@ void* splitk_ws(int dev) {
 
 template <class T, bool TA, bool TB>
 hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
+    if (!lower && g.n <= TBN && g.m >= 2 * TBM) {
+        const int64_t tmt = FL_DIV_UP(g.m, TBM);
+        int64_t S = 1;
+        T* P = nullptr;
+        if (tmt < 384 && g.k >= 512) {
+            S = std::min<int64_t>({FL_DIV_UP(768, tmt), g.k / 256, 32});
+            while (S > 1 && S * g.m * g.n * (int64_t)sizeof(T) > SPLITK_WS_BYTES) --S;
+            int dev = 0;
+            P = (S > 1 && hipGetDevice(&dev) == hipSuccess) ? (T*)splitk_ws(dev) : nullptr;
+            if (!P) S = 1;
+        }
+        if (S > 1) {
+            int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), TKB) * TKB;
+            S = FL_DIV_UP(g.k, kc);
+            gemm_thin_kernel<T, TA, TB><<<dim3((unsigned)tmt, 1, (unsigned)S), NT, 0, s>>>(g, kc, P);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            dim3 rg((unsigned)FL_DIV_UP(g.m, 256), (unsigned)std::min<int64_t>(g.n, 65535));
+            splitk_reduce_kernel<T><<<rg, 256, 0, s>>>(g.m, g.n, (int)S, P, g.beta, g.C, g.ldc);
+            return hipGetLastError();
+        }
+        gemm_thin_kernel<T, TA, TB><<<dim3((unsigned)tmt, 1, 1), NT, 0, s>>>(g, g.k, nullptr);
+        return hipGetLastError();
+    }
     const int64_t tm = FL_DIV_UP(g.m, BM), tn = FL_DIV_UP(g.n, BN);
     const int64_t tiles = tm * tn;
     // few output tiles and a long k: split k so that the chip fills up

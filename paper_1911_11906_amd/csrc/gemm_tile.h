@@ -36,11 +36,13 @@ constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int SA = BM + 2;  // LDS row strides (doubles)
 constexpr int SB = BN + 2;
 constexpr int NT = 256;
-// LDS doubles needed by tile_gemm<.., KB, NBUF>
-template <int KB, int NBUF>
+// LDS doubles needed by tile_gemm<.., KB, NBUF, T, WM>: WM waves along M
+// (workgroup tile 64 WM x 64 (4 / WM); WM = 2: 128 x 128, WM = 4: 256 x 64
+// for products with at most 64 columns)
+template <int KB, int NBUF, int WM = 2>
 struct TileLds {
-    static constexpr int A = NBUF * KB * SA;
-    static constexpr int B = NBUF * KB * SB;
+    static constexpr int A = NBUF * KB * (64 * WM + 2);
+    static constexpr int B = NBUF * KB * (64 * (4 / WM) + 2);
 };
 // (elements of the tile's element type)
 
@@ -66,14 +68,15 @@ typedef BPlainT<double> BPlain;
 
 // KB: k-step; NBUF: LDS buffers (2 = double buffered, one barrier per step;
 // 1 = register prefetch, two barriers per step, half the LDS).
-template <bool TA, bool KFAST_B, class BSrc, int KB = 32, int NBUF = 1, class T = double>
+template <bool TA, bool KFAST_B, class BSrc, int KB = 32, int NBUF = 1, class T = double, int WM = 2>
 __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __restrict__ A, int64_t lda,
                                  const BSrc& bs, T alpha, T beta, T* __restrict__ C, int64_t ldc,
                                  int64_t bi, int64_t bj, T* As, T* Bs) {
     typedef typename Mfma<T>::acc acc_t;
+    constexpr int BM = 64 * WM, BN = 64 * (4 / WM), SA = BM + 2, SB = BN + 2;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const int wi = wave & 1, wj = wave >> 1;
+    const int wi = wave % WM, wj = wave / WM;
     const int64_t i0 = bi * BM, j0 = bj * BN;
     acc_t acc[4][4];
     // beta = +-1 with alpha = +-1: C (times beta / alpha, exact) is loaded into

@@ -29,7 +29,8 @@ def to_np(t):
 
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (300, 257, 129), (128, 128, 16), (513, 70, 1000)])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (300, 257, 129), (128, 128, 16), (513, 70, 1000),
+                                   (530, 64, 301), (700, 64, 600), (1100, 37, 3000)])
 def test_dgemm_matches_numpy(ctx, ta, tb, m, n, k):
     note("dgemm", ta, tb, m, n, k)
     rng = np.random.default_rng(m * 7 + n + k)
