@@ -4,6 +4,12 @@
 // A[c0+b:n, c0:c0+b] = (I - V T V^T) [R; 0].  The trailing block is then
 // updated two-sidedly on the matrix cores:
 //     X = A22 V T,  W = X - 1/2 V (T^T V^T X),  A22 -= V W^T + W V^T.
+// The rank-2b updates of up to QL consecutive panels are deferred and applied
+// as one rank-2 QL b product (a k of 2 b = 128 leaves each output tile's
+// load and store of C unamortised).  Until then the pending pairs (V_k, W_k)
+// are kept side by side in [V W] and [W V] (absolute rows), and a panel sees
+// the current matrix through them: its own columns get the pending update
+// before the QR, and A22 V = A22_stale V - [V W] ([W V]^T V).
 // The panel QR is one cooperative kernel: each workgroup keeps a 128-row slab
 // of the panel in registers; per column one grid barrier exchanges the
 // partial dot products (every workgroup then reduces them itself, in a fixed
@@ -96,13 +102,23 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         if (!grid_barrier(counter, (unsigned)(c + 1) * G, abort)) return;
         // reduce the partials of all workgroups in a fixed order (the same
         // in every workgroup): row group q sums workgroups q, q+4, ..., the
-        // four sums are added in LDS; the loads are independent, so they are
-        // issued ahead of the additions
+        // four sums are added in LDS.  The loads (which miss the cache after
+        // the barrier) are all issued before the first addition, RB at a
+        // time, with clamped, always valid addresses.
         {
+            constexpr int RB = 32;
             T acc = T(0);
             const T* pp = part + (size_t)par * G * 64 + lane;
-#pragma unroll 8
-            for (unsigned w = (unsigned)grp; w < G; w += 4) acc += pp[(size_t)w * 64];
+            for (unsigned w0 = (unsigned)grp; w0 < G; w0 += 4 * RB) {
+                T buf[RB];
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const unsigned w = w0 + 4 * q;
+                    buf[q] = pp[(size_t)(w < G ? w : 0) * 64];
+                }
+#pragma unroll
+                for (int q = 0; q < RB; ++q) acc += (w0 + 4 * q < G) ? buf[q] : T(0);
+            }
             red[grp][lane] = acc;
         }
         __syncthreads();
@@ -214,6 +230,8 @@ hipError_t copy_t(hipStream_t s, int64_t m, int64_t n, const T* A, int64_t lda, 
 int64_t fl_sy2sb_panels(int64_t n, int b);
 namespace {
 
+constexpr int QL = 8;  // panels per deferred trailing update
+
 template <class T>
 hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, int64_t ldv, T* T1, T* tau1, T* work,
                    T* part, unsigned* cnt, int* abort) {
@@ -223,11 +241,26 @@ hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, in
         e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * np, s);
         if (e != hipSuccess) return e;
     }
+    const int64_t kw = 2 * (int64_t)QL * b;  // columns of [V W] and [W V]
+    T* Gm = work;                            // b x b
+    T* S = Gm + (int64_t)b * b;              // b x b
+    T* R = S + (int64_t)b * b;               // b x b
+    T* Y = R + (int64_t)b * b;               // n x b (ld m)
+    T* X = Y + n * (int64_t)b;               // n x b (ld m)
+    T* VW = X + n * (int64_t)b;              // n x kw (ld n), slot k: [V_k W_k]
+    T* WV = VW + n * kw;                     // n x kw (ld n), slot k: [W_k V_k]
+    T* Z = WV + n * kw;                      // kw x b (ld kw)
+    int64_t p0 = 0;                          // first panel whose update is pending
     for (int64_t p = 0; p < np; ++p) {
         const int64_t c0 = p * b, r0 = c0 + b, m = n - r0;
         const int kb = b;
         const int kref = (int)std::min<int64_t>(b, m - 1);
         if (kref <= 0) break;
+        const int64_t kp = 2 * (p - p0) * (int64_t)b;  // pending columns of [V W]
+        // the panel's columns (diagonal block included) get the pending update
+        if (kp > 0 && (e = fl_gemm_t(s, 0, 1, n - c0, kb, kp, -1.0, VW + c0, n, WV + c0, n, 1.0, A + c0 + c0 * lda,
+                                     lda)))
+            return e;
         T* Pn = A + r0 + c0 * lda;
         T* Vp = V1 + r0 + c0 * ldv;
         T* tp = tau1 + c0;
@@ -243,32 +276,43 @@ hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, in
             if (e != hipSuccess) return e;
         }
         // T from G = V^T V
-        T* Gm = work;                 // b x b
         T* Tp = T1 + p * (int64_t)b * b;
         e = fl_gemm_t(s, 1, 0, kref, kref, m, 1.0, Vp, ldv, Vp, ldv, 0.0, Gm, b);
         if (e != hipSuccess) return e;
         larft_gram_kernel<T><<<1, 64, 0, s>>>(kref, Gm, b, tp, Tp, b);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // two-sided update of A22 = A[r0:n, r0:n]
+        // Y = A22 V with A22 = A[r0:n, r0:n] as of the last trailing update,
+        // corrected by the pending pairs
         T* A22 = A + r0 + r0 * lda;
-        T* Y = work + (int64_t)b * b;     // m x kref
-        T* X = Y + m * (int64_t)b;        // m x kref
-        T* VW = X + m * (int64_t)b;       // m x 2 kref : [V W]
-        T* WV = VW + 2 * m * (int64_t)b;  // m x 2 kref : [W V]
-        T* S = WV + 2 * m * (int64_t)b;   // kref x kref
-        T* R = S + (int64_t)b * b;        // kref x kref
-        if ((e = fl_gemm_t(s, 0, 0, m, kref, m, 1.0, A22, lda, Vp, ldv, 0.0, Y, m))) return e;   // Y = A22 V
+        if ((e = fl_gemm_t(s, 0, 0, m, kref, m, 1.0, A22, lda, Vp, ldv, 0.0, Y, m))) return e;
+        if (kp > 0) {
+            if ((e = fl_gemm_t(s, 1, 0, kp, kref, m, 1.0, WV + r0, n, Vp, ldv, 0.0, Z, kw))) return e;
+            if ((e = fl_gemm_t(s, 0, 0, m, kref, kp, -1.0, VW + r0, n, Z, kw, 1.0, Y, m))) return e;
+        }
         if ((e = fl_gemm_t(s, 0, 0, m, kref, kref, 1.0, Y, m, Tp, b, 0.0, X, m))) return e;      // X = Y T
         if ((e = fl_gemm_t(s, 1, 0, kref, kref, m, 1.0, Vp, ldv, X, m, 0.0, S, b))) return e;     // S = V^T X
         if ((e = fl_gemm_t(s, 1, 0, kref, kref, kref, 1.0, Tp, b, S, b, 0.0, R, b))) return e;   // R = T^T S
-        // W = X - 1/2 V R, written straight into both concatenations
-        if ((e = copy_t<T>(s, m, kref, X, m, VW + kref * m, m))) return e;
-        if ((e = fl_gemm_t(s, 0, 0, m, kref, kref, -0.5, Vp, ldv, R, b, 1.0, VW + kref * m, m))) return e;
-        if ((e = copy_t<T>(s, m, kref, Vp, ldv, VW, m))) return e;
-        if ((e = copy_t<T>(s, m, kref, VW + kref * m, m, WV, m))) return e;
-        if ((e = copy_t<T>(s, m, kref, Vp, ldv, WV + kref * m, m))) return e;
-        // A22 -= [V W] [W V]^T
-        if ((e = fl_gemm_t(s, 0, 1, m, m, 2 * kref, -1.0, VW, m, WV, m, 1.0, A22, lda))) return e;
+        // slot of this panel; a short last panel leaves columns of its slot
+        // unwritten, which must then hold zeros
+        T* vw = VW + kp * n;
+        T* wv = WV + kp * n;
+        if (kref < b) {
+            for (T* q : {vw, wv}) {
+                e = hipMemset2DAsync(q + r0, sizeof(T) * n, 0, sizeof(T) * m, 2 * b, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        // W = X - 1/2 V R, written straight into both slots
+        if ((e = copy_t<T>(s, m, kref, X, m, vw + b * n + r0, n))) return e;
+        if ((e = fl_gemm_t(s, 0, 0, m, kref, kref, -0.5, Vp, ldv, R, b, 1.0, vw + b * n + r0, n))) return e;
+        if ((e = copy_t<T>(s, m, kref, Vp, ldv, vw + r0, n))) return e;
+        if ((e = copy_t<T>(s, m, kref, vw + b * n + r0, n, wv + r0, n))) return e;
+        if ((e = copy_t<T>(s, m, kref, Vp, ldv, wv + b * n + r0, n))) return e;
+        // trailing update of the group: A[r0:n, r0:n] -= [V W] [W V]^T
+        if (p + 1 - p0 == QL || p + 1 == np) {
+            if ((e = fl_gemm_t(s, 0, 1, m, m, kp + 2 * b, -1.0, VW + r0, n, WV + r0, n, 1.0, A22, lda))) return e;
+            p0 = p + 1;
+        }
     }
     return hipSuccess;
 }
@@ -284,8 +328,9 @@ int64_t fl_sy2sb_panels(int64_t n, int b) {
 
 // Reduce the symmetric A (full storage, ld lda) to band width b.  V1 (n x n,
 // ld ldv) receives the explicit reflectors of every panel at the panel's own
-// rows/columns, T1 (np blocks of b x b) their T factors.  work: >= 4 n b + b*b
-// + 2 b*b doubles; part: fl_sy2sb_part_elems(n) doubles; cnt: >= np unsigned;
+// rows/columns (its entries above each panel must be zero on entry), T1 (np
+// blocks of b x b) their T factors.  work: fl_sy2sb_work_elems(n, b) elements
+// (about 4 QL n b); part: fl_sy2sb_part_elems(n) doubles; cnt: >= np unsigned;
 // abort: device flag raised if a cooperative wait was abandoned.
 hipError_t fl_sy2sb(hipStream_t s, int64_t n, int b, double* A, int64_t lda, double* V1, int64_t ldv, double* T1,
                     double* tau1, double* work, double* part, unsigned* cnt, int* abort) {
@@ -296,7 +341,10 @@ hipError_t fl_ssy2sb(hipStream_t s, int64_t n, int b, float* A, int64_t lda, flo
     return sy2sb_t<float>(s, n, b, A, lda, V1, ldv, T1, tau1, work, part, cnt, abort);
 }
 
-int64_t fl_sy2sb_work_elems(int64_t n, int b) { return 6 * n * (int64_t)b + 4 * (int64_t)b * b; }
+int64_t fl_sy2sb_work_elems(int64_t n, int b) {
+    const int64_t kw = 2 * (int64_t)QL * b;
+    return 3 * (int64_t)b * b + 2 * n * (int64_t)b + 2 * n * kw + kw * b;
+}
 int64_t fl_sy2sb_part_elems(int64_t n) { return 2 * FL_DIV_UP(n, PROWS) * 64 + 128; }
 
 hipError_t fl_extract_band(hipStream_t s, int64_t n, int b, const double* A, int64_t lda, double* AB, int64_t ldab) {
