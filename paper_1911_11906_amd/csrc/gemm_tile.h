@@ -9,6 +9,7 @@
 // waves of 64 x 64, operands staged k-major in LDS and double buffered.
 #pragma once
 #include "common.h"
+#include <type_traits>
 
 namespace fl_tile {
 
@@ -105,54 +106,62 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __res
     constexpr int NA = BM * KB / NT, NB = BN * KB / NT;
     T ra[NA], rb[NB];
     typename BSrc::H bh[NB];
-    bool bok[NB];
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
         int e = t + NT * r;
         int jj = KFAST_B ? e / KB : e % BN;
         int64_t gj = j0 + jj;
-        bok[r] = gj < n;
-        bh[r] = bs.col(bok[r] ? gj : j0);
+        bh[r] = bs.col(gj < n ? gj : n - 1);
     }
-    auto gload = [&](int64_t k0) {
+    // Operand loads are unconditional: rows of A beyond m and columns of B
+    // beyond n read a clamped, valid row / column (their products land in
+    // outputs that are never stored); only a partial last k-step clamps k and
+    // writes zeros for the rows past k.  No load sits in a branch, so the
+    // compiler need not wait for one before the next.
+    auto gload = [&](int64_t k0, auto edge) {
+        constexpr bool EDGE = decltype(edge)::value;
 #pragma unroll
         for (int r = 0; r < NA; ++r) {
             int e = t + NT * r;
             int ii, kk;
             if (!TA) { ii = e % BM; kk = e / BM; } else { kk = e % KB; ii = e / KB; }
             int64_t gi = i0 + ii, gk = k0 + kk;
-            T v = T(0);
-            if (gi < m && gk < k) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
-            ra[r] = v;
+            gi = gi < m ? gi : m - 1;
+            if (EDGE) gk = gk < k ? gk : k - 1;
+            ra[r] = TA ? A[gk + gi * lda] : A[gi + gk * lda];
         }
         // with KFAST_B every element a thread loads shares one k-row (t % KB)
         T ks = T(1);
-        if (BSrc::KSCALE && KFAST_B && k0 + (t % KB) < k) ks = bs.kscale(j0, k0 + (t % KB));
+        if (BSrc::KSCALE && KFAST_B) {
+            int64_t gk = k0 + (t % KB);
+            if (EDGE) gk = gk < k ? gk : k - 1;
+            ks = bs.kscale(j0, gk);
+        }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
             int e = t + NT * r;
-            int jj, kk;
-            if (KFAST_B) { kk = e % KB; jj = e / KB; } else { jj = e % BN; kk = e / BN; }
+            int kk = KFAST_B ? e % KB : e / BN;
             int64_t gk = k0 + kk;
-            (void)jj;
-            T v = (bok[r] && gk < k) ? bs.at(bh[r], gk) : T(0);
+            if (EDGE) gk = gk < k ? gk : k - 1;
+            T v = bs.at(bh[r], gk);
             rb[r] = BSrc::KSCALE ? v * ks : v;
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, int64_t k0, auto edge) {
+        constexpr bool EDGE = decltype(edge)::value;
 #pragma unroll
         for (int r = 0; r < NA; ++r) {
             int e = t + NT * r;
             int ii, kk;
             if (!TA) { ii = e % BM; kk = e / BM; } else { kk = e % KB; ii = e / KB; }
-            As[buf * KB * SA + kk * SA + ii] = ra[r];
+            As[buf * KB * SA + kk * SA + ii] = (EDGE && k0 + kk >= k) ? T(0) : ra[r];
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
             int e = t + NT * r;
             int jj, kk;
             if (KFAST_B) { kk = e % KB; jj = e / KB; } else { jj = e % BN; kk = e / BN; }
-            Bs[buf * KB * SB + kk * SB + jj] = rb[r];
+            Bs[buf * KB * SB + kk * SB + jj] = (EDGE && k0 + kk >= k) ? T(0) : rb[r];
         }
     };
     const int64_t nkt = FL_DIV_UP(k, KB);
@@ -173,26 +182,45 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __res
                     acc[ib][jb] = Mfma<T>::mma(fa[jb], fb[ib], acc[ib][jb]);
         }
     };
+    // k-step kt is partial only when it is the last one and KB does not divide k
+    const bool kpart = (k % KB) != 0;
+    auto is_edge = [&](int64_t kt) { return kpart && kt == nkt - 1; };
+    const std::true_type E1;
+    const std::false_type E0;
     if (NBUF == 2) {
         if (nkt > 0) {
-            gload(0);
-            sstore(0);
+            if (is_edge(0)) { gload(0, E1); sstore(0, 0, E1); }
+            else { gload(0, E0); sstore(0, 0, E0); }
         }
         __syncthreads();
         for (int64_t kt = 0; kt < nkt; ++kt) {
             const int cur = (int)(kt & 1);
-            if (kt + 1 < nkt) gload((kt + 1) * KB);
+            const bool nedge = is_edge(kt + 1);
+            if (kt + 1 < nkt) {
+                if (nedge) gload((kt + 1) * KB, E1);
+                else gload((kt + 1) * KB, E0);
+            }
             compute(As + cur * KB * SA, Bs + cur * KB * SB);
-            if (kt + 1 < nkt) sstore(1 - cur);
+            if (kt + 1 < nkt) {
+                if (nedge) sstore(1 - cur, (kt + 1) * KB, E1);
+                else sstore(1 - cur, (kt + 1) * KB, E0);
+            }
             __syncthreads();
         }
     } else {
-        if (nkt > 0) gload(0);
+        if (nkt > 0) {
+            if (is_edge(0)) gload(0, E1);
+            else gload(0, E0);
+        }
         for (int64_t kt = 0; kt < nkt; ++kt) {
             __syncthreads();
-            sstore(0);
+            if (is_edge(kt)) sstore(0, kt * KB, E1);
+            else sstore(0, kt * KB, E0);
             __syncthreads();
-            if (kt + 1 < nkt) gload((kt + 1) * KB);
+            if (kt + 1 < nkt) {
+                if (is_edge(kt + 1)) gload((kt + 1) * KB, E1);
+                else gload((kt + 1) * KB, E0);
+            }
             compute(As, Bs);
         }
     }
