@@ -99,12 +99,12 @@ struct BScaledUniform {
 };
 
 template <class BS>
-__global__ __launch_bounds__(NT) void scaled_gemm_kernel(int64_t n, int64_t ncol, const double* __restrict__ V,
+__global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void scaled_gemm_kernel(int64_t n, int64_t ncol, const double* __restrict__ V,
                                                          int64_t ldv, BS bs, double* __restrict__ U,
                                                          int64_t ldu) {
-    __shared__ double As[TileLds<32, 1>::A];
-    __shared__ double Bs[TileLds<32, 1>::B];
-    tile_gemm<false, true, BS, 32, 1>(n, ncol, n, V, ldv, bs, 1.0, 0.0, U, ldu, blockIdx.x, blockIdx.y, As, Bs);
+    __shared__ double As[TileLds<16, 1>::A];
+    __shared__ double Bs[TileLds<16, 1>::B];
+    tile_gemm<false, true, BS, 16, 1>(n, ncol, n, V, ldv, bs, 1.0, 0.0, U, ldu, blockIdx.x, blockIdx.y, As, Bs);
 }
 
 // galpha[b] = sum_k P[k,b] * (-0.5 ln theta_k) * W[k,b] * C[k,b]; one block per b,

@@ -20,7 +20,7 @@
 namespace {
 using namespace fl_tile;
 
-constexpr int GKB = 32, GNBUF = 1;  // k-step 32 with register prefetch (measured best on gfx950)
+constexpr int GKB = 16, GNBUF = 1;  // k-step 16 with register prefetch: fits two waves per SIMD
 
 template <class T>
 struct Prob {
@@ -39,7 +39,7 @@ struct Prob {
 // FL_KT_B_LOWER op(B)[k][j] = 0 for k < j.  (BM = BN is a multiple of the
 // k-step, so the shortened ranges stay aligned.)
 template <class T, bool TA, bool TB, bool LOWER, int KT = FL_KT_NONE>
-__global__ __launch_bounds__(NT) void gemm_kernel(Prob<T> g) {
+__global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void gemm_kernel(Prob<T> g) {
     __shared__ T As[TileLds<GKB, GNBUF>::A];
     __shared__ T Bs[TileLds<GKB, GNBUF>::B];
     const int64_t bi = blockIdx.x, bj = blockIdx.y;
@@ -57,7 +57,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(Prob<T> g) {
 
 // Products with at most 64 columns: 256 x 64 tiles (four waves along M), so
 // no half of each tile multiplies padding.  Split along k when the tiles are
-// too few to fill the chip.
+// too few to fill the chip.  (One wave per SIMD: the transposed variants
+// would spill at two.)
 constexpr int TKB = 16, TWM = 4, TBM = 64 * TWM, TBN = 64;
 template <class T, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void gemm_thin_kernel(Prob<T> g, int64_t kc, T* P) {
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(NT) void gemm_thin_kernel(Prob<T> g, int64_t kc, T*
 
 // Split-K: slice z of the k range into its own partial product P_z (beta = 0).
 template <class T, bool TA, bool TB>
-__global__ __launch_bounds__(NT) void gemm_splitk_kernel(Prob<T> g, int64_t kc, T* P) {
+__global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void gemm_splitk_kernel(Prob<T> g, int64_t kc, T* P) {
     __shared__ T As[TileLds<GKB, GNBUF>::A];
     __shared__ T Bs[TileLds<GKB, GNBUF>::B];
     const int64_t z = blockIdx.z;
@@ -106,7 +107,7 @@ __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int S, const T* __res
 }
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(NT) void dgemm_batched_kernel(const GemmProblem* __restrict__ probs) {
+__global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void dgemm_batched_kernel(const GemmProblem* __restrict__ probs) {
     __shared__ double As[TileLds<GKB, GNBUF>::A];
     __shared__ double Bs[TileLds<GKB, GNBUF>::B];
     const GemmProblem g = probs[blockIdx.z];

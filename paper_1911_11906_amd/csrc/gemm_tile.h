@@ -33,6 +33,11 @@ template <> struct Mfma<float> {
     static __device__ inline int row(int lr, int r) { return 4 * lr + r; }
 };
 
+// Tile kernels are compiled for two waves per SIMD (at most 256 registers per
+// lane, accumulators included), so two workgroups share a CU and one's LDS
+// staging and barriers overlap the other's matrix-core work.
+#define FL_TWO_WAVES_PER_SIMD __attribute__((amdgpu_waves_per_eu(2, 2)))
+
 constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int SA = BM + 2;  // LDS row strides (doubles)
 constexpr int SB = BN + 2;
