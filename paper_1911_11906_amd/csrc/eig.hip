@@ -112,10 +112,10 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
     FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
     FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
     FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
-    FL_HIP(ctx, bprog.alloc(sizeof(int) * (n + 2)));
+    FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
     FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
     double* e = be.as<double>();
-    int* abort_flag = bprog.as<int>() + n + 1;
+    int* abort_flag = bprog.as<int>() + 2 * n + 1;
     FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
 
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
@@ -173,11 +173,11 @@ int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int ba
     FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
     FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
     FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
-    FL_HIP(ctx, bprog.alloc(sizeof(int) * (n + 2)));
+    FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
     FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
     double* e = be.as<double>();
     float* A = bA.as<float>();
-    int* abort_flag = bprog.as<int>() + n + 1;
+    int* abort_flag = bprog.as<int>() + 2 * n + 1;
     FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
 
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
@@ -414,9 +414,9 @@ int fl_dsytrd_2stage(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, d
     FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
     FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
     FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
-    FL_HIP(ctx, bprog.alloc(sizeof(int) * (n + 2)));
+    FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
     FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
-    int* abort_flag = bprog.as<int>() + n + 1;
+    int* abort_flag = bprog.as<int>() + 2 * n + 1;
     FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
     FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, bV1.as<double>(), n, bT1.as<double>(), btau1.as<double>(), bwork.as<double>(),
                          bpart.as<double>(), bcnt.as<unsigned>(), abort_flag));

@@ -9,8 +9,13 @@
 // so the working band holds 2b sub-diagonals.  Task (i, j) touches
 // the blocks (R_j, R_{j-1}), (R_j, R_j) and (R_{j+1}, R_j); the blocks of task
 // (i-1, j') are the same blocks shifted up by one row and column, which meet
-// those of (i, j) only for j' in [j-1, j+2].  So (i, j) may start once sweep
-// i-1 has finished task j+2.
+// those of (i, j) only for j' in [j-1, j+2].  With (i-1, j+2) they share a
+// single element: the first entry of the column that (i-1, j+2) annihilates
+// (which becomes its beta), the last row and column of (i, j)'s block below.
+// So (i, j) may start once sweep i-1 has finished task j+1 and task j+2 has
+// formed its reflector and stored that column: each task publishes the
+// annihilated column right after its Householder step (progx) and the rest
+// of its blocks at its end (prog); the final write-back skips that column.
 //
 // One persistent cooperative launch: workgroup w runs sweeps w, w+G, ...;
 // each task stages its three b x b blocks in LDS; per-sweep progress
@@ -33,7 +38,7 @@ __device__ inline double band_get(const double* AB, int64_t ldab, int64_t r, int
 constexpr long SPIN_CAP = 20000000;  // bounded wait: every wave exits even if a predecessor stalls
 
 __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB, int64_t ldab, double* V2,
-                                                    double* tau2, int64_t maxt, int* prog, int* abort) {
+                                                    double* tau2, int64_t maxt, int* prog, int* progx, int* abort) {
     __shared__ double bufA[BMAX * LDB], bufB[BMAX * LDB];  // off-diagonal / below blocks (rotate roles)
     __shared__ double S[BMAX * LDB];                        // symmetric diagonal block (full)
     __shared__ double vv[BMAX], pv[BMAX], wv[BMAX], pb[BMAX];
@@ -53,10 +58,12 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
             if (t == 0) {
                 quit = 0;
                 if (i > 0) {
-                    int need = (int)((j + 3 < ntp) ? (j + 3) : ntp);
+                    const int need = (int)((j + 2 < ntp) ? (j + 2) : ntp);
+                    const int needx = (int)((j + 3 < ntp) ? (j + 3) : ntp);
                     long spins = 0;
                     // poll relaxed (no cache invalidation per poll), acquire once
-                    while (__hip_atomic_load(&prog[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    while (__hip_atomic_load(&prog[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need ||
+                           __hip_atomic_load(&progx[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < needx) {
                         __builtin_amdgcn_s_sleep(2);
                         if (++spins > SPIN_CAP || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                             __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -121,8 +128,19 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                     scale = 1.0 / (x0 - beta);
                 }
                 vv[t] = (t == 0) ? 1.0 : (t < L ? xr * scale : 0.0);
-                if (t < L) Boff[t] = (t == 0) ? beta : 0.0;
+                const double xn = (t == 0) ? beta : 0.0;
+                if (t < L) Boff[t] = xn;
                 if (t == 0) sc[1] = tauc;
+                // publish the annihilated column (column i for j = 0, else the
+                // first column of the block left of R_j): wave 0 waits for its
+                // own stores, then releases them with the flag
+                if (t < L) {
+                    const int64_t col = (j == 0) ? i : c0;
+                    AB[(r0 + t - col) + col * ldab] = xn;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_s_waitcnt(0);
+                if (t == 0) __hip_atomic_store(&progx[i], (int)(j + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
             const double tauc = sc[1];
@@ -172,11 +190,10 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                 }
             }
             __syncthreads();
-            // ---- write back
-            if (j == 0 && t < L) AB[(r0 + t - i) + i * ldab] = Boff[t];
+            // ---- write back (the annihilated column went out with progx)
             for (int e = t; e < BMAX * BMAX; e += NTH) {
                 const int r = e & (BMAX - 1), c = e >> 6;
-                if (j > 0 && r < L && c < b) AB[(r0 + r - (c0 + c)) + (c0 + c) * ldab] = Boff[r + c * LDB];
+                if (j > 0 && r < L && c >= 1 && c < b) AB[(r0 + r - (c0 + c)) + (c0 + c) * ldab] = Boff[r + c * LDB];
                 if (r < L && c < L && r >= c) AB[(r - c) + (r0 + c) * ldab] = S[r + c * LDB];
                 if (r < Lb && c < L) AB[(q0 + r - (r0 + c)) + (r0 + c) * ldab] = Bbl[r + c * LDB];
             }
@@ -210,18 +227,19 @@ int64_t fl_sb2st_maxt(int64_t n, int b) { return n >= 3 ? 1 + (n - 3) / b : 1; }
 
 // Band AB (lower, ld ldab >= 2b+1, zero below the first b+1 diagonals) ->
 // d, e.  V2 (n-2 sweeps x maxt tasks x b) and tau2 receive the reflectors.
-// prog: n ints of scratch; abort: device flag raised if a wait was abandoned.
+// prog: 2n ints of scratch; abort: device flag raised if a wait was abandoned.
 hipError_t fl_sb2st(hipStream_t s, int64_t n, int b, double* AB, int64_t ldab, double* d, double* e, double* V2,
                     double* tau2, int* prog, int grid, int* abort) {
     hipError_t err;
     if (n >= 3 && b > 1) {
-        if ((err = hipMemsetAsync(prog, 0, sizeof(int) * n, s)) != hipSuccess) return err;
+        if ((err = hipMemsetAsync(prog, 0, sizeof(int) * 2 * n, s)) != hipSuccess) return err;
         int64_t maxt = fl_sb2st_maxt(n, b);
         int64_t nsw = n - 2;
         unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nsw, grid));
         int64_t nn = n, lda = ldab, mt = maxt;
         int bb = b;
-        void* args[] = {&nn, &bb, &AB, &lda, &V2, &tau2, &mt, &prog, &abort};
+        int* progx = prog + n;
+        void* args[] = {&nn, &bb, &AB, &lda, &V2, &tau2, &mt, &prog, &progx, &abort};
         {
             KScope ks("sb2st", s);
             err = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(G), dim3(NTH), args, 0, s);
