@@ -378,16 +378,27 @@ __device__ void wg_make_w(int n, int64_t g0, int m, double tk, const double (&ac
 // s.dd and s.ee.  One pass over the trailing matrix per step: the rank-2
 // update of step k, A22 -= v w^T + w v^T, is fused with the product
 // A22' v' of step k+1 (A22' = A22 without its first row and column).
-// Rows t + q BT (q < RPT) of columns g0 + j0 .. g0 + j0 + SU - 1 (j < m).
-__device__ inline void sytrd_load_chunk(const double* A, int64_t lda, int64_t g0, int j0, int m, int n,
-                                        const bool (&own)[RPT], double (&buf)[SU][RPT]) {
+// The streamed matrix is addressed as global memory (a generic pointer would
+// make every access a flat one, counted against the LDS counter as well, and
+// the compiler then drains all loads before the first store of a chunk).
+typedef __attribute__((address_space(1))) double gdouble;
+
+// Rows t + q BT (q < RPT) of columns g0 + j0 .. g0 + j0 + SU - 1.  The loads
+// are unconditional, from a row and column clamped into the matrix, so none
+// sits in a branch; entries that are not the caller's (rows it does not own,
+// columns j >= m) are never used.
+__device__ inline void sytrd_load_chunk(const gdouble* A, int64_t lda, int64_t g0, int j0, int m, int n,
+                                        double (&buf)[SU][RPT]) {
     const int t = threadIdx.x;
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
-        const int j = j0 + u;
-        const double* col = A + (g0 + j) * lda;
+        const int j = (j0 + u < m) ? j0 + u : m - 1;
+        const gdouble* col = A + (g0 + j) * lda;
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) buf[u][q] = (j < m && own[q]) ? col[t + q * BT] : 0.0;
+        for (int q = 0; q < RPT; ++q) {
+            const int g = t + q * BT;
+            buf[u][q] = col[g < n ? g : n - 1];
+        }
     }
 }
 
@@ -478,16 +489,48 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
                 wi[q] = own[q] ? w[i] : 0.0;
                 acc[q] = 0.0;
             }
-            double cur[SU][RPT], nx[SU][RPT];
-            sytrd_load_chunk(A, lda, g0, 1, m, n, own, cur);
-            for (int j0 = 1; j0 < m; j0 += SU) {
-                if (j0 + SU < m) sytrd_load_chunk(A, lda, g0, j0 + SU, m, n, own, nx);
+            // Two chunk buffers in turn (no copies between them): while one
+            // is updated and stored, the loads of the next are in flight.
+            // Full chunk pairs run without branches, so that the compiler can
+            // count the loads still in flight instead of draining them: rows
+            // above the trailing block store their value back unchanged (no
+            // other thread touches row g), and a row past the matrix stores
+            // row t's final value to row t once more, after row t's store.
+            double ca[SU][RPT], cb[SU][RPT];
+            const gdouble* gA = (const gdouble*)A;
+            gdouble* wA = (gdouble*)A;
+            int64_t roff[RPT];
+            bool valid[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                valid[q] = t + q * BT < n;
+                roff[q] = valid[q] ? t + q * BT : t;
+            }
+            auto process = [&](const double (&cur)[SU][RPT], int j0) {
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int j = j0 + u;
+                    const double vj = v[j], wj = w[j], v2j = v2[j - 1];
+                    gdouble* col = wA + (g0 + j) * lda;
+                    double a0 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) {
+                        const double p1 = __dmul_rn(vi[q], wj), p2 = __dmul_rn(wi[q], vj);
+                        double a = own[q] ? __dsub_rn(cur[u][q], __dadd_rn(p1, p2)) : cur[u][q];
+                        if (q == 0) a0 = a;
+                        a = valid[q] ? a : a0;
+                        col[roff[q]] = a;
+                        acc[q] = fma(a, v2j, acc[q]);
+                    }
+                }
+            };
+            auto process_tail = [&](const double (&cur)[SU][RPT], int j0) {
 #pragma unroll
                 for (int u = 0; u < SU; ++u) {
                     const int j = j0 + u;
                     if (j < m) {
                         const double vj = v[j], wj = w[j], v2j = v2[j - 1];
-                        double* col = A + (g0 + j) * lda;
+                        gdouble* col = wA + (g0 + j) * lda;
 #pragma unroll
                         for (int q = 0; q < RPT; ++q) {
                             if (own[q]) {
@@ -499,10 +542,34 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
                         }
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < SU; ++u)
-#pragma unroll
-                    for (int q = 0; q < RPT; ++q) cur[u][q] = nx[u][q];
+            };
+            if (t < n) {
+                sytrd_load_chunk(gA, lda, g0, 1, m, n, ca);
+                int j0 = 1;
+                // (the first use of a buffer after the loop's back edge waits
+                // for every load, so the loop body holds two pairs)
+                for (; j0 + 4 * SU <= m; j0 += 4 * SU) {
+                    sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                    process(ca, j0);
+                    sytrd_load_chunk(gA, lda, g0, j0 + 2 * SU, m, n, ca);
+                    process(cb, j0 + SU);
+                    sytrd_load_chunk(gA, lda, g0, j0 + 3 * SU, m, n, cb);
+                    process(ca, j0 + 2 * SU);
+                    sytrd_load_chunk(gA, lda, g0, j0 + 4 * SU, m, n, ca);
+                    process(cb, j0 + 3 * SU);
+                }
+                if (j0 + 2 * SU <= m) {
+                    sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                    process(ca, j0);
+                    sytrd_load_chunk(gA, lda, g0, j0 + 2 * SU, m, n, ca);
+                    process(cb, j0 + SU);
+                    j0 += 2 * SU;
+                }
+                if (j0 < m) {
+                    sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                    process_tail(ca, j0);
+                    if (j0 + SU < m) process_tail(cb, j0 + SU);
+                }
             }
             // (d) w of step k+1
             wg_make_w(n, g0 + 1, m - 1, tk, acc, v2, s.wa[nxt], s);
