@@ -82,7 +82,8 @@ int grid_for_sb2st(int64_t n, int b) {
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
     }
-    int64_t useful = n / (3 * (int64_t)b) + 2;
+    // sweeps start about two tasks apart, so about n / 2b of them are active
+    int64_t useful = n / (2 * (int64_t)b) + 2;
     return (int)std::max<int64_t>(1, std::min<int64_t>(useful, cus));
 }
 

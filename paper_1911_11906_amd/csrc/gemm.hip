@@ -142,8 +142,8 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
         const int64_t tmt = FL_DIV_UP(g.m, TBM);
         int64_t S = 1;
         T* P = nullptr;
-        if (tmt < 384 && g.k >= 512) {
-            S = std::min<int64_t>({FL_DIV_UP(768, tmt), g.k / 256, 32});
+        if (tmt < 384 && g.k >= 256) {
+            S = std::min<int64_t>({FL_DIV_UP(768, tmt), g.k / 128, 32});
             while (S > 1 && S * g.m * g.n * (int64_t)sizeof(T) > SPLITK_WS_BYTES) --S;
             int dev = 0;
             P = (S > 1 && hipGetDevice(&dev) == hipSuccess) ? (T*)splitk_ws(dev) : nullptr;
