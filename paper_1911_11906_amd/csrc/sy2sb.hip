@@ -51,16 +51,34 @@ __device__ inline bool grid_barrier(unsigned* counter, unsigned target, int* abo
 // QR of the m x kb panel P (ld lda) with kref reflectors.  On exit P holds R
 // on and above its diagonal and the reflectors below (LAPACK layout), Vx
 // (ld ldv) the explicit unit-lower V (zeros above the diagonal), tau[c].
-// part: scratch of 2 * G * 64 doubles; prow: 2 * 64; counter: zeroed;
+//
+// Two reflectors per grid barrier where that is safe.  One exchange carries,
+// besides s_j = x_c^T a_j (rows > c) and rows c, c+1, the Gram row
+// g_j = a_{c+1}^T a_j (rows > c+1).  With reflector c = (tau, v, w) known,
+// column c+1 after it and its products with the other updated columns follow
+// exactly from these sums:
+//     P_j = v^T a_j (rows > c+1) = scale (s_j - x_{c+1} a_j[c+1]),
+//     Q   = v^T v   (rows > c+1) = scale^2 (|x|^2 - x_{c+1}^2),
+//     s'_j = g_j - tau w_j P_{c+1} - tau w_{c+1} P_j + tau^2 w_{c+1} w_j Q,
+// and |a'_{c+1}|^2 = s'_{c+1}.  That norm loses accuracy by the factor
+// g_{c+1} / s'_{c+1}; every workgroup takes reflector c+1 from the exchange
+// only if that factor is at most 1 / PAIR_MIN (and otherwise runs it in the
+// next exchange as a single step), so its relative error stays below
+// ~4 eps / PAIR_MIN.  The decision is made on the same reduced sums in every
+// workgroup, in a fixed summation order: the result is deterministic.
+//
+// part: scratch of 2 * G * 128 doubles; prow: 2 * 128; counter: zeroed;
 // abort: raised when a barrier wait is abandoned (the result is then invalid).
+constexpr double PAIR_MIN = 1.0 / 64;
 template <class T>
 __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kref, T* P, int64_t lda, T* Vx,
                                                        int64_t ldv, T* tau, T* part, T* prow, unsigned* counter,
                                                        int* abort) {
-    __shared__ T xc[PROWS];
-    __shared__ T red[4][64];
-    __shared__ T wv[64];
-    __shared__ T sc[4];  // scale, tau, beta, x0
+    __shared__ T xc[PROWS];   // pivot column c (this slab's rows)
+    __shared__ T xd[PROWS];   // column c+1: before reflector c (Gram row), after it (second update)
+    __shared__ T red[4][64], red2[4][64];
+    __shared__ T wv[64], gv[64];
+    __shared__ T sc[8];  // scale, tau, beta, | scale', tau', beta', pair flag
     const int t = threadIdx.x;
     const int lane = t & 63;   // panel column handled by this thread
     const int grp = t >> 6;    // row group
@@ -72,61 +90,89 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         int64_t r = slab0 + grp + 4 * q;
         v[q] = (r < m && lane < kb) ? P[r + lane * lda] : T(0);
     }
-    for (int c = 0; c < kref; ++c) {
-        const int par = c & 1;
-        // pivot column into LDS
+    unsigned k = 0;  // exchanges so far
+    for (int c = 0; c < kref;) {
+        const int par = k & 1;
+        const bool try2 = c + 1 < kref;
+        // pivot column (and column c+1) into LDS
         if (lane == c) {
 #pragma unroll
             for (int q = 0; q < PRPT; ++q) xc[grp + 4 * q] = v[q];
         }
+        if (try2 && lane == c + 1) {
+#pragma unroll
+            for (int q = 0; q < PRPT; ++q) xd[grp + 4 * q] = v[q];
+        }
         __syncthreads();
-        // partial dot products over rows r > c of this slab: s_j = sum x_r a_j[r]
-        T s = T(0);
+        // partial sums over this slab: s_j (rows > c), g_j (rows > c+1)
+        T s = T(0), g = T(0);
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
             int64_t r = slab0 + grp + 4 * q;
             if (r > c && r < m) s += xc[grp + 4 * q] * v[q];
+            if (try2 && r > c + 1 && r < m) g += xd[grp + 4 * q] * v[q];
         }
         red[grp][lane] = s;
-        // the workgroup owning row c publishes it
-        if (slab0 <= c && c < slab0 + PROWS) {
-            int lr = (int)(c - slab0);
-            if (grp == (lr & 3)) prow[par * 64 + lane] = v[lr >> 2];
+        red2[grp][lane] = g;
+        // the workgroups owning rows c and c+1 publish them
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t row = c + h;
+            if ((h == 0 || try2) && slab0 <= row && row < slab0 + PROWS) {
+                int lr = (int)(row - slab0);
+                if (grp == (lr & 3)) prow[par * 128 + h * 64 + lane] = v[lr >> 2];
+            }
         }
         __syncthreads();
-        if (t < 64) part[(size_t)par * G * 64 + (size_t)blockIdx.x * 64 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-        // every wave waits for its own stores (partials, published row); the
+        if (t < 64) {
+            T* pw = part + (size_t)par * G * 128 + (size_t)blockIdx.x * 128;
+            pw[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+            pw[64 + t] = red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
+        }
+        // every wave waits for its own stores (partials, published rows); the
         // barrier's single agent-scope release then writes the L2 back once
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_s_waitcnt(0);
-        if (!grid_barrier(counter, (unsigned)(c + 1) * G, abort)) return;
-        // reduce the partials of all workgroups in a fixed order (the same
-        // in every workgroup): row group q sums workgroups q, q+4, ..., the
-        // four sums are added in LDS.  The loads (which miss the cache after
-        // the barrier) are all issued before the first addition, RB at a
-        // time, with clamped, always valid addresses.
+        ++k;
+        if (!grid_barrier(counter, k * G, abort)) return;
+        // reduce the partials of all workgroups in a fixed order (the same in
+        // every workgroup): row group q sums workgroups q, q+4, ..., the four
+        // sums are added in LDS.  The loads (which miss the cache after the
+        // barrier) are issued RB at a time before the additions, from
+        // clamped, always valid addresses.
         {
-            constexpr int RB = 32;
-            T acc = T(0);
-            const T* pp = part + (size_t)par * G * 64 + lane;
+            constexpr int RB = 16;
+            T acc = T(0), acc2 = T(0);
+            const T* pp = part + (size_t)par * G * 128 + lane;
             for (unsigned w0 = (unsigned)grp; w0 < G; w0 += 4 * RB) {
-                T buf[RB];
+                T buf[RB], buf2[RB];
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
                     const unsigned w = w0 + 4 * q;
-                    buf[q] = pp[(size_t)(w < G ? w : 0) * 64];
+                    const size_t o = (size_t)(w < G ? w : 0) * 128;
+                    buf[q] = pp[o];
+                    buf2[q] = pp[o + 64];
                 }
 #pragma unroll
-                for (int q = 0; q < RB; ++q) acc += (w0 + 4 * q < G) ? buf[q] : T(0);
+                for (int q = 0; q < RB; ++q) {
+                    acc += (w0 + 4 * q < G) ? buf[q] : T(0);
+                    acc2 += (w0 + 4 * q < G) ? buf2[q] : T(0);
+                }
             }
             red[grp][lane] = acc;
+            red2[grp][lane] = acc2;
         }
         __syncthreads();
-        if (t < 64) wv[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+        if (t < 64) {
+            wv[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+            gv[t] = (red2[0][t] + red2[1][t]) + (red2[2][t] + red2[3][t]);
+        }
         __syncthreads();
+        const T* r0v = prow + par * 128;       // row c
+        const T* r1v = prow + par * 128 + 64;  // row c+1
         if (t == 0) {
-            const T x0 = prow[par * 64 + c];
-            const T sig = wv[c];  // |x(1:)|^2
+            const T x0 = r0v[c];
+            const T sig = wv[c];  // |x(rows > c)|^2
             T beta, tauc, scale;
             if (sig == T(0)) {
                 beta = x0;
@@ -141,13 +187,45 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
             sc[0] = scale;
             sc[1] = tauc;
             sc[2] = beta;
-            sc[3] = x0;
             if (blockIdx.x == 0) tau[c] = tauc;
+            int pair = 0;
+            if (try2) {
+                const T x1 = r1v[c];  // pivot column at row c+1
+                const T v1 = scale * x1;
+                const T w1 = r0v[c + 1] + scale * wv[c + 1];
+                const T P1 = scale * (wv[c + 1] - x1 * r1v[c + 1]);
+                const T Q = scale * scale * (sig - x1 * x1);
+                const T gcc = gv[c + 1];
+                const T sig2 = gcc - T(2) * tauc * w1 * P1 + tauc * tauc * w1 * w1 * Q;
+                if (sig2 >= T(PAIR_MIN) * gcc) {
+                    pair = 1;
+                    const T y0 = r1v[c + 1] - tauc * v1 * w1;  // column c+1 at row c+1 after reflector c
+                    T beta2, tau2, scale2;
+                    if (!(sig2 > T(0))) {
+                        beta2 = y0;
+                        tau2 = T(0);
+                        scale2 = T(0);
+                    } else {
+                        T nrm = sqrt(y0 * y0 + sig2);
+                        beta2 = (y0 >= T(0)) ? -nrm : nrm;
+                        tau2 = (beta2 - y0) / beta2;
+                        scale2 = T(1) / (y0 - beta2);
+                    }
+                    sc[3] = scale2;
+                    sc[4] = tau2;
+                    sc[5] = beta2;
+                    sc[6] = v1;
+                    sc[7] = w1;
+                    if (blockIdx.x == 0) tau[c + 1] = tau2;
+                }
+            }
+            red[0][0] = (T)pair;
         }
         __syncthreads();
         const T scale = sc[0], tauc = sc[1], beta = sc[2];
+        const bool pair = red[0][0] != T(0);
         // w_j = v^T a_j = a_j[c] + scale * s_j   (j > c)
-        const T wj = (lane > c && lane < kb) ? (prow[par * 64 + lane] + scale * wv[lane]) : T(0);
+        const T wj = (lane > c && lane < kb) ? (r0v[lane] + scale * wv[lane]) : T(0);
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
             int64_t r = slab0 + grp + 4 * q;
@@ -160,7 +238,42 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
                 v[q] -= tauc * vr * wj;
             }
         }
+        if (!pair) {
+            __syncthreads();
+            c += 1;
+            continue;
+        }
+        // reflector c+1 from the same exchange
+        const T scale2 = sc[3], tau2 = sc[4], beta2 = sc[5], v1 = sc[6], w1 = sc[7];
+        T wj2 = T(0);
+        if (lane > c + 1 && lane < kb) {
+            const T x1 = r1v[c];
+            const T P1 = scale * (wv[c + 1] - x1 * r1v[c + 1]);
+            const T Q = scale * scale * (wv[c] - x1 * x1);
+            const T Pj = scale * (wv[lane] - x1 * r1v[lane]);
+            const T s2 = gv[lane] - tauc * wj * P1 - tauc * w1 * Pj + tauc * tauc * w1 * wj * Q;
+            wj2 = (r1v[lane] - tauc * v1 * wj) + scale2 * s2;
+        }
+        // column c+1 after reflector c, for the second update
+        if (lane == c + 1) {
+#pragma unroll
+            for (int q = 0; q < PRPT; ++q) xd[grp + 4 * q] = v[q];
+        }
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PRPT; ++q) {
+            int64_t r = slab0 + grp + 4 * q;
+            if (r >= m) continue;
+            if (lane == c + 1) {
+                if (r > c + 1) v[q] = scale2 * v[q];
+                else if (r == c + 1) v[q] = beta2;
+            } else if (lane > c + 1 && lane < kb) {
+                T vr = (r > c + 1) ? scale2 * xd[grp + 4 * q] : (r == c + 1 ? T(1) : T(0));
+                v[q] -= tau2 * vr * wj2;
+            }
+        }
+        __syncthreads();
+        c += 2;
     }
     // write back the factored panel and the explicit reflectors
 #pragma unroll
@@ -175,26 +288,39 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
 
 // T (kref x kref upper, ld ldt) of the forward block reflector from the Gram
 // matrix G = V^T V and tau: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) G(0:j, j).
+// G is staged in LDS once; at step j, four lanes share row t < j, each summing
+// every fourth term of its dot product, combined by two lane exchanges, so a
+// step costs one barrier and at most 16 products per lane.
+constexpr int LFT = 256;
 template <class E>
-__global__ __launch_bounds__(64) void larft_gram_kernel(int kref, const E* __restrict__ G, int64_t ldg,
-                                                        const E* __restrict__ tau, E* T, int64_t ldt) {
-    __shared__ E Ts[64 * 64];
-    __shared__ E y[64];
-    const int t = threadIdx.x;
+__global__ __launch_bounds__(LFT) void larft_gram_kernel(int kref, const E* __restrict__ G, int64_t ldg,
+                                                         const E* __restrict__ tau, E* T, int64_t ldt) {
+    __shared__ E Ts[64 * 65];
+    __shared__ E Gs[64 * 65];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * 64; e += LFT) {
+        const int r = e & 63, c = e >> 6;
+        Gs[r + c * 65] = (r < kref && c < kref) ? G[r + c * ldg] : E(0);
+        Ts[r + c * 65] = E(0);
+    }
+    __syncthreads();
+    const int t = tid >> 2, part = tid & 3;  // row t, quarter part of its dot product
     for (int j = 0; j < kref; ++j) {
-        if (t < j) y[t] = G[t + j * ldg];
-        __syncthreads();
-        if (t < j) {
-            E acc = E(0);
-            for (int k = t; k < j; ++k) acc += Ts[t + k * 64] * y[k];
-            Ts[t + j * 64] = -tau[j] * acc;
+        E acc = E(0);
+        if (t < j)
+            for (int k = t + part; k < j; k += 4) acc += Ts[t + k * 65] * Gs[k + j * 65];
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (part == 0) {
+            if (t < j) Ts[t + j * 65] = -tau[j] * acc;
+            if (t == j) Ts[j + j * 65] = tau[j];
         }
-        if (t == j) Ts[j + j * 64] = tau[j];
-        if (t > j && t < kref) Ts[t + j * 64] = E(0);
         __syncthreads();
     }
-    for (int j = 0; j < kref; ++j)
-        if (t < kref) T[t + j * ldt] = Ts[t + j * 64];
+    for (int e = tid; e < kref * kref; e += LFT) {
+        const int r = e % kref, c = e / kref;
+        T[r + c * ldt] = Ts[r + c * 65];
+    }
 }
 
 // Band (lower, ld ldab, 2b+1 rows reserved) from the reduced matrix: the
@@ -269,7 +395,7 @@ hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, in
             int64_t mm = m;
             int kbb = kb, krf = kref;
             int64_t ldaa = lda, ldvv = ldv;
-            T* prow = part + 2 * FL_DIV_UP(n, PROWS) * 64;
+            T* prow = part + 2 * FL_DIV_UP(n, PROWS) * 128;
             unsigned* counter = cnt + p;
             void* args[] = {&mm, &kbb, &krf, &Pn, &ldaa, &Vp, &ldvv, &tp, &part, &prow, &counter, &abort};
             e = hipLaunchCooperativeKernel((const void*)panel_qr_kernel<T>, dim3(G), dim3(PNT), args, 0, s);
@@ -279,7 +405,7 @@ hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, in
         T* Tp = T1 + p * (int64_t)b * b;
         e = fl_gemm_t(s, 1, 0, kref, kref, m, 1.0, Vp, ldv, Vp, ldv, 0.0, Gm, b);
         if (e != hipSuccess) return e;
-        larft_gram_kernel<T><<<1, 64, 0, s>>>(kref, Gm, b, tp, Tp, b);
+        larft_gram_kernel<T><<<1, LFT, 0, s>>>(kref, Gm, b, tp, Tp, b);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // Y = A22 V with A22 = A[r0:n, r0:n] as of the last trailing update,
         // corrected by the pending pairs
@@ -345,7 +471,7 @@ int64_t fl_sy2sb_work_elems(int64_t n, int b) {
     const int64_t kw = 2 * (int64_t)QL * b;
     return 3 * (int64_t)b * b + 2 * n * (int64_t)b + 2 * n * kw + kw * b;
 }
-int64_t fl_sy2sb_part_elems(int64_t n) { return 2 * FL_DIV_UP(n, PROWS) * 64 + 128; }
+int64_t fl_sy2sb_part_elems(int64_t n) { return 2 * FL_DIV_UP(n, PROWS) * 128 + 256; }
 
 hipError_t fl_extract_band(hipStream_t s, int64_t n, int b, const double* A, int64_t lda, double* AB, int64_t ldab) {
     if (n <= 0) return hipSuccess;
