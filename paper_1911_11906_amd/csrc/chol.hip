@@ -13,33 +13,54 @@ namespace {
 constexpr int LB = 128;  // leaf block
 constexpr int LT = 1024; // threads of the leaf kernel
 
-// In-place inverse of the lower-triangular LB x LB block S (column-major,
-// ld LB), last column first: X_jj = 1/L_jj, X(j+1:, j) = -X_jj X(j+1:, j+1:) L(j+1:, j).
-__device__ void invert_lower_lds(double* S, double* y, int t) {
+// Inverse X of the lower-triangular LB x LB block L in LDS (column-major, ld
+// LB), written to out (LB x LB, zero above the diagonal).  X L = I gives, row
+// by row from the right, X_ii = 1 / L_ii and
+//     X_ij = -(1 / L_jj) sum_{k = j+1..i} X_ik L_kj   (j < i),
+// which uses only row i of X: eight lanes own row i (lane p keeps X_ik for
+// k = p mod 8 in registers) and split each sum, so no workgroup barrier is
+// needed.  L is only read.
+__device__ void invert_lower_rows(const double* L, double* out, int t) {
+    const int i = t >> 3, part = t & 7;  // 1024 threads: 128 rows x 8 lanes
+    double X[LB / 8];
+#pragma unroll
+    for (int q = 0; q < LB / 8; ++q) X[q] = 0.0;
     for (int j = LB - 1; j >= 0; --j) {
-        double xjj = 1.0 / S[j + j * LB];
-        for (int i = j + 1 + t; i < LB; i += LT) {
-            double acc = 0.0;
-            for (int k = j + 1; k <= i; ++k) acc += S[i + k * LB] * S[k + j * LB];
-            y[i] = -xjj * acc;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < LB / 8; ++q) {
+            const int k = 8 * q + part;
+            if (k > j && k <= i) acc += X[q] * L[k + j * LB];
         }
-        __syncthreads();
-        for (int i = j + 1 + t; i < LB; i += LT) S[i + j * LB] = y[i];
-        if (t == 0) S[j + j * LB] = xjj;
-        __syncthreads();
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        acc += __shfl_xor(acc, 4, 64);
+        const double x = (j == i) ? 1.0 / L[j + j * LB] : -acc / L[j + j * LB];
+        if (j <= i && part == (j & 7)) {
+#pragma unroll
+            for (int q = 0; q < LB / 8; ++q)
+                if (q == (j >> 3)) X[q] = x;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < LB / 8; ++q) {
+        const int k = 8 * q + part;
+        out[i + k * LB] = (k <= i) ? X[q] : 0.0;
     }
 }
 
 // Factor the nb x nb (nb <= 128) diagonal block at A (ld lda) in LDS; write L
 // back (strict upper triangle of the block zeroed) and its inverse (128 x 128,
 // zero padded) to Linv.  info: first failing global pivot (1-based) if unset.
+// The elimination keeps the columns unscaled (S_ic -= S_ij S_cj / d_j), one
+// barrier per column; L = column j / sqrt(d_j) is formed at the end.  A
+// pivot d_j <= 0 is reported and replaced by 1 (every thread derives the same
+// replacement from either value it may read).
 __global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, int nb, int64_t goff,
                                                         double* Linv, int64_t* info) {
     __shared__ double S[LB * LB];  // column-major with ld LB (128 KB of the 160 KB LDS)
     __shared__ double y[LB];
-    __shared__ int bad;
     const int t = threadIdx.x;
-    if (t == 0) bad = 0;
     for (int e = t; e < LB * LB; e += LT) {
         int i = e % LB, j = e / LB;
         double v;
@@ -50,49 +71,45 @@ __global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, 
         S[i + j * LB] = v;
     }
     __syncthreads();
-    // right-looking unblocked Cholesky
+    bool bad = false;  // thread 0 only
     for (int j = 0; j < nb; ++j) {
-        if (t == 0) {
-            double d = S[j + j * LB];
-            if (!(d > 0.0)) {
-                if (!bad) {
-                    bad = 1;
-                    if (*info == 0) *info = goff + j + 1;
-                }
-                d = 1.0;  // keep going with a harmless pivot; the status reports the failure
-            }
-            S[j + j * LB] = sqrt(d);
+        const double d = S[j + j * LB];
+        const double deff = (d > 0.0) ? d : 1.0;
+        if (t == 0 && !(d > 0.0)) {
+            if (!bad && *info == 0) *info = goff + j + 1;
+            bad = true;
+            S[j + j * LB] = deff;
         }
-        __syncthreads();
-        const double dj = S[j + j * LB];
-        for (int i = j + 1 + t; i < nb; i += LT) S[i + j * LB] /= dj;
-        __syncthreads();
+        const double inv = 1.0 / deff;
         const int w = nb - j - 1;
         for (int e = t; e < w * w; e += LT) {
             int r = e % w, c = e / w;
             if (r >= c) {
                 int i = j + 1 + r, cc = j + 1 + c;
-                S[i + cc * LB] -= S[i + j * LB] * S[cc + j * LB];
+                S[i + cc * LB] -= S[i + j * LB] * (S[cc + j * LB] * inv);
             }
         }
         __syncthreads();
     }
+    if (t < LB) y[t] = sqrt(S[t + t * LB]);
+    __syncthreads();
+    for (int e = t; e < LB * LB; e += LT) {
+        int i = e % LB, j = e / LB;
+        if (i > j) S[e] = S[e] / y[j];
+        else if (i == j) S[e] = y[j];
+    }
+    __syncthreads();
     for (int e = t; e < nb * nb; e += LT) {
         int i = e % nb, j = e / nb;
         A[i + (int64_t)j * lda] = (i >= j) ? S[i + j * LB] : 0.0;
     }
-    invert_lower_lds(S, y, t);
-    for (int e = t; e < LB * LB; e += LT) {
-        int i = e % LB, j = e / LB;
-        Linv[e] = (i >= j) ? S[i + j * LB] : 0.0;
-    }
+    invert_lower_rows(S, Linv, t);
 }
 
 // Inverses of the 128 x 128 diagonal blocks of an existing lower factor L
 // (one workgroup per block).
 __global__ __launch_bounds__(LT) void trtri_leaves_kernel(int64_t n, const double* L, int64_t ldl, double* Linv) {
     __shared__ double S[LB * LB];
-    __shared__ double y[LB];
     const int t = threadIdx.x;
     const int64_t off = (int64_t)blockIdx.x * LB;
     const int nb = (int)((n - off) < LB ? (n - off) : LB);
@@ -101,12 +118,7 @@ __global__ __launch_bounds__(LT) void trtri_leaves_kernel(int64_t n, const doubl
         S[i + j * LB] = (i < nb && j < nb) ? ((i >= j) ? L[off + i + (off + j) * ldl] : 0.0) : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
-    invert_lower_lds(S, y, t);
-    double* out = Linv + (int64_t)blockIdx.x * LB * LB;
-    for (int e = t; e < LB * LB; e += LT) {
-        int i = e % LB, j = e / LB;
-        out[e] = (i >= j) ? S[i + j * LB] : 0.0;
-    }
+    invert_lower_rows(S, Linv + (int64_t)blockIdx.x * LB * LB, t);
 }
 
 __global__ void symmetrize_kernel(int64_t n, double* A, int64_t lda) {

@@ -42,7 +42,17 @@ template <class T, bool TA, bool TB, bool LOWER, int KT = FL_KT_NONE>
 __global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void gemm_kernel(Prob<T> g) {
     __shared__ T As[TileLds<GKB, GNBUF>::A];
     __shared__ T Bs[TileLds<GKB, GNBUF>::B];
-    const int64_t bi = blockIdx.x, bj = blockIdx.y;
+    int64_t bi = blockIdx.x, bj = blockIdx.y;
+    if (KT == FL_KT_A_LOWER || KT == FL_KT_A_UPPER) {
+        // tiles differ in k length by row block: hand out the row blocks in
+        // order of decreasing length (column blocks fastest), so the last
+        // tiles to start are the short ones
+        const int64_t tm = gridDim.x, tn = gridDim.y;
+        const int64_t id = (int64_t)blockIdx.x + tm * blockIdx.y;
+        const int64_t q = id / tn;
+        bj = id - q * tn;
+        bi = (KT == FL_KT_A_LOWER) ? tm - 1 - q : q;
+    }
     if (LOWER && (bi + 1) * BM <= bj * BN) return;  // tile strictly above the diagonal
     int64_t kb = 0, ke = g.k;
     if (KT == FL_KT_A_LOWER) ke = std::min<int64_t>(g.k, (bi + 1) * BM);
