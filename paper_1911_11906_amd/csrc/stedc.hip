@@ -409,17 +409,19 @@ __global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __r
             if (done) return;
             // j <= kk contributes to psi, j > kk to phi
             const int split = (int)std::min<int64_t>(std::max<int64_t>(kk + 1 - base, 0), lim);
+            // one division per pole: t = w / dl and t / dl from 1 / dl
+            // (two roundings each, well inside the stopping test's 8 eps)
             for (int q = 0; q < split; ++q) {
-                const double dl = (sd[q] - dorg) - x;
-                const double tq = sw[q] / dl;
+                const double rl = 1.0 / ((sd[q] - dorg) - x);
+                const double tq = sw[q] * rl;
                 psi += tq;
-                dpsi += tq / dl;
+                dpsi += tq * rl;
             }
             for (int q = split; q < lim; ++q) {
-                const double dl = (sd[q] - dorg) - x;
-                const double tq = sw[q] / dl;
+                const double rl = 1.0 / ((sd[q] - dorg) - x);
+                const double tq = sw[q] * rl;
                 phi += tq;
-                dphi += tq / dl;
+                dphi += tq * rl;
             }
         });
         if (done) continue;
