@@ -81,13 +81,12 @@ __global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, 
             S[j + j * LB] = deff;
         }
         const double inv = 1.0 / deff;
-        const int w = nb - j - 1;
-        for (int e = t; e < w * w; e += LT) {
-            int r = e % w, c = e / w;
-            if (r >= c) {
-                int i = j + 1 + r, cc = j + 1 + c;
-                S[i + cc * LB] -= S[i + j * LB] * (S[cc + j * LB] * inv);
-            }
+        // thread t updates row t % LB of the columns j+1+(t / LB), step 8
+        // (fixed row, no index division)
+        const int i = t & (LB - 1);
+        if (i > j && i < nb) {
+            const double sij = S[i + j * LB] * inv;
+            for (int cc = j + 1 + (t >> 7); cc <= i; cc += LT / LB) S[i + cc * LB] -= sij * S[cc + j * LB];
         }
         __syncthreads();
     }

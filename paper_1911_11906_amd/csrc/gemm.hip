@@ -65,6 +65,30 @@ __global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void gemm_kernel(Prob<T> 
                                                   bj, As, Bs);
 }
 
+// Lower triangle of a square tile grid: one block per tile on or below the
+// diagonal (a full grid whose upper blocks exit at once ran ~25 % slower),
+// tiles numbered row by row (bi slow, bj = 0..bi fast).  With KT_A_LOWER the
+// k range grows with bi, so the rows are handed out last to first.
+template <class T, bool TA, bool TB, int KT = FL_KT_NONE>
+__global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void gemm_lower_kernel(Prob<T> g, int64_t ntiles) {
+    __shared__ T As[TileLds<GKB, GNBUF>::A];
+    __shared__ T Bs[TileLds<GKB, GNBUF>::B];
+    const int64_t id = (KT == FL_KT_A_LOWER) ? ntiles - 1 - (int64_t)blockIdx.x : (int64_t)blockIdx.x;
+    int64_t bi = (int64_t)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > id) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= id) ++bi;
+    const int64_t bj = id - bi * (bi + 1) / 2;
+    int64_t kb = 0, ke = g.k;
+    if (KT == FL_KT_A_LOWER) ke = std::min<int64_t>(g.k, (bi + 1) * BM);
+    if (KT == FL_KT_A_UPPER) kb = std::min<int64_t>(g.k, bi * BM);
+    if (KT == FL_KT_B_LOWER) kb = std::min<int64_t>(g.k, bj * BN);
+    const T* A = TA ? g.A + kb : g.A + kb * g.lda;
+    const T* B = TB ? g.B + kb * g.ldb : g.B + kb;
+    BPlainT<T> bsrc{B, g.ldb, TB};
+    tile_gemm<TA, !TB, BPlainT<T>, GKB, GNBUF, T>(g.m, g.n, ke - kb, A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi,
+                                                  bj, As, Bs);
+}
+
 // Products with at most 64 columns: 256 x 64 tiles (four waves along M), so
 // no half of each tile multiplies padding.  Split along k when the tiles are
 // too few to fill the chip.  (One wave per SIMD: the transposed variants
@@ -192,7 +216,10 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
         }
     }
     dim3 grid((unsigned)tm, (unsigned)tn);
-    if (lower)
+    if (lower && tm == tn) {
+        const int64_t nt = tm * (tm + 1) / 2;
+        gemm_lower_kernel<T, TA, TB><<<(unsigned)nt, NT, 0, s>>>(g, nt);
+    } else if (lower)
         gemm_kernel<T, TA, TB, true><<<grid, NT, 0, s>>>(g);
     else
         gemm_kernel<T, TA, TB, false><<<grid, NT, 0, s>>>(g);
@@ -202,7 +229,10 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
 template <int KT, bool TA, bool TB>
 hipError_t launch_tri(hipStream_t s, const Prob<double>& g, int lower) {
     dim3 grid((unsigned)FL_DIV_UP(g.m, BM), (unsigned)FL_DIV_UP(g.n, BN));
-    if (lower)
+    if (lower && grid.x == grid.y) {
+        const int64_t nt = (int64_t)grid.x * (grid.x + 1) / 2;
+        gemm_lower_kernel<double, TA, TB, KT><<<(unsigned)nt, NT, 0, s>>>(g, nt);
+    } else if (lower)
         gemm_kernel<double, TA, TB, true, KT><<<grid, NT, 0, s>>>(g);
     else
         gemm_kernel<double, TA, TB, false, KT><<<grid, NT, 0, s>>>(g);
