@@ -27,6 +27,7 @@ namespace {
 constexpr int BT = 512;                    // threads per workgroup (8 waves)
 constexpr int NMAX = 1024;                 // largest problem
 constexpr int PB = 32;                     // panel / reflector block width
+constexpr int OB = 128;                    // row group of the two-level triangular solves
 constexpr int TM = 64, TN = 128, TK = 32;  // GEMM tile: eight waves of 32 x 32, k-slab 32
 constexpr int RPT = NMAX / BT;             // rows per thread in the tridiagonalisation
 constexpr int DCL = 32;                    // largest leaf of the divide and conquer
@@ -252,64 +253,83 @@ __device__ __attribute__((noinline)) int wg_potrf(int n, double* A, int64_t lda,
 // Solve L X = B in place (L lower, n x n; B n x nrhs).
 __device__ __attribute__((noinline)) void wg_trsm_ln(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
-    for (int i0 = 0; i0 < n; i0 += PB) {
-        const int ib = min(PB, n - i0);
-        for (int e = t; e < PB * PB; e += BT) {
-            const int r = e % PB, c = e / PB;
-            s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
-        }
-        __syncthreads();
-        for (int j = t; j < nrhs; j += BT) {
-            double x[PB];
+    // Two-level blocking: PB-row blocks are solved and update only the rest
+    // of their OB-row group (k = PB); each finished group then updates all
+    // rows below it in one product with k = OB, so the trailing rows are
+    // read and written once per group instead of once per block.
+    for (int o0 = 0; o0 < n; o0 += OB) {
+        const int oe = min(n, o0 + OB);
+        for (int i0 = o0; i0 < oe; i0 += PB) {
+            const int ib = min(PB, oe - i0);
+            for (int e = t; e < PB * PB; e += BT) {
+                const int r = e % PB, c = e / PB;
+                s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
+            }
+            __syncthreads();
+            for (int j = t; j < nrhs; j += BT) {
+                double x[PB];
 #pragma unroll
-            for (int r = 0; r < PB; ++r) {
-                if (r < ib) {
-                    double v = B[i0 + r + (int64_t)j * ldb];
+                for (int r = 0; r < PB; ++r) {
+                    if (r < ib) {
+                        double v = B[i0 + r + (int64_t)j * ldb];
 #pragma unroll
-                    for (int q = 0; q < r; ++q) v -= s.D[r][q] * x[q];
-                    x[r] = v / s.D[r][r];
-                    B[i0 + r + (int64_t)j * ldb] = x[r];
-                } else {
-                    x[r] = 0.0;
+                        for (int q = 0; q < r; ++q) v -= s.D[r][q] * x[q];
+                        x[r] = v / s.D[r][r];
+                        B[i0 + r + (int64_t)j * ldb] = x[r];
+                    } else {
+                        x[r] = 0.0;
+                    }
                 }
             }
+            gsync();
+            if (i0 + ib < oe)
+                wg_gemm(false, false, oe - i0 - ib, nrhs, ib, -1.0, L + i0 + ib + (int64_t)i0 * ldl, ldl, B + i0, ldb,
+                        1.0, B + i0 + ib, ldb, s);
         }
-        gsync();
-        if (i0 + ib < n)
-            wg_gemm(false, false, n - i0 - ib, nrhs, ib, -1.0, L + i0 + ib + (int64_t)i0 * ldl, ldl, B + i0, ldb,
-                    1.0, B + i0 + ib, ldb, s);
+        if (oe < n)
+            wg_gemm(false, false, n - oe, nrhs, oe - o0, -1.0, L + oe + (int64_t)o0 * ldl, ldl, B + o0, ldb, 1.0,
+                    B + oe, ldb, s);
     }
 }
 
-// Solve L^T X = B in place.
+// Solve L^T X = B in place (two-level blocking as in wg_trsm_ln, from the
+// last group up: within a group k = PB, the rows above it get one k = OB
+// product).
 __device__ __attribute__((noinline)) void wg_trsm_lt(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
-    const int nblk = (n + PB - 1) / PB;
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-        const int i0 = bi * PB, ib = min(PB, n - i0);
-        for (int e = t; e < PB * PB; e += BT) {
-            const int r = e % PB, c = e / PB;
-            s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
-        }
-        __syncthreads();
-        for (int j = t; j < nrhs; j += BT) {
-            double x[PB];
+    const int ngrp = (n + OB - 1) / OB;
+    for (int gi = ngrp - 1; gi >= 0; --gi) {
+        const int o0 = gi * OB, oe = min(n, o0 + OB);
+        const int nblk = (oe - o0 + PB - 1) / PB;
+        for (int bi = nblk - 1; bi >= 0; --bi) {
+            const int i0 = o0 + bi * PB, ib = min(PB, oe - i0);
+            for (int e = t; e < PB * PB; e += BT) {
+                const int r = e % PB, c = e / PB;
+                s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
+            }
+            __syncthreads();
+            for (int j = t; j < nrhs; j += BT) {
+                double x[PB];
 #pragma unroll
-            for (int r = PB - 1; r >= 0; --r) {
-                if (r < ib) {
-                    double v = B[i0 + r + (int64_t)j * ldb];
+                for (int r = PB - 1; r >= 0; --r) {
+                    if (r < ib) {
+                        double v = B[i0 + r + (int64_t)j * ldb];
 #pragma unroll
-                    for (int q = r + 1; q < PB; ++q)
-                        if (q < ib) v -= s.D[q][r] * x[q];
-                    x[r] = v / s.D[r][r];
-                    B[i0 + r + (int64_t)j * ldb] = x[r];
-                } else {
-                    x[r] = 0.0;
+                        for (int q = r + 1; q < PB; ++q)
+                            if (q < ib) v -= s.D[q][r] * x[q];
+                        x[r] = v / s.D[r][r];
+                        B[i0 + r + (int64_t)j * ldb] = x[r];
+                    } else {
+                        x[r] = 0.0;
+                    }
                 }
             }
+            gsync();
+            if (i0 > o0)
+                wg_gemm(true, false, i0 - o0, nrhs, ib, -1.0, L + i0 + (int64_t)o0 * ldl, ldl, B + i0, ldb, 1.0,
+                        B + o0, ldb, s);
         }
-        gsync();
-        if (i0 > 0) wg_gemm(true, false, i0, nrhs, ib, -1.0, L + i0, ldl, B + i0, ldb, 1.0, B, ldb, s);
+        if (o0 > 0) wg_gemm(true, false, o0, nrhs, oe - o0, -1.0, L + o0, ldl, B + o0, ldb, 1.0, B, ldb, s);
     }
 }
 
