@@ -621,44 +621,73 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
 // Z := Q Z with Q = H_0 H_1 ... H_{n-3} from wg_sytrd, applied as block
 // reflectors of PB consecutive H (forward, columnwise: I - V T V^T), last
 // block first.  work: >= 3 PB n + PB PB doubles.
+// Work of wg_ormtr with block width w, and the size of its work array.
+__host__ __device__ inline int64_t ormtr_need(int64_t n, int64_t w) {
+    return (n - 1) * w + 2 * w * w + w * PB + 2 * w * n;
+}
+__host__ __device__ inline int64_t ormtr_wsz(int64_t n) {
+    return n * n > ormtr_need(n, PB) ? n * n : ormtr_need(n, PB);
+}
+
 __device__ __attribute__((noinline)) void wg_ormtr(int n, const double* A, int64_t lda, const double* tau, double* Z, int64_t ldz,
                          double* work, Lds& s) {
     const int t = threadIdx.x;
     const int nref = n - 2;
     if (nref <= 0) return;
-    const int nblk = (nref + PB - 1) / PB;
+    // Block reflectors of QW = 4 PB reflectors when the n x n work array has
+    // room (one pass over Z per 128 reflectors instead of per 32), else PB.
+    // T of a wide block: its PB x PB diagonal blocks by the column recurrence
+    // in LDS, the blocks above them from T(0:c0, S) = -T(0:c0, 0:c0)
+    // G(0:c0, S) T_SS with G = V^T V.
+    constexpr int QW = 4 * PB;
+    const int W = (ormtr_need(n, QW) <= ormtr_wsz(n)) ? QW : PB;
+    const int nblk = (nref + W - 1) / W;
     for (int bi = nblk - 1; bi >= 0; --bi) {
-        const int k0 = bi * PB, nb = min(PB, nref - k0);
+        const int k0 = bi * W, nb = min(W, nref - k0);
         const int rows = n - k0 - 1;  // rows k0+1 .. n-1
         double* Vb = work;                          // rows x nb
-        double* Tm = Vb + (int64_t)rows * PB;       // PB x PB
-        double* Wt = Tm + PB * PB;                  // nb x n
-        double* Wt2 = Wt + (int64_t)PB * n;         // nb x n
+        double* Tm = Vb + (int64_t)rows * W;        // W x W
+        double* Gm = Tm + W * W;                    // W x W
+        double* Xm = Gm + W * W;                    // W x PB
+        double* Wt = Xm + W * PB;                   // nb x n
+        double* Wt2 = Wt + (int64_t)W * n;          // nb x n
         for (int c = 0; c < nb; ++c)
             for (int rr = t; rr < rows; rr += BT)
                 Vb[rr + (int64_t)c * rows] =
                     rr < c ? 0.0 : (rr == c ? 1.0 : A[(k0 + 1 + rr) + (int64_t)(k0 + c) * lda]);
+        for (int e = t; e < W * W; e += BT) Tm[e] = 0.0;
         gsync();
-        // G = V^T V (in Wt), then T column by column: T[c][c] = tau_c,
-        // T[0:c, c] = -tau_c T[0:c, 0:c] G[0:c, c]
-        wg_gemm(true, false, nb, nb, rows, 1.0, Vb, rows, Vb, rows, 0.0, Wt, PB, s);
-        for (int e = t; e < PB * PB; e += BT) s.D[e % PB][e / PB] = 0.0;
-        __syncthreads();
-        for (int c = 0; c < nb; ++c) {
-            const double tc = tau[k0 + c];
-            double acc = 0.0;
-            if (t < c) {
-                for (int q = t; q < c; ++q) acc += s.D[t][q] * Wt[q + c * PB];
+        wg_gemm(true, false, nb, nb, rows, 1.0, Vb, rows, Vb, rows, 0.0, Gm, W, s);
+        for (int c0 = 0; c0 < nb; c0 += PB) {
+            const int sb = min(PB, nb - c0);
+            // T_SS: T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] G[0:c, c] (within the sub-block)
+            for (int e = t; e < PB * PB; e += BT) s.D[e % PB][e / PB] = 0.0;
+            __syncthreads();
+            for (int c = 0; c < sb; ++c) {
+                const double tc = tau[k0 + c0 + c];
+                double acc = 0.0;
+                if (t < c) {
+                    for (int q = t; q < c; ++q) acc += s.D[t][q] * Gm[(c0 + q) + (int64_t)(c0 + c) * W];
+                }
+                __syncthreads();
+                if (t < c) s.D[t][c] = -tc * acc;
+                if (t == c) s.D[c][c] = tc;
+                __syncthreads();
             }
-            __syncthreads();
-            if (t < c) s.D[t][c] = -tc * acc;
-            if (t == c) s.D[c][c] = tc;
-            __syncthreads();
+            for (int e = t; e < PB * PB; e += BT) {
+                const int r = e % PB, c = e / PB;
+                if (r < sb && c < sb) Tm[(c0 + r) + (int64_t)(c0 + c) * W] = s.D[r][c];
+            }
+            gsync();
+            if (c0 > 0) {
+                // T(0:c0, S) = -(T(0:c0, 0:c0) G(0:c0, S)) T_SS
+                wg_gemm(false, false, c0, sb, c0, 1.0, Tm, W, Gm + (int64_t)c0 * W, W, 0.0, Xm, W, s);
+                wg_gemm(false, false, c0, sb, sb, -1.0, Xm, W, Tm + c0 + (int64_t)c0 * W, W, 0.0,
+                        Tm + (int64_t)c0 * W, W, s);
+            }
         }
-        for (int e = t; e < PB * PB; e += BT) Tm[e] = s.D[e % PB][e / PB];
-        gsync();
         wg_gemm(true, false, nb, n, rows, 1.0, Vb, rows, Z + k0 + 1, ldz, 0.0, Wt, nb, s);
-        wg_gemm(false, false, nb, n, nb, 1.0, Tm, PB, Wt, nb, 0.0, Wt2, nb, s);
+        wg_gemm(false, false, nb, n, nb, 1.0, Tm, W, Wt, nb, 0.0, Wt2, nb, s);
         wg_gemm(false, false, rows, n, nb, -1.0, Vb, rows, Wt2, nb, 1.0, Z + k0 + 1, ldz, s);
     }
 }
@@ -1243,7 +1272,7 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
     auto al = [](int64_t x) { return (x + 31) / 32 * 32; };
     for (int64_t i = 0; i < count; ++i) {
         const int64_t n = ops[i]->n;
-        const int64_t wsz = std::max<int64_t>(n * n, 3 * (int64_t)PB * n + PB * PB);
+        const int64_t wsz = ormtr_wsz(n);
         off[i] = tot;
         tot += al(n * n) * 5 + al(wsz) + al(4 * n) + al(n);
     }
@@ -1258,7 +1287,7 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         if (!op->V) FL_HIP(ctx, hipMalloc(&op->V, sizeof(double) * op->ld * n));
         op->has_eig = 0;
         double* w = bws.as<double>() + off[i];
-        const int64_t wsz = std::max<int64_t>(n * n, 3 * (int64_t)PB * n + PB * PB);
+        const int64_t wsz = ormtr_wsz(n);
         BProb& b = hp[i];
         b.n = n;
         b.ld = op->ld;
