@@ -336,14 +336,20 @@ __global__ __launch_bounds__(256) void merge_rotate_kernel(const MergeDesc* __re
 // iterates until all its roots have converged.
 constexpr int STILE = 1024;
 constexpr int SNT = 256;
+constexpr int SRL = 4;             // lanes per root: each sums every fourth pole
+constexpr int SRW = SNT / SRL;     // roots per workgroup
 __global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __restrict__ md, const MergeCounts* __restrict__ cnt,
                                                             const double* __restrict__ dk, const double* __restrict__ zk,
                                                             int64_t* rorg, double* rtau, double* lam, int* fail) {
     __shared__ double sd[STILE], sw[STILE], sz[STILE];  // d_j, (rho z_j) z_j, z_j
     const MergeDesc g = md[blockIdx.y];
     const int64_t K = cnt[blockIdx.y].K;
-    if ((int64_t)blockIdx.x * SNT >= K) return;  // uniform over the workgroup
-    const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+    if ((int64_t)blockIdx.x * SRW >= K) return;  // uniform over the workgroup
+    // SRL adjacent lanes share root k and split its sums over the poles (the
+    // partial sums are combined by lane exchanges, so all of them hold the
+    // same totals and take the same steps)
+    const int sub = threadIdx.x & (SRL - 1);
+    const int64_t k = (int64_t)blockIdx.x * SRW + (threadIdx.x / SRL);
     const bool act = k < K;
     const double rho = cnt[blockIdx.y].rho2;
     const double* d = dk + g.o;
@@ -372,13 +378,18 @@ __global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __r
     const bool last = kk >= K - 1;
     const double dkk = d[kk];
     const double mid = last ? 0.0 : 0.5 * (d[kk + 1] - dkk);
-    double f0 = 1.0, zz = 0.0;
+    double f0 = 0.0, zz = 0.0;
     stream([&](int64_t, int lim) {
         if (!last)
-            for (int q = 0; q < lim; ++q) f0 += sw[q] / ((sd[q] - dkk) - mid);
+            for (int q = sub; q < lim; q += SRL) f0 += sw[q] / ((sd[q] - dkk) - mid);
         else
-            for (int q = 0; q < lim; ++q) zz += sz[q] * sz[q];
+            for (int q = sub; q < lim; q += SRL) zz += sz[q] * sz[q];
     });
+    f0 += __shfl_xor(f0, 1, 64);
+    f0 += __shfl_xor(f0, 2, 64);
+    zz += __shfl_xor(zz, 1, 64);
+    zz += __shfl_xor(zz, 2, 64);
+    f0 += 1.0;
     int64_t org;
     double lo, hi;
     if (!last) {
@@ -411,19 +422,25 @@ __global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __r
             const int split = (int)std::min<int64_t>(std::max<int64_t>(kk + 1 - base, 0), lim);
             // one division per pole: t = w / dl and t / dl from 1 / dl
             // (two roundings each, well inside the stopping test's 8 eps)
-            for (int q = 0; q < split; ++q) {
+            for (int q = sub; q < lim; q += SRL) {
                 const double rl = 1.0 / ((sd[q] - dorg) - x);
                 const double tq = sw[q] * rl;
-                psi += tq;
-                dpsi += tq * rl;
-            }
-            for (int q = split; q < lim; ++q) {
-                const double rl = 1.0 / ((sd[q] - dorg) - x);
-                const double tq = sw[q] * rl;
-                phi += tq;
-                dphi += tq * rl;
+                if (q < split) {
+                    psi += tq;
+                    dpsi += tq * rl;
+                } else {
+                    phi += tq;
+                    dphi += tq * rl;
+                }
             }
         });
+#pragma unroll
+        for (int o = 1; o < SRL; o <<= 1) {
+            psi += __shfl_xor(psi, o, 64);
+            phi += __shfl_xor(phi, o, 64);
+            dpsi += __shfl_xor(dpsi, o, 64);
+            dphi += __shfl_xor(dphi, o, 64);
+        }
         if (done) continue;
         const double f = 1.0 + psi + phi;
         if (f < 0.0)
@@ -474,7 +491,7 @@ __global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __r
         }
         x = xn;
     }
-    if (!act) return;
+    if (!act || sub != 0) return;
     if (!converged) *fail = 2;
     lam[g.o + k] = dorg + x;
     rorg[g.o + k] = org;
@@ -751,7 +768,7 @@ int fl_stedc_device(fl_ctx* ctx, int64_t n, double* d, const double* e, double* 
         FL_HIP(ctx, hipGetLastError());
         merge_rotate_kernel<<<dim3(bx, nm), 256, 0, s>>>(md, cnt, ra, rb, rc, rs, Z, ldw);
         FL_HIP(ctx, hipGetLastError());
-        merge_secular_kernel<<<dim3((unsigned)FL_DIV_UP(Nmax, SNT), nm), SNT, 0, s>>>(md, cnt, dk, zk, rorg, rtau,
+        merge_secular_kernel<<<dim3((unsigned)FL_DIV_UP(Nmax, SRW), nm), SNT, 0, s>>>(md, cnt, dk, zk, rorg, rtau,
                                                                                       lam, fail);
         FL_HIP(ctx, hipGetLastError());
         merge_zhat_kernel<<<dim3(bx, nm), 256, 0, s>>>(md, cnt, dk, zk, rorg, rtau, zh);
