@@ -243,8 +243,11 @@ __global__ __launch_bounds__(256) void merge_deflate_kernel(const MergeDesc* __r
                     cz = zj;
                     continue;
                 }
-                const double r = hypot(cz, zj);
-                const double c = zj / r, s = cz / r;
+                // |z| <= 1 and, not deflated, rho' |z| > tol: the squares
+                // neither overflow nor underflow, so no hypot is needed
+                const double r = sqrt(cz * cz + zj * zj);
+                const double ir = 1.0 / r;
+                const double c = zj * ir, s = cz * ir;
                 const double tt = dj - cd;
                 const int64_t cp = ccol;
                 if (fabs(tt * c * s) <= tol) {
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(256) void merge_rotate_kernel(const MergeDesc* __re
 // iterates until all its roots have converged.
 constexpr int STILE = 1024;
 constexpr int SNT = 256;
-constexpr int SRL = 4;             // lanes per root: each sums every fourth pole
+constexpr int SRL = 8;             // lanes per root: each sums every eighth pole
 constexpr int SRW = SNT / SRL;     // roots per workgroup
 __global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __restrict__ md, const MergeCounts* __restrict__ cnt,
                                                             const double* __restrict__ dk, const double* __restrict__ zk,
@@ -385,10 +388,11 @@ __global__ __launch_bounds__(SNT) void merge_secular_kernel(const MergeDesc* __r
         else
             for (int q = sub; q < lim; q += SRL) zz += sz[q] * sz[q];
     });
-    f0 += __shfl_xor(f0, 1, 64);
-    f0 += __shfl_xor(f0, 2, 64);
-    zz += __shfl_xor(zz, 1, 64);
-    zz += __shfl_xor(zz, 2, 64);
+#pragma unroll
+    for (int o = 1; o < SRL; o <<= 1) {
+        f0 += __shfl_xor(f0, o, 64);
+        zz += __shfl_xor(zz, o, 64);
+    }
     f0 += 1.0;
     int64_t org;
     double lo, hi;
