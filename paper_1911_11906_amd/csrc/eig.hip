@@ -76,6 +76,26 @@ int clamp_band(int64_t n, int band) {
     return b;
 }
 
+// Band of the bulge chase.  Every task hands its blocks to a sweep on another
+// XCD, so the L2 keeps nothing reusable of it; in uncached memory the
+// agent-scope release and acquire of each task find no band lines to write
+// back or drop.  Uncached memory is not freed while the process runs (memory
+// allocated after such a free has been seen to hold wrong values), so the
+// context keeps one buffer, replaced by a larger one when needed (the old
+// one stays allocated).  Falls back to ordinary memory (returns null).
+double* band_buffer(fl_ctx* ctx, size_t bytes) {
+    if (ctx->band_uc_bytes < bytes) {
+        void* p = nullptr;
+        if (hipExtMallocWithFlags(&p, bytes, hipDeviceMallocUncached) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        ctx->band_uc = p;
+        ctx->band_uc_bytes = bytes;
+    }
+    return static_cast<double*>(ctx->band_uc);
+}
+
 int grid_for_sb2st(int64_t n, int b) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -103,7 +123,11 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
     const int64_t maxt = fl_sb2st_maxt(n, b);
     const int64_t nsw = std::max<int64_t>(1, n - 2);
     DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
-    FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+    double* ABp = band_buffer(ctx, sizeof(double) * ldab * n);
+    if (!ABp) {
+        FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+        ABp = bAB.as<double>();
+    }
     FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
     FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(double) * (size_t)n * n, s));  // Q1 reads above each panel
     FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
@@ -122,9 +146,9 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
     FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, bV1.as<double>(), n, bT1.as<double>(), btau1.as<double>(),
                          bwork.as<double>(), bpart.as<double>(), bcnt.as<unsigned>(), abort_flag));
-    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, bAB.as<double>(), ldab));
+    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, ABp, ldab));
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
-    FL_HIP(ctx, fl_sb2st(s, n, b, bAB.as<double>(), ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
+    FL_HIP(ctx, fl_sb2st(s, n, b, ABp, ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
                          grid_for_sb2st(n, b), abort_flag));
     {
         int ab = 0;
@@ -164,7 +188,11 @@ int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int ba
     const int64_t nsw = std::max<int64_t>(1, n - 2);
     DevBuf bA, bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
     FL_HIP(ctx, bA.alloc(sizeof(float) * (size_t)n * n));
-    FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+    double* ABp = band_buffer(ctx, sizeof(double) * ldab * n);
+    if (!ABp) {
+        FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+        ABp = bAB.as<double>();
+    }
     FL_HIP(ctx, bV1.alloc(sizeof(float) * (size_t)n * n));
     FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(float) * (size_t)n * n, s));  // Q1 reads above each panel
     FL_HIP(ctx, bT1.alloc(sizeof(float) * np * b * b));
@@ -186,7 +214,7 @@ int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int ba
         FL_HIP(ctx, fl_d2s(s, n, n, C, ldc, A, n));
         FL_HIP(ctx, fl_ssy2sb(s, n, b, A, n, bV1.as<float>(), n, bT1.as<float>(), btau1.as<float>(),
                               bwork.as<float>(), bpart.as<float>(), bcnt.as<unsigned>(), abort_flag));
-        FL_HIP(ctx, fl_extract_band_f(s, n, b, A, n, bAB.as<double>(), ldab));
+        FL_HIP(ctx, fl_extract_band_f(s, n, b, A, n, ABp, ldab));
     } else {
         // FP64 band reduction; its block reflectors are rounded to FP32 for Q1
         DevBuf bV1d, bT1d, btau1d, bworkd, bpartd;
@@ -198,13 +226,13 @@ int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int ba
         FL_HIP(ctx, bpartd.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
         FL_HIP(ctx, fl_sy2sb(s, n, b, C, ldc, bV1d.as<double>(), n, bT1d.as<double>(), btau1d.as<double>(),
                              bworkd.as<double>(), bpartd.as<double>(), bcnt.as<unsigned>(), abort_flag));
-        FL_HIP(ctx, fl_extract_band(s, n, b, C, ldc, bAB.as<double>(), ldab));
+        FL_HIP(ctx, fl_extract_band(s, n, b, C, ldc, ABp, ldab));
         FL_HIP(ctx, fl_d2s(s, n, n, bV1d.as<double>(), n, bV1.as<float>(), n));
         FL_HIP(ctx, fl_d2s(s, np * b, b, bT1d.as<double>(), np * b, bT1.as<float>(), np * b));
         FL_HIP(ctx, hipStreamSynchronize(s));  // the FP64 buffers are released at scope exit
     }
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
-    FL_HIP(ctx, fl_sb2st(s, n, b, bAB.as<double>(), ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
+    FL_HIP(ctx, fl_sb2st(s, n, b, ABp, ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
                          grid_for_sb2st(n, b), abort_flag));
     {
         int ab = 0;
@@ -405,7 +433,11 @@ int fl_dsytrd_2stage(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, d
     const int64_t maxt = fl_sb2st_maxt(n, b);
     const int64_t nsw = std::max<int64_t>(1, n - 2);
     DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
-    FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+    double* ABp = band_buffer(ctx, sizeof(double) * ldab * n);
+    if (!ABp) {
+        FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+        ABp = bAB.as<double>();
+    }
     FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
     FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(double) * (size_t)n * n, s));  // Q1 reads above each panel
     FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
@@ -421,8 +453,8 @@ int fl_dsytrd_2stage(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, d
     FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
     FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, bV1.as<double>(), n, bT1.as<double>(), btau1.as<double>(), bwork.as<double>(),
                          bpart.as<double>(), bcnt.as<unsigned>(), abort_flag));
-    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, bAB.as<double>(), ldab));
-    FL_HIP(ctx, fl_sb2st(s, n, b, bAB.as<double>(), ldab, d, be.as<double>(), bV2.as<double>(), btau2.as<double>(),
+    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, ABp, ldab));
+    FL_HIP(ctx, fl_sb2st(s, n, b, ABp, ldab, d, be.as<double>(), bV2.as<double>(), btau2.as<double>(),
                          bprog.as<int>(), grid_for_sb2st(n, b), abort_flag));
     {
         int ab = 0;

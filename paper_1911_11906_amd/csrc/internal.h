@@ -10,6 +10,10 @@ struct fl_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // band of the bulge chase in uncached memory, grown on demand and never
+    // freed (see band_buffer in eig.hip)
+    void* band_uc = nullptr;
+    size_t band_uc_bytes = 0;
 };
 
 struct fl_op {
