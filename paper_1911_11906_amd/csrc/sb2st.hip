@@ -198,8 +198,13 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
                 if (r < Lb && c < L) AB[(q0 + r - (r0 + c)) + (r0 + c) * ldab] = Bbl[r + c * LDB];
             }
             double* vout = V2 + (i * maxt + j) * (int64_t)b;
-            for (int r = t; r < b; r += NTH) vout[r] = (r < L) ? vv[r] : 0.0;
-            if (t == 0) tau2[i * maxt + j] = tauc;
+            // reflectors are read only by the back-transform, after the
+            // launch: written through to memory (system-scope relaxed
+            // stores) so that the per-task release has no dirty lines of
+            // them to write back
+            for (int r = t; r < b; r += NTH)
+                __hip_atomic_store(&vout[r], (r < L) ? vv[r] : 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (t == 0) __hip_atomic_store(&tau2[i * maxt + j], tauc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             // ---- publish progress: every wave first waits for its own stores
             // (a plain workgroup barrier waits for LDS traffic only), then
             // thread 0's agent-scope release writes the L2 back and sets the flag
