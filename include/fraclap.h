@@ -98,6 +98,10 @@ typedef struct fl_eig_info {
  * legacy default stream).  *out receives the context. */
 int fl_ctx_create(int device, void *hip_stream, fl_ctx **out);
 int fl_ctx_set_stream(fl_ctx *ctx, void *hip_stream);
+/* Frees the context.  The uncached buffer that an eigensolve of this context
+ * allocated for the bulge chase's band ((2 band + 1) n doubles for the
+ * largest n solved) is not freed: uncached device memory stays allocated until
+ * the process ends. */
 void fl_ctx_destroy(fl_ctx *ctx);
 /* Message for the last non-OK status on this context ("" if none). */
 const char *fl_last_error(const fl_ctx *ctx);
