@@ -74,7 +74,8 @@ struct BScaled {
     }
     __device__ inline double at(const H& h, int64_t kk) const { return h.w[kk] * h.c[kk]; }
     static constexpr bool KSCALE = false;
-    __device__ inline double kscale(int64_t, int64_t) const { return 1.0; }
+    __device__ inline const double* kcol(int64_t) const { return nullptr; }
+    __device__ inline double kscale(const double*, int64_t) const { return 1.0; }
 };
 
 // Same operand when every column of a 128-wide tile has the same alpha
@@ -95,7 +96,9 @@ struct BScaledUniform {
     }
     __device__ inline double at(const H& h, int64_t kk) const { return h.c[kk]; }
     static constexpr bool KSCALE = true;
-    __device__ inline double kscale(int64_t col0, int64_t kk) const { return W[kk + (col0 / nf) * ldw]; }
+    // the weight column of the tile's alpha (one index division per tile)
+    __device__ inline const double* kcol(int64_t col0) const { return W + (col0 / nf) * ldw; }
+    __device__ inline double kscale(const double* wc, int64_t kk) const { return wc[kk]; }
 };
 
 template <class BS>

@@ -66,9 +66,11 @@ struct BPlainT {
     };
     __device__ inline H col(int64_t j) const { return trans ? H{B + j, ldb} : H{B + j * ldb, 1}; }
     __device__ inline T at(const H& h, int64_t kk) const { return h.p[kk * h.stride]; }
-    // per-(tile, k-row) factor applied to every element of that k-row
+    // per-(tile, k-row) factor applied to every element of that k-row:
+    // kcol(first column of the tile) once per tile, then kscale(kcol, k)
     static constexpr bool KSCALE = false;
-    __device__ inline T kscale(int64_t, int64_t) const { return T(1); }
+    __device__ inline const T* kcol(int64_t) const { return nullptr; }
+    __device__ inline T kscale(const T*, int64_t) const { return T(1); }
 };
 typedef BPlainT<double> BPlain;
 
@@ -123,6 +125,7 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __res
     // outputs that are never stored); only a partial last k-step clamps k and
     // writes zeros for the rows past k.  No load sits in a branch, so the
     // compiler need not wait for one before the next.
+    const auto kc = bs.kcol(j0);  // per-tile k-row factors (KSCALE sources)
     auto gload = [&](int64_t k0, auto edge) {
         constexpr bool EDGE = decltype(edge)::value;
 #pragma unroll
@@ -140,7 +143,7 @@ __device__ inline void tile_gemm(int64_t m, int64_t n, int64_t k, const T* __res
         if (BSrc::KSCALE && KFAST_B) {
             int64_t gk = k0 + (t % KB);
             if (EDGE) gk = gk < k ? gk : k - 1;
-            ks = bs.kscale(j0, gk);
+            ks = bs.kscale(kc, gk);
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {

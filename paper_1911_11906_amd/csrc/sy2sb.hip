@@ -19,8 +19,9 @@
 namespace {
 
 constexpr int PNT = 256;   // threads per panel workgroup
+constexpr int NGRP = PNT / 64;  // row groups (one wave each)
 constexpr int PRPT = 32;   // panel rows per thread-row-group
-constexpr int PROWS = 4 * PRPT;  // rows per workgroup slab (4 groups of 64 column lanes)
+constexpr int PROWS = NGRP * PRPT;  // rows per workgroup slab (NGRP groups of 64 column lanes)
 
 constexpr long SPIN_CAP = 20000000;  // bounded wait: every wave exits even if a peer never arrives
 
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
                                                        int* abort) {
     __shared__ T xc[PROWS];   // pivot column c (this slab's rows)
     __shared__ T xd[PROWS];   // column c+1: before reflector c (Gram row), after it (second update)
-    __shared__ T red[4][64], red2[4][64];
+    __shared__ T red[NGRP][64], red2[NGRP][64];
     __shared__ T wv[64], gv[64];
     __shared__ T sc[8];  // scale, tau, beta, | scale', tau', beta', pair flag
     const int t = threadIdx.x;
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
     T v[PRPT];
 #pragma unroll
     for (int q = 0; q < PRPT; ++q) {
-        int64_t r = slab0 + grp + 4 * q;
+        int64_t r = slab0 + grp + NGRP * q;
         v[q] = (r < m && lane < kb) ? P[r + lane * lda] : T(0);
     }
     unsigned k = 0;  // exchanges so far
@@ -97,20 +98,20 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         // pivot column (and column c+1) into LDS
         if (lane == c) {
 #pragma unroll
-            for (int q = 0; q < PRPT; ++q) xc[grp + 4 * q] = v[q];
+            for (int q = 0; q < PRPT; ++q) xc[grp + NGRP * q] = v[q];
         }
         if (try2 && lane == c + 1) {
 #pragma unroll
-            for (int q = 0; q < PRPT; ++q) xd[grp + 4 * q] = v[q];
+            for (int q = 0; q < PRPT; ++q) xd[grp + NGRP * q] = v[q];
         }
         __syncthreads();
         // partial sums over this slab: s_j (rows > c), g_j (rows > c+1)
         T s = T(0), g = T(0);
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
-            int64_t r = slab0 + grp + 4 * q;
-            if (r > c && r < m) s += xc[grp + 4 * q] * v[q];
-            if (try2 && r > c + 1 && r < m) g += xd[grp + 4 * q] * v[q];
+            int64_t r = slab0 + grp + NGRP * q;
+            if (r > c && r < m) s += xc[grp + NGRP * q] * v[q];
+            if (try2 && r > c + 1 && r < m) g += xd[grp + NGRP * q] * v[q];
         }
         red[grp][lane] = s;
         red2[grp][lane] = g;
@@ -120,14 +121,20 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
             const int64_t row = c + h;
             if ((h == 0 || try2) && slab0 <= row && row < slab0 + PROWS) {
                 int lr = (int)(row - slab0);
-                if (grp == (lr & 3)) prow[par * 128 + h * 64 + lane] = v[lr >> 2];
+                if (grp == lr % NGRP) prow[par * 128 + h * 64 + lane] = v[lr / NGRP];
             }
         }
         __syncthreads();
         if (t < 64) {
             T* pw = part + (size_t)par * G * 128 + (size_t)blockIdx.x * 128;
-            pw[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-            pw[64 + t] = red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
+            T a = T(0), a2 = T(0);
+#pragma unroll
+            for (int q = 0; q < NGRP; ++q) {
+                a += red[q][t];
+                a2 += red2[q][t];
+            }
+            pw[t] = a;
+            pw[64 + t] = a2;
         }
         // every wave waits for its own stores (partials, published rows); the
         // barrier's single agent-scope release then writes the L2 back once
@@ -136,27 +143,27 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         ++k;
         if (!grid_barrier(counter, k * G, abort)) return;
         // reduce the partials of all workgroups in a fixed order (the same in
-        // every workgroup): row group q sums workgroups q, q+4, ..., the four
-        // sums are added in LDS.  The loads (which miss the cache after the
+        // every workgroup): row group q sums workgroups q, q+NGRP, ..., the
+        // NGRP sums are added in LDS.  The loads (which miss the cache after the
         // barrier) are issued RB at a time before the additions, from
         // clamped, always valid addresses.
         {
             constexpr int RB = 16;
             T acc = T(0), acc2 = T(0);
             const T* pp = part + (size_t)par * G * 128 + lane;
-            for (unsigned w0 = (unsigned)grp; w0 < G; w0 += 4 * RB) {
+            for (unsigned w0 = (unsigned)grp; w0 < G; w0 += NGRP * RB) {
                 T buf[RB], buf2[RB];
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
-                    const unsigned w = w0 + 4 * q;
+                    const unsigned w = w0 + NGRP * q;
                     const size_t o = (size_t)(w < G ? w : 0) * 128;
                     buf[q] = pp[o];
                     buf2[q] = pp[o + 64];
                 }
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
-                    acc += (w0 + 4 * q < G) ? buf[q] : T(0);
-                    acc2 += (w0 + 4 * q < G) ? buf2[q] : T(0);
+                    acc += (w0 + NGRP * q < G) ? buf[q] : T(0);
+                    acc2 += (w0 + NGRP * q < G) ? buf2[q] : T(0);
                 }
             }
             red[grp][lane] = acc;
@@ -164,8 +171,14 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         }
         __syncthreads();
         if (t < 64) {
-            wv[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-            gv[t] = (red2[0][t] + red2[1][t]) + (red2[2][t] + red2[3][t]);
+            T a = T(0), a2 = T(0);
+#pragma unroll
+            for (int q = 0; q < NGRP; ++q) {
+                a += red[q][t];
+                a2 += red2[q][t];
+            }
+            wv[t] = a;
+            gv[t] = a2;
         }
         __syncthreads();
         const T* r0v = prow + par * 128;       // row c
@@ -228,13 +241,13 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         const T wj = (lane > c && lane < kb) ? (r0v[lane] + scale * wv[lane]) : T(0);
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
-            int64_t r = slab0 + grp + 4 * q;
+            int64_t r = slab0 + grp + NGRP * q;
             if (r >= m) continue;
             if (lane == c) {
                 if (r > c) v[q] = scale * v[q];          // reflector entry
                 else if (r == c) v[q] = beta;
             } else if (lane > c && lane < kb) {
-                T vr = (r > c) ? scale * xc[grp + 4 * q] : (r == c ? T(1) : T(0));
+                T vr = (r > c) ? scale * xc[grp + NGRP * q] : (r == c ? T(1) : T(0));
                 v[q] -= tauc * vr * wj;
             }
         }
@@ -257,18 +270,18 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         // column c+1 after reflector c, for the second update
         if (lane == c + 1) {
 #pragma unroll
-            for (int q = 0; q < PRPT; ++q) xd[grp + 4 * q] = v[q];
+            for (int q = 0; q < PRPT; ++q) xd[grp + NGRP * q] = v[q];
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
-            int64_t r = slab0 + grp + 4 * q;
+            int64_t r = slab0 + grp + NGRP * q;
             if (r >= m) continue;
             if (lane == c + 1) {
                 if (r > c + 1) v[q] = scale2 * v[q];
                 else if (r == c + 1) v[q] = beta2;
             } else if (lane > c + 1 && lane < kb) {
-                T vr = (r > c + 1) ? scale2 * xd[grp + 4 * q] : (r == c + 1 ? T(1) : T(0));
+                T vr = (r > c + 1) ? scale2 * xd[grp + NGRP * q] : (r == c + 1 ? T(1) : T(0));
                 v[q] -= tau2 * vr * wj2;
             }
         }
@@ -278,7 +291,7 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
     // write back the factored panel and the explicit reflectors
 #pragma unroll
     for (int q = 0; q < PRPT; ++q) {
-        int64_t r = slab0 + grp + 4 * q;
+        int64_t r = slab0 + grp + NGRP * q;
         if (r < m && lane < kb) {
             P[r + lane * lda] = v[q];
             if (lane < kref) Vx[r + lane * ldv] = (r > lane) ? v[q] : (r == lane ? T(1) : T(0));
