@@ -91,6 +91,33 @@ def test_sytrd_2stage(ctx, oracle_mod, n, b):
     assert np.abs(np.sort(np.linalg.eigvalsh(T)) - np.sort(wo)).max() <= 100 * n * EPS * scale
 
 
+@pytest.mark.parametrize("kind", ["smooth", "lowrank", "diagonal"])
+def test_sytrd_2stage_structured(ctx, oracle_mod, kind):
+    """Panels with nearly dependent or zero columns: the band reduction's
+    two-reflectors-per-exchange step must fall back to single steps (smooth
+    kernel matrix, low-rank plus small diagonal) or see zero columns
+    (diagonal input), and the factorisation stays orthogonal and exact."""
+    n, b = 700, 64
+    note("sytrd_2stage_structured", kind, n, b)
+    i = np.arange(n)
+    if kind == "smooth":
+        A = np.exp(-((i[:, None] - i[None, :]) / 40.0) ** 2)
+    elif kind == "lowrank":
+        rng = np.random.default_rng(11)
+        U = rng.standard_normal((n, 6))
+        A = U @ U.T + 1e-9 * np.diag(rng.standard_normal(n))
+    else:
+        A = np.diag(np.linspace(1.0, 2.0, n))
+    d, e, Q = ctx.dsytrd_2stage(A, band=b)
+    d, e, Q = to_np(d), to_np(e), to_np(Q)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    scale = np.abs(A).max()
+    assert np.abs(Q.T @ Q - np.eye(n)).max() <= 100 * n * EPS
+    assert np.abs(Q @ T @ Q.T - A).max() <= 100 * n * EPS * scale
+    wo, _, _ = oracle_mod.jacobi(A)
+    assert np.abs(np.sort(np.linalg.eigvalsh(T)) - np.sort(wo)).max() <= 100 * n * EPS * scale
+
+
 @pytest.mark.parametrize("n,b", [(50, 8), (513, 64), (1000, 32)])
 def test_syevd(ctx, oracle_mod, n, b):
     note("syevd", n, b)
