@@ -618,6 +618,189 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
     }
 }
 
+// Blocked variant for n >= SYTRD_BLK_MIN: the rank-2 updates of up to NBB
+// consecutive steps stay pending in P = [V | W] (global, n x 2 NBB, ld n,
+// zeros above each vector's first row) and are applied to the trailing
+// matrix in two workgroup products every NBB steps.  A step sees the current
+// matrix through them: its column gets the pending updates before the
+// Householder step, and the product with the new v is formed from the stale
+// matrix (one read-only pass instead of a read-write pass) and corrected by
+// V (W^T v) + W (V^T v).  Same reflectors as wg_sytrd in exact arithmetic.
+constexpr int NBB = 32;
+constexpr int SYTRD_BLK_MIN = 256;
+
+__device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t lda, double* tau, double* P, Lds& s) {
+    const int t = threadIdx.x;
+    double* PV = P;                    // column i: v_i (global rows)
+    double* PW = P + (int64_t)NBB * n; // column i: w_i
+    int np = 0;                        // pending pairs
+    // append (v, w) of the reflector whose first row is r1 (v, w indexed from r1)
+    auto append = [&](int r1, const double* v, const double* w) {
+        for (int g = t; g < n; g += BT) {
+            const bool in = g >= r1;
+            PV[g + (int64_t)np * n] = in ? v[g - r1] : 0.0;
+            PW[g + (int64_t)np * n] = in ? w[g - r1] : 0.0;
+        }
+        ++np;
+        gsync();
+    };
+    // A[f:, f:] -= V W^T + W V^T over the pending pairs
+    auto flush = [&](int f) {
+        if (np > 0 && f < n) {
+            const int mm = n - f;
+            wg_gemm(false, true, mm, mm, np, -1.0, PV + f, n, PW + f, n, 1.0, A + f + (int64_t)f * lda, lda, s);
+            wg_gemm(false, true, mm, mm, np, -1.0, PW + f, n, PV + f, n, 1.0, A + f + (int64_t)f * lda, lda, s);
+        }
+        np = 0;
+    };
+    // reflector 0 and w_0 (no pending updates yet)
+    {
+        double beta;
+        if (t == 0) s.dval[1] = A[1];
+        __syncthreads();
+        const double tk = wg_house(n, 1, n - 1, A, s.dval[1], s.va[0], &beta, s);
+        if (t == 0) {
+            s.dd[0] = A[0];
+            s.ee[0] = beta;
+            tau[0] = tk;
+        }
+        __syncthreads();
+        double acc[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+        for (int j = 1; j < n; ++j) {
+            const double vj = s.va[0][j - 1];
+            const double* col = A + (int64_t)j * lda;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int g = t + q * BT;
+                if (g >= 1 && g < n) acc[q] = fma(col[g], vj, acc[q]);
+            }
+        }
+        wg_make_w(n, 1, n - 1, tk, acc, s.va[0], s.wa[0], s);
+        append(1, s.va[0], s.wa[0]);
+    }
+    const gdouble* gA = (const gdouble*)A;
+    for (int k = 0; k < n - 3; ++k) {
+        const int nxt = (k + 1) & 1;
+        const int64_t g0 = k + 1;  // column of reflector k+1, first row/column of A22
+        const int m = n - k - 1;   // order of A22
+        if (np == NBB) flush((int)g0);
+        // (a) column g0, rows g0.., with the pending updates
+        {
+            double* c0 = A + g0 * lda;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t g = t + q * BT;
+                if (g < n && g >= g0) {
+                    double a = c0[g];
+                    for (int i = 0; i < np; ++i)
+                        a -= PV[g + (int64_t)i * n] * PW[g0 + (int64_t)i * n] +
+                             PW[g + (int64_t)i * n] * PV[g0 + (int64_t)i * n];
+                    c0[g] = a;
+                    if (g == g0) s.dval[0] = a;
+                    if (g == g0 + 1) s.dval[1] = a;
+                }
+            }
+        }
+        gsync();
+        // (b) reflector k+1 from rows g0+1.. of that column
+        double beta;
+        const double tk = wg_house(n, g0 + 1, m - 1, A + g0 * lda, s.dval[1], s.va[nxt], &beta, s);
+        if (t == 0) {
+            s.dd[k + 1] = s.dval[0];
+            s.ee[k + 1] = beta;
+            tau[k + 1] = tk;
+        }
+        __syncthreads();
+        const double* v2 = s.va[nxt];  // indexed from global row g0+1
+        // (c) acc = A22_stale v2: one read-only pass, two chunk buffers in turn
+        double acc[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+        if (t < n) {
+            double ca[SU][RPT], cb[SU][RPT];
+            auto mac = [&](const double (&cur)[SU][RPT], int j0) {
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int j = j0 + u;
+                    const double v2j = (j < m) ? v2[j - 1] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) acc[q] = fma(cur[u][q], v2j, acc[q]);
+                }
+            };
+            sytrd_load_chunk(gA, lda, g0, 1, m, n, ca);
+            int j0 = 1;
+            for (; j0 + 2 * SU <= m; j0 += 2 * SU) {
+                sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                mac(ca, j0);
+                sytrd_load_chunk(gA, lda, g0, j0 + 2 * SU, m, n, ca);
+                mac(cb, j0 + SU);
+            }
+            if (j0 < m) {
+                sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                mac(ca, j0);
+                mac(cb, j0 + SU);
+            }
+        }
+        // corrections: acc -= V (W^T v2) + W (V^T v2) over rows g0+1..
+        {
+            double* dots = &s.qx[0][0];  // 2 NBB sums: alpha_i = w_i^T v2, beta_i = v_i^T v2
+            for (int i = 0; i < np; ++i) {
+                double pa = 0.0, pb = 0.0;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const int64_t g = t + q * BT;
+                    if (g < n && g >= g0 + 1) {
+                        const double vg = v2[g - g0 - 1];
+                        pa += PW[g + (int64_t)i * n] * vg;
+                        pb += PV[g + (int64_t)i * n] * vg;
+                    }
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    pa += __shfl_xor(pa, o, 64);
+                    pb += __shfl_xor(pb, o, 64);
+                }
+                if ((t & 63) == 0) {
+                    s.qy[0][(t >> 6) * 2 * NBB + i] = pa;
+                    s.qy[0][(t >> 6) * 2 * NBB + NBB + i] = pb;
+                }
+            }
+            __syncthreads();
+            if (t < 2 * np) {
+                const int i = (t < np) ? t : NBB + (t - np);
+                double a = 0.0;
+                for (int w = 0; w < BT / 64; ++w) a += s.qy[0][w * 2 * NBB + i];
+                dots[i] = a;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t g = t + q * BT;
+                if (g < n && g >= g0 + 1) {
+                    double c = 0.0;
+                    for (int i = 0; i < np; ++i)
+                        c += PV[g + (int64_t)i * n] * dots[i] + PW[g + (int64_t)i * n] * dots[NBB + i];
+                    acc[q] -= c;
+                }
+            }
+        }
+        // (d) w of step k+1, then the pair joins the pending ones
+        wg_make_w(n, g0 + 1, m - 1, tk, acc, v2, s.wa[nxt], s);
+        append((int)g0 + 1, v2, s.wa[nxt]);
+    }
+    // the last 2 x 2 block, rows and columns n-2, n-1, after all pending updates
+    flush(n - 2);
+    gsync();
+    if (t == 0) {
+        s.dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * lda];
+        s.ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
+        s.dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * lda];
+        s.ee[n - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
 // Z := Q Z with Q = H_0 H_1 ... H_{n-3} from wg_sytrd, applied as block
 // reflectors of PB consecutive H (forward, columnwise: I - V T V^T), last
 // block first.  work: >= 3 PB n + PB PB doubles.
@@ -1203,7 +1386,10 @@ __device__ int64_t solve_one(const BProb& p, Lds& s) {
             A[j + (int64_t)i * n] = v;
         }
     gsync();
-    wg_sytrd(n, A, n, p.tau, s);
+    if (n >= SYTRD_BLK_MIN)
+        wg_sytrd_blk(n, A, n, p.tau, p.U, s);
+    else
+        wg_sytrd(n, A, n, p.tau, s);
     const int dc = wg_stedc(n, Z, n, W, p.U, p.Y, p.R, s);
     gsync();
     if (dc) return -(int64_t)dc;
