@@ -1,12 +1,14 @@
-// FP64 MFMA GEMM tile machinery shared by the plain GEMM and the fused
-// spectral-application GEMM (operand B produced on the fly).
+// FP64 / FP32 MFMA GEMM tile machinery shared by the plain GEMMs and the
+// fused spectral-application GEMM (operand B produced on the fly).
 //
 // v_mfma_f64_16x16x4f64 operand layout (measured on gfx950): lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l holds
 // D[l/16 + 4r][l%16].  We compute C^T tiles (MFMA "A" <- op(B), "B" <- op(A))
 // so that lanes sharing an accumulator row write consecutive rows of the
-// column-major C.  Workgroup tile 128 x 128, k-step 16, 256 threads as 2 x 2
-// waves of 64 x 64, operands staged k-major in LDS and double buffered.
+// column-major C.  Workgroup tile 128 x 128 (or 256 x 64), 256 threads as
+// four waves of 64 x 64, operands staged k-major in LDS; the next k-step's
+// operands are prefetched into registers (NBUF = 1) or a second LDS buffer
+// (NBUF = 2) while the current one is multiplied.
 #pragma once
 #include "common.h"
 #include <type_traits>
