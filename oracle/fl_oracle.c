@@ -131,7 +131,7 @@ int or_assemble(int elem, int64_t n_nodes, const double *xy, int64_t n_elem,
     if (Mfull) memset(Mfull, 0, sizeof(double) * (size_t)n_nodes * (size_t)n_nodes);
     int nv = elem;
     for (int64_t e = 0; e < n_elem; ++e) {
-        double x[4], y[4], Ke[16], Me[16];
+        double x[4] = {0}, y[4] = {0}, Ke[16], Me[16];  // nv (3 or 4) entries are set below
         for (int a = 0; a < nv; ++a) {
             int32_t v = conn[e * nv + a];
             x[a] = xy[2 * (size_t)v];
