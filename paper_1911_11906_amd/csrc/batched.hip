@@ -628,6 +628,26 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
 // V (W^T v) + W (V^T v).  Same reflectors as wg_sytrd in exact arithmetic.
 constexpr int NBB = 32;
 constexpr int SYTRD_BLK_MIN = 256;
+constexpr int PU = 8;  // pending pairs read per batch of loads
+
+// Entries of pending pairs i0 .. i0+PU-1 (clamped to np-1) at this thread's
+// rows (clamped to n-1): all loads issued before any is used, so a batch
+// costs one memory latency instead of PU.
+__device__ inline void pend_rows(const double* PV, const double* PW, int n, int np, int i0,
+                                 double (&pv)[PU][RPT], double (&pw)[PU][RPT]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+        const int64_t i = (i0 + u < np) ? i0 + u : np - 1;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int g = t + q * BT;
+            const int64_t gg = g < n ? g : n - 1;
+            pv[u][q] = PV[gg + i * n];
+            pw[u][q] = PW[gg + i * n];
+        }
+    }
+}
 
 __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t lda, double* tau, double* P, Lds& s) {
     const int t = threadIdx.x;
@@ -686,20 +706,41 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t
         const int64_t g0 = k + 1;  // column of reflector k+1, first row/column of A22
         const int m = n - k - 1;   // order of A22
         if (np == NBB) flush((int)g0);
-        // (a) column g0, rows g0.., with the pending updates
+        // (a) column g0, rows g0.., with the pending updates (row g0 of the
+        // pending pairs staged in LDS first)
         {
+            double* r0 = &s.qx[1][0];  // [0, NBB): v_i[g0], [NBB, 2 NBB): w_i[g0]
+            if (t < np) {
+                r0[t] = PV[g0 + (int64_t)t * n];
+                r0[NBB + t] = PW[g0 + (int64_t)t * n];
+            }
+            __syncthreads();
             double* c0 = A + g0 * lda;
+            double a[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int g = t + q * BT;
+                a[q] = c0[g < n ? g : n - 1];
+            }
+            for (int i0 = 0; i0 < np; i0 += PU) {
+                double pv[PU][RPT], pw[PU][RPT];
+                pend_rows(PV, PW, n, np, i0, pv, pw);
+#pragma unroll
+                for (int u = 0; u < PU; ++u) {
+                    if (i0 + u < np) {
+#pragma unroll
+                        for (int q = 0; q < RPT; ++q)
+                            a[q] -= pv[u][q] * r0[NBB + i0 + u] + pw[u][q] * r0[i0 + u];
+                    }
+                }
+            }
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int64_t g = t + q * BT;
                 if (g < n && g >= g0) {
-                    double a = c0[g];
-                    for (int i = 0; i < np; ++i)
-                        a -= PV[g + (int64_t)i * n] * PW[g0 + (int64_t)i * n] +
-                             PW[g + (int64_t)i * n] * PV[g0 + (int64_t)i * n];
-                    c0[g] = a;
-                    if (g == g0) s.dval[0] = a;
-                    if (g == g0 + 1) s.dval[1] = a;
+                    c0[g] = a[q];
+                    if (g == g0) s.dval[0] = a[q];
+                    if (g == g0 + 1) s.dval[1] = a[q];
                 }
             }
         }
@@ -746,24 +787,33 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t
         // corrections: acc -= V (W^T v2) + W (V^T v2) over rows g0+1..
         {
             double* dots = &s.qx[0][0];  // 2 NBB sums: alpha_i = w_i^T v2, beta_i = v_i^T v2
-            for (int i = 0; i < np; ++i) {
-                double pa = 0.0, pb = 0.0;
+            double vg[RPT];
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) {
-                    const int64_t g = t + q * BT;
-                    if (g < n && g >= g0 + 1) {
-                        const double vg = v2[g - g0 - 1];
-                        pa += PW[g + (int64_t)i * n] * vg;
-                        pb += PV[g + (int64_t)i * n] * vg;
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t g = t + q * BT;
+                vg[q] = (g < n && g >= g0 + 1) ? v2[g - g0 - 1] : 0.0;
+            }
+            for (int i0 = 0; i0 < np; i0 += PU) {
+                double pv[PU][RPT], pw[PU][RPT];
+                pend_rows(PV, PW, n, np, i0, pv, pw);
+#pragma unroll
+                for (int u = 0; u < PU; ++u) {
+                    if (i0 + u < np) {
+                        double pa = 0.0, pb = 0.0;
+#pragma unroll
+                        for (int q = 0; q < RPT; ++q) {
+                            pa += pw[u][q] * vg[q];
+                            pb += pv[u][q] * vg[q];
+                        }
+                        for (int o = 32; o > 0; o >>= 1) {
+                            pa += __shfl_xor(pa, o, 64);
+                            pb += __shfl_xor(pb, o, 64);
+                        }
+                        if ((t & 63) == 0) {
+                            s.qy[0][(t >> 6) * 2 * NBB + i0 + u] = pa;
+                            s.qy[0][(t >> 6) * 2 * NBB + NBB + i0 + u] = pb;
+                        }
                     }
-                }
-                for (int o = 32; o > 0; o >>= 1) {
-                    pa += __shfl_xor(pa, o, 64);
-                    pb += __shfl_xor(pb, o, 64);
-                }
-                if ((t & 63) == 0) {
-                    s.qy[0][(t >> 6) * 2 * NBB + i] = pa;
-                    s.qy[0][(t >> 6) * 2 * NBB + NBB + i] = pb;
                 }
             }
             __syncthreads();
@@ -774,15 +824,24 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t
                 dots[i] = a;
             }
             __syncthreads();
+            double c[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) c[q] = 0.0;
+            for (int i0 = 0; i0 < np; i0 += PU) {
+                double pv[PU][RPT], pw[PU][RPT];
+                pend_rows(PV, PW, n, np, i0, pv, pw);
+#pragma unroll
+                for (int u = 0; u < PU; ++u) {
+                    if (i0 + u < np) {
+#pragma unroll
+                        for (int q = 0; q < RPT; ++q) c[q] += pv[u][q] * dots[i0 + u] + pw[u][q] * dots[NBB + i0 + u];
+                    }
+                }
+            }
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int64_t g = t + q * BT;
-                if (g < n && g >= g0 + 1) {
-                    double c = 0.0;
-                    for (int i = 0; i < np; ++i)
-                        c += PV[g + (int64_t)i * n] * dots[i] + PW[g + (int64_t)i * n] * dots[NBB + i];
-                    acc[q] -= c;
-                }
+                if (g < n && g >= g0 + 1) acc[q] -= c[q];
             }
         }
         // (d) w of step k+1, then the pair joins the pending ones
