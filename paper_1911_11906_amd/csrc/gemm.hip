@@ -38,10 +38,10 @@ struct Prob {
 // range: FL_KT_A_LOWER op(A)[i][k] = 0 for k > i; FL_KT_A_UPPER for k < i;
 // FL_KT_B_LOWER op(B)[k][j] = 0 for k < j.  (BM = BN is a multiple of the
 // k-step, so the shortened ranges stay aligned.)
-template <class T, bool TA, bool TB, bool LOWER, int KT = FL_KT_NONE>
+template <class T, bool TA, bool TB, bool LOWER, int KT = FL_KT_NONE, int KB = GKB>
 __global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void gemm_kernel(Prob<T> g) {
-    __shared__ T As[TileLds<GKB, GNBUF>::A];
-    __shared__ T Bs[TileLds<GKB, GNBUF>::B];
+    __shared__ T As[TileLds<KB, GNBUF>::A];
+    __shared__ T Bs[TileLds<KB, GNBUF>::B];
     int64_t bi = blockIdx.x, bj = blockIdx.y;
     if (KT == FL_KT_A_LOWER || KT == FL_KT_A_UPPER) {
         // tiles differ in k length by row block: hand out the row blocks in
@@ -61,8 +61,8 @@ __global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void gemm_kernel(Prob<T> 
     const T* A = TA ? g.A + kb : g.A + kb * g.lda;
     const T* B = TB ? g.B + kb * g.ldb : g.B + kb;
     BPlainT<T> bsrc{B, g.ldb, TB};
-    tile_gemm<TA, !TB, BPlainT<T>, GKB, GNBUF, T>(g.m, g.n, ke - kb, A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi,
-                                                  bj, As, Bs);
+    tile_gemm<TA, !TB, BPlainT<T>, KB, GNBUF, T>(g.m, g.n, ke - kb, A, g.lda, bsrc, g.alpha, g.beta, g.C, g.ldc, bi,
+                                                 bj, As, Bs);
 }
 
 // Lower triangle of a square tile grid: one block per tile on or below the
@@ -216,6 +216,12 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
         }
     }
     dim3 grid((unsigned)tm, (unsigned)tn);
+    // long FP32 products: k-step 32 fits the same registers and LDS bytes as
+    // FP64's 16 and halves the barriers per flop
+    if (!lower && sizeof(T) == 4 && g.k >= 8192) {
+        gemm_kernel<T, TA, TB, false, FL_KT_NONE, 2 * GKB><<<grid, NT, 0, s>>>(g);
+        return hipGetLastError();
+    }
     if (lower && tm == tn) {
         const int64_t nt = tm * (tm + 1) / 2;
         gemm_lower_kernel<T, TA, TB><<<(unsigned)nt, NT, 0, s>>>(g, nt);
