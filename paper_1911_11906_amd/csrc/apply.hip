@@ -107,7 +107,9 @@ __global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void scaled_gemm_kernel(i
                                                          int64_t ldu) {
     __shared__ double As[TileLds<16, 1>::A];
     __shared__ double Bs[TileLds<16, 1>::B];
-    tile_gemm<false, true, BS, 16, 1>(n, ncol, n, V, ldv, bs, 1.0, 0.0, U, ldu, blockIdx.x, blockIdx.y, As, Bs);
+    int64_t bi, bj;
+    xcd_grouped_tile(bi, bj);
+    tile_gemm<false, true, BS, 16, 1>(n, ncol, n, V, ldv, bs, 1.0, 0.0, U, ldu, bi, bj, As, Bs);
 }
 
 // galpha[b] = sum_k P[k,b] * (-0.5 ln theta_k) * W[k,b] * C[k,b]; one block per b,
