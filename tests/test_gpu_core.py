@@ -181,3 +181,23 @@ def test_apply_uniform_tile_path(ctx, oracle_mod, c1_oracle):
     Uo = oracle_mod.apply_fractional(th, V, M, F, al)
     assert np.abs(U - Uo).max() <= 1e-12 * np.abs(Uo).max()
     assert np.abs(U[:, :256] - F).max() <= 2e-12 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("nf,na", [(256, 4), (100, 10)])
+def test_apply_grouped_tile_grid(ctx, oracle_mod, c1_oracle, nf, na):
+    """Tile grids of 5 x 8 (n = 576 rows, 1024 or 1000 columns): the tile
+    count is a multiple of 8, so the XCD-aware order splits it into eighths,
+    and the band of 8 row tiles is cut to 5.  Both the uniform-alpha tiles
+    (nf = 256) and the per-column weights (nf = 100) match the oracle."""
+    note(f"apply grouped tile grid nf={nf} na={na}")
+    from paper_1911_11906_amd.api import Operator
+    mesh, K, M, th, V = c1_oracle
+    op = Operator.assemble(ctx, mesh)
+    op.set_eigenpairs(th, V)
+    F = inputs.polynomial_forcings(mesh, nf, tag=41)
+    al = np.linspace(0.0, 2.0, na)
+    U = to_np(op.apply(F, al))
+    Uo = oracle_mod.apply_fractional(th, V, M, F, al)
+    assert U.shape == Uo.shape == (576, nf * na)
+    assert np.abs(U - Uo).max() <= 1e-12 * np.abs(Uo).max()
+    assert np.abs(U[:, :nf] - F).max() <= 2e-12 * np.abs(F).max()
