@@ -52,6 +52,8 @@ def lib():
         L.or_eigensolve.restype = ctypes.c_int
         L.or_apply.argtypes = [i64, P, P, P, i64, P, i64, P, P]
         L.or_grad.argtypes = [i64, P, P, P, i64, P, P, P, P, P]
+        L.or_apply_diffusion.argtypes = [i64, P, P, P, i64, P, i64, P, P, P, P]
+        L.or_grad_diffusion.argtypes = [i64, P, P, P, i64, P, P, P, P, P, P, P, P, P]
         L.or_inertia_negative.argtypes = [i64, P]
         L.or_inertia_negative.restype = i64
         L.or_inertia_negative_band.argtypes = [i64, i64, P]
@@ -150,6 +152,36 @@ def grad_apply(theta, V, M, F, alpha, GU):
     lib().or_grad(n, _p(np.ascontiguousarray(theta, dtype=np.float64)), _p(np.asfortranarray(V)),
                   _p(np.asfortranarray(M)), nb, _p(F), _p(alpha), _p(GU), _p(GF), _p(ga))
     return GF, ga
+
+
+def apply_diffusion(theta, V, M, U0, alpha, t, mu):
+    """U[:, j + i*nf] = u(t_i; alpha_i, mu_i, u0_j) of the fractional
+    diffusion equation (alpha, t, mu: one value each per i)."""
+    U0 = np.asfortranarray(np.atleast_2d(U0.T).T, dtype=np.float64)
+    n, nf = U0.shape
+    alpha = np.ascontiguousarray(np.atleast_1d(alpha), dtype=np.float64)
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), alpha.shape))
+    mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), alpha.shape))
+    U = np.zeros((n, nf * alpha.size), order="F")
+    lib().or_apply_diffusion(n, _p(np.ascontiguousarray(theta, dtype=np.float64)), _p(np.asfortranarray(V)),
+                             _p(np.asfortranarray(M)), nf, _p(U0), alpha.size, _p(alpha), _p(t), _p(mu), _p(U))
+    return U
+
+
+def grad_diffusion(theta, V, M, U0, alpha, t, mu, GU):
+    """Adjoint of the paired diffusion map: returns (GU0, galpha, gt, gmu)."""
+    U0 = np.asfortranarray(U0, dtype=np.float64)
+    GU = np.asfortranarray(GU, dtype=np.float64)
+    n, nb = U0.shape
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), alpha.shape))
+    mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), alpha.shape))
+    GU0 = np.zeros((n, nb), order="F")
+    ga, gt, gm = np.zeros(nb), np.zeros(nb), np.zeros(nb)
+    lib().or_grad_diffusion(n, _p(np.ascontiguousarray(theta, dtype=np.float64)), _p(np.asfortranarray(V)),
+                            _p(np.asfortranarray(M)), nb, _p(U0), _p(alpha), _p(t), _p(mu), _p(GU), _p(GU0),
+                            _p(ga), _p(gt), _p(gm))
+    return GU0, ga, gt, gm
 
 
 def inertia_count(K, M, sigma: float) -> int:

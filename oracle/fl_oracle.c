@@ -20,7 +20,10 @@
  *     Jacobi on C (parallel round-robin order), phi = L^-T q;
  *   - the discrete solution v = sum_k theta_k^(-alpha/2) <f, phi_k> phi_k with
  *     <f, phi_k> = phi_k^T M f (the equation for g and v in Section "Method");
- *   - its adjoint with respect to f and alpha.
+ *   - its adjoint with respect to f and alpha;
+ *   - the solution of the fractional diffusion equation
+ *     u(t) = sum_k exp(-mu theta_k^(alpha/2) t) <u0, phi_k> phi_k (equation
+ *     diffusion_solution) and its adjoint with respect to u0, alpha, t, mu.
  *
  * All matrices are column-major: A[i + j*lda].
  * Precision: IEEE double throughout.
@@ -498,6 +501,99 @@ void or_grad(int64_t n, const double *theta, const double *V, const double *M, i
         free(c);
         free(p);
         free(y);
+    }
+}
+
+/* Fractional diffusion (Section "Method", equations model_diffusion and
+ * diffusion_solution): with the discrete eigenpairs in place of the
+ * continuum ones,
+ *   u(t) = sum_k exp(-mu theta_k^(alpha/2) t) (phi_k^T M u0) phi_k.
+ * U(:, j + i*nf) = u(t_i; alpha_i, mu_i, u0_j) for j < nf, i < na. */
+void or_apply_diffusion(int64_t n, const double *theta, const double *V, const double *M, int64_t nf,
+                        const double *U0, int64_t na, const double *alpha, const double *t, const double *mu,
+                        double *U) {
+    double *MU = (double *)malloc(sizeof(double) * (size_t)n * nf);
+    double *Cf = (double *)malloc(sizeof(double) * (size_t)n * nf);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < nf; ++j)
+        for (int64_t r = 0; r < n; ++r) {
+            double s = 0.0;
+            for (int64_t c = 0; c < n; ++c) s += M[IDX(r, c, n)] * U0[IDX(c, j, n)];
+            MU[IDX(r, j, n)] = s;
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < nf; ++j)
+        for (int64_t k = 0; k < n; ++k) {
+            double s = 0.0;
+            for (int64_t r = 0; r < n; ++r) s += V[IDX(r, k, n)] * MU[IDX(r, j, n)];
+            Cf[IDX(k, j, n)] = s;
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t i = 0; i < na; ++i)
+        for (int64_t j = 0; j < nf; ++j) {
+            double *u = U + (size_t)(j + i * nf) * n;
+            for (int64_t r = 0; r < n; ++r) u[r] = 0.0;
+            for (int64_t k = 0; k < n; ++k) {
+                double w = exp(-mu[i] * pow(theta[k], 0.5 * alpha[i]) * t[i]);
+                double a = w * Cf[IDX(k, j, n)];
+                const double *v = V + (size_t)k * n;
+                for (int64_t r = 0; r < n; ++r) u[r] += a * v[r];
+            }
+        }
+    free(MU);
+    free(Cf);
+}
+
+/* Adjoint of the paired diffusion map u_b = sum_k w_kb (phi_k^T M u0_b) phi_k,
+ * w_kb = exp(-mu_b theta_k^(alpha_b/2) t_b), b < nb.  Given GU = dL/du:
+ * with c = V^T M u0, p = V^T GU, e_k = theta_k^(alpha/2):
+ *   dL/du0 = M V (w o p)
+ *   dL/dalpha = sum_k p_k c_k w_k (-mu t e_k ln(theta_k) / 2)
+ *   dL/dt     = sum_k p_k c_k w_k (-mu e_k)
+ *   dL/dmu    = sum_k p_k c_k w_k (-t e_k). */
+void or_grad_diffusion(int64_t n, const double *theta, const double *V, const double *M, int64_t nb,
+                       const double *U0, const double *alpha, const double *t, const double *mu, const double *GU,
+                       double *GU0, double *galpha, double *gt, double *gmu) {
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nb; ++b) {
+        double *mu0 = (double *)malloc(sizeof(double) * n);
+        double *p = (double *)malloc(sizeof(double) * n);
+        double *gy = (double *)malloc(sizeof(double) * n);
+        const double *u0 = U0 + (size_t)b * n, *gu = GU + (size_t)b * n;
+        for (int64_t r = 0; r < n; ++r) {
+            double s = 0.0;
+            for (int64_t q = 0; q < n; ++q) s += M[IDX(r, q, n)] * u0[q];
+            mu0[r] = s;
+        }
+        double ga = 0.0, g_t = 0.0, g_mu = 0.0;
+        for (int64_t r = 0; r < n; ++r) gy[r] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            const double *v = V + (size_t)k * n;
+            double sc = 0.0, sp = 0.0;
+            for (int64_t r = 0; r < n; ++r) {
+                sc += v[r] * mu0[r];
+                sp += v[r] * gu[r];
+            }
+            p[k] = sp;
+            double e = pow(theta[k], 0.5 * alpha[b]);
+            double w = exp(-mu[b] * e * t[b]);
+            double q = sp * sc * w;
+            ga += q * (-mu[b] * t[b] * e * 0.5 * log(theta[k]));
+            g_t += q * (-mu[b] * e);
+            g_mu += q * (-t[b] * e);
+            for (int64_t r = 0; r < n; ++r) gy[r] += w * sp * v[r];
+        }
+        galpha[b] = ga;
+        gt[b] = g_t;
+        gmu[b] = g_mu;
+        for (int64_t r = 0; r < n; ++r) {
+            double s = 0.0;
+            for (int64_t q = 0; q < n; ++q) s += M[IDX(r, q, n)] * gy[q];
+            GU0[(size_t)b * n + r] = s;
+        }
+        free(mu0);
+        free(p);
+        free(gy);
     }
 }
 

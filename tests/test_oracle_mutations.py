@@ -36,6 +36,14 @@ MUTANTS = {
     "grad_log_weight": ("ga += sp * sc * w * (-0.5 * log(theta[k]));", "ga += sp * sc * w * (-log(theta[k]));"),
     "grad_mass_dropped": ("for (int64_t q = 0; q < n; ++q) s += M[IDX(r, q, n)] * y[q];",
                           "for (int64_t q = 0; q < n; ++q) s += (r == q) * y[q];"),
+    "diffusion_half_dropped": ("double w = exp(-mu[i] * pow(theta[k], 0.5 * alpha[i]) * t[i]);",
+                               "double w = exp(-mu[i] * pow(theta[k], alpha[i]) * t[i]);"),
+    "diffusion_sign": ("double w = exp(-mu[b] * e * t[b]);", "double w = exp(mu[b] * e * t[b]);"),
+    "diffusion_grad_t_weight": ("g_t += q * (-mu[b] * e);", "g_t += q * (-t[b] * e);"),
+    "diffusion_grad_alpha_half": ("ga += q * (-mu[b] * t[b] * e * 0.5 * log(theta[k]));",
+                                  "ga += q * (-mu[b] * t[b] * e * log(theta[k]));"),
+    "diffusion_grad_mass_dropped": ("for (int64_t q = 0; q < n; ++q) s += M[IDX(r, q, n)] * gy[q];",
+                                    "for (int64_t q = 0; q < n; ++q) s += (r == q) * gy[q];"),
     "band_ldl_index": ("-= l * AB[(size_t)(r - j) + (size_t)j * ld];", "-= l * AB[(size_t)(c - j) + (size_t)j * ld];"),
 }
 
@@ -113,6 +121,46 @@ def failing_pins():
             D = np.random.default_rng(0).standard_normal(F.shape)
             fd = (loss(F + hh * D, al) - loss(F - hh * D, al)) / (2 * hh)
             check("grad_f_fd", abs(np.sum(GF * D) - fd) < 1e-6 * max(1.0, abs(fd)))
+            # fractional diffusion: the (1,1) mode decays by exp(-mu theta_11^(alpha/2) t)
+            ud = oracle.apply_diffusion(th, V, Mq, f, [1.3], [0.4], [1.0])
+            check("diffusion_eigenfunction",
+                  np.abs(ud[:, 0] - np.exp(-th11 ** 0.65 * 0.4) * f[:, 0]).max() < 1e-12)
+            # alpha = 2: M du/dt = -mu K u (central difference in t)
+            tt, mu_, hd = 0.01, 0.7, 1e-5
+            up = oracle.apply_diffusion(th, V, Mq, F[:, :1], [2.0], [tt + hd], [mu_])[:, 0]
+            um = oracle.apply_diffusion(th, V, Mq, F[:, :1], [2.0], [tt - hd], [mu_])[:, 0]
+            u0 = oracle.apply_diffusion(th, V, Mq, F[:, :1], [2.0], [tt], [mu_])[:, 0]
+            lhs = Mq @ (up - um) / (2 * hd)
+            check("diffusion_alpha2_ode", np.abs(lhs + mu_ * Kq @ u0).max() < 1e-5 * np.abs(lhs).max())
+            ad, td, md = np.array([0.6, 1.5]), np.array([0.3, 0.05]), np.array([1.0, 2.0])
+            Uod = oracle.apply_diffusion(th, V, Mq, F, [0.9], [0.2], [1.0])
+
+            def dloss(ax, tx, mx):
+                tot = 0.0
+                for b in range(2):
+                    r = oracle.apply_diffusion(th, V, Mq, F[:, b], [ax[b]], [tx[b]], [mx[b]])[:, 0] - Uod[:, b]
+                    tot += r @ Mq @ r
+                return tot
+            Ud = np.stack([oracle.apply_diffusion(th, V, Mq, F[:, b], [ad[b]], [td[b]], [md[b]])[:, 0]
+                           for b in range(2)], 1)
+            _, gad, gtd, gmd = oracle.grad_diffusion(th, V, Mq, F, ad, td, md, 2 * Mq @ (Ud - Uod))
+            e0 = np.array([hh, 0.0])
+            fa = (dloss(ad + e0, td, md) - dloss(ad - e0, td, md)) / (2 * hh)
+            ft = (dloss(ad, td + e0, md) - dloss(ad, td - e0, md)) / (2 * hh)
+            fm = (dloss(ad, td, md + e0) - dloss(ad, td, md - e0)) / (2 * hh)
+            check("diffusion_grad_fd", abs(gad[0] - fa) < 1e-6 * max(1.0, abs(fa)) and
+                  abs(gtd[0] - ft) < 1e-6 * max(1.0, abs(ft)) and abs(gmd[0] - fm) < 1e-6 * max(1.0, abs(fm)))
+            GU0 = oracle.grad_diffusion(th, V, Mq, F, ad, td, md, 2 * Mq @ (Ud - Uod))[0]
+            Dd = np.random.default_rng(1).standard_normal(F.shape)
+
+            def floss(Fx):
+                tot = 0.0
+                for b in range(2):
+                    r = oracle.apply_diffusion(th, V, Mq, Fx[:, b], [ad[b]], [td[b]], [md[b]])[:, 0] - Uod[:, b]
+                    tot += r @ Mq @ r
+                return tot
+            fd = (floss(F + hh * Dd) - floss(F - hh * Dd)) / (2 * hh)
+            check("diffusion_grad_u0_fd", abs(np.sum(GU0 * Dd) - fd) < 1e-6 * max(1.0, abs(fd)))
             # Sylvester counts of the banded LDL^T against LAPACK
             ok = True
             for k in (5, 40, 90):
