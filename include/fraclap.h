@@ -27,8 +27,14 @@
  *    before any device work, so a rejected call leaves all buffers untouched.
  *  - Synchrony: fl_assemble, fl_op_from_dense, fl_eigensolve and the fl_d*
  *    stage calls return after their device work has completed;
- *    fl_apply_fractional and fl_grad_apply are asynchronous on the context
- *    stream.
+ *    fl_apply_fractional, fl_apply_diffusion, fl_apply_graph and the adjoints
+ *    (unless they return per-column derivatives to the host) are
+ *    asynchronous on the context stream.
+ *  - Streams: work is queued on the context's current stream
+ *    (fl_ctx_set_stream).  Each operator keeps one application workspace per
+ *    stream, and products split along k use a buffer owned by their stream,
+ *    so applications queued on different streams never share intermediate
+ *    buffers.  Calls on one stream are ordered by that stream.
  *  - Threading: one context per host thread.
  */
 #ifndef FRACLAP_H
@@ -49,7 +55,8 @@ enum {
     FL_EHIP = -3,     /* HIP runtime error */
     FL_ENOTSPD = -4,  /* M (or a matrix to factor) is not positive definite; info->index = pivot */
     FL_ENOCONV = -5,  /* an iterative stage did not converge; info->index = stage */
-    FL_ESTATE = -6    /* call out of order (apply before eigensolve) */
+    FL_ESTATE = -6,   /* call out of order (apply before eigensolve) */
+    FL_EIO = -7       /* a file could not be read or written, or failed its checks */
 };
 enum { FL_ELEM_P1 = 3, FL_ELEM_Q1 = 4 };
 enum { FL_FP64 = 0, FL_MIXED = 1 };
@@ -142,13 +149,15 @@ int fl_eigensolve(fl_op *op, int precision, const fl_eig_opts *opts, fl_eig_info
  * once and reused for every forcing, Section "Method") in one persistent
  * launch: each workgroup takes the next problem, largest n first, from an
  * atomic counter and runs Cholesky, reduction to standard form, Householder
- * tridiagonalisation, implicit QL and the back-transforms on its own, in FP64.
+ * tridiagonalisation, tridiagonal divide and conquer (implicit-QL leaves,
+ * secular-equation merges) and the back-transforms on its own, in FP64.
  * ops: host array of count distinct operators of this context's device, each
  * with 1 <= n <= 1024.  precision must be FL_FP64.  On return each op holds
  * theta ascending and M-orthonormal V, as after fl_eigensolve.  infos (host,
  * count entries, may be NULL) receive per-problem status and index
- * (FL_ENOTSPD: 1-based pivot; FL_ENOCONV: eigenvalue) and, in total_ms, the
- * time of the whole launch.  Returns FL_OK, or the status of the first failed
+ * (FL_ENOTSPD: 1-based pivot; FL_ENOCONV: index 1, the tridiagonal divide
+ * and conquer did not converge) and, in total_ms, the time of the whole
+ * launch.  Returns FL_OK, or the status of the first failed
  * problem (the others are still solved).  Workspace: about 4 n^2 doubles per
  * problem, allocated and released by the call.  Synchronous. */
 int fl_eigensolve_batched(fl_ctx *ctx, int64_t count, fl_op *const *ops, int precision, fl_eig_info *infos);
@@ -157,6 +166,23 @@ int fl_eigenpairs(const fl_op *op, double *theta, double *V, int64_t ldv, int on
 /* Install eigenpairs computed elsewhere (resume, or testing the apply path
  * alone).  theta must be positive. */
 int fl_op_set_eigenpairs(fl_op *op, const double *theta, const double *V, int64_t ldv, int on_device);
+
+/* ---- persistence: the basis is computed once and reused for every later
+ * forcing (Section "Method", the paragraph after the equation for v) --------
+ * fl_op_save writes the pencil (its CSR pattern and the K and M values), and
+ * theta, V and how they were obtained (precision, refinement steps, last
+ * refinement residual) when present, with a SHA-256 of the pencil and one of
+ * the whole file; the file is written under path + ".part" and renamed when
+ * complete.  fl_op_load reads such a file into a new operator of ctx's device
+ * (dense K and M rebuilt from the pattern), after checking the magic, the
+ * version, the sizes, the pattern's indices and the file checksum: FL_EIO on
+ * any failure (nothing is created).  Both synchronous. */
+int fl_op_save(const fl_op *op, const char *path);
+int fl_op_load(fl_ctx *ctx, const char *path, fl_op **out);
+/* n, whether eigenpairs are present, and how they were obtained (precision
+ * FL_FP64, FL_MIXED, or -1 when installed by fl_op_set_eigenpairs); any
+ * output may be NULL. */
+int fl_op_info(const fl_op *op, int64_t *n, int *has_eig, int *precision, int *refine_iters, double *refine_resid);
 
 /* ---- spectral application (the equation for v, Section "Method") ---------
  * F: device, n x nf (ld ldf).  alpha: host, na orders in [0, 2].
@@ -176,6 +202,43 @@ int fl_apply_fractional(fl_op *op, int64_t nf, const double *F, int64_t ldf, int
  * Synchronises the stream when galpha is requested. */
 int fl_grad_apply(fl_op *op, int64_t nb, const double *F, int64_t ldf, const double *alpha, const double *GU,
                   int64_t ldgu, double *GF, int64_t ldgf, double *galpha);
+
+/* Same result as fl_apply_fractional (bit for bit), from a graph: the first
+ * call with a given set of arguments (operator, sizes, the F and U pointers
+ * and leading dimensions, and the values of alpha) captures the sequence
+ * G = M F, C = V^T G, weights, scaled product into a HIP graph with its own
+ * workspace; every later call with the same arguments replays it.  Replays
+ * run on a stream owned by the context, ordered after the work already
+ * queued on the context stream and before the work queued after the call.
+ * F is read and U written at replay time, so a caller may refill F between
+ * calls.  Up to 8 graphs are kept per operator (least recently replayed
+ * evicted); they are released with the operator.  FL_ESTATE if the context
+ * stream is itself being captured.  Asynchronous. */
+int fl_apply_graph(fl_op *op, int64_t nf, const double *F, int64_t ldf, int64_t na, const double *alpha,
+                   int paired, double *U, int64_t ldu);
+
+/* ---- fractional diffusion (Section "Method", equations model_diffusion and
+ * diffusion_solution; the exact solution of Section "Accuracy", equations
+ * diffusion_ics and diffusion_sols) ------------------------------------------
+ * u(t) = sum_k exp(-mu theta_k^(alpha/2) t) <u0, phi_k> phi_k,
+ * <u0, phi_k> = phi_k^T M u0.  U0: device n x nf (ld ldu0).  alpha, t, mu:
+ * host, na values each (alpha in [0, 2], t >= 0, mu >= 0, finite).
+ * paired = 0: U (device n x nf*na, ld ldu) column j + i*nf = u(t_i; alpha_i,
+ * mu_i, u0_j); paired = 1: requires na == nf, column b uses parameter set b.
+ * Same pipeline as fl_apply_fractional with W_ki = exp(-mu_i t_i
+ * theta_k^(alpha_i/2)) (t = 0 gives exactly 1).  Asynchronous. */
+int fl_apply_diffusion(fl_op *op, int64_t nf, const double *U0, int64_t ldu0, int64_t na, const double *alpha,
+                       const double *t, const double *mu, int paired, double *U, int64_t ldu);
+/* Adjoint of the paired diffusion map, b < nb.  GU = dL/du (device n x nb).
+ * With c = V^T M u0, w = exp(-s theta^(alpha/2)), s = mu t, p = V^T GU:
+ *   GU0 = dL/du0 = M V (w o p)                     (device; may be NULL)
+ *   galpha_b = sum_k p_k c_k w_k (-s theta_k^(alpha/2) ln(theta_k) / 2)
+ *   gt_b = mu_b sum_k p_k c_k w_k (-theta_k^(alpha/2)),  gmu_b = t_b (same sum)
+ * (host, nb each; each may be NULL).  Synchronises the stream when any of
+ * them is requested. */
+int fl_grad_diffusion(fl_op *op, int64_t nb, const double *U0, int64_t ldu0, const double *alpha, const double *t,
+                      const double *mu, const double *GU, int64_t ldgu, double *GU0, int64_t ldgu0, double *galpha,
+                      double *gt, double *gmu);
 
 /* ---- stage entry points (device pointers; synchronous) -------------------
  * Exposed so that each stage can be checked on its own. */
@@ -200,14 +263,50 @@ int fl_dsytrd_2stage(fl_ctx *ctx, int64_t n, double *A, int64_t lda, int band, d
  * Z orthonormal (n x n, ld ldz). */
 int fl_dsyevd(fl_ctx *ctx, int64_t n, double *A, int64_t lda, int band, double *w, double *Z, int64_t ldz);
 
+/* ---- launch-shape autotuner ------------------------------------------------
+ * The matrix-core products consult a process-wide table that maps a product
+ * shape to a launch shape.  kind: FL_TUNE_F64 / FL_TUNE_F32 (C = op(A) op(B),
+ * m x n x k) or FL_TUNE_SCALED (the fused spectral-application product,
+ * n x ncols x n; ta = tb = 0).  variant: FL_GV_SQUARE16 / FL_GV_SQUARE32
+ * (128 x 128 tiles, k-step 16 / 32), FL_GV_THIN (256 x 64 tiles, n <= 64);
+ * split: k split factor (plain products); group: row tiles per band of the
+ * XCD-grouped tile order (spectral product).  Shapes match on kind, ta, tb,
+ * m, n and the power-of-two bucket of k.  fl_gemm_tune times every candidate
+ * on ctx's stream on synthetic operands (median of reps after one warm-up),
+ * records the fastest and returns it (ms = its time).  fl_gemm_tuning_set
+ * installs an entry (e.g. one saved by an earlier process; FL_EINVAL if
+ * malformed); fl_gemm_tuning_count / fl_gemm_tuning_get enumerate the table. */
+enum { FL_TUNE_F64 = 0, FL_TUNE_F32 = 1, FL_TUNE_SCALED = 2 };
+enum { FL_GV_AUTO = 0, FL_GV_SQUARE16 = 1, FL_GV_SQUARE32 = 2, FL_GV_THIN = 3 };
+typedef struct fl_gemm_choice {
+    int32_t kind, ta, tb;
+    int64_t m, n, k;
+    int32_t variant, split, group;
+    double ms;
+} fl_gemm_choice;
+int fl_gemm_tune(fl_ctx *ctx, int kind, int ta, int tb, int64_t m, int64_t n, int64_t k, int reps,
+                 fl_gemm_choice *best);
+int fl_gemm_tuning_set(const fl_gemm_choice *choice);
+int64_t fl_gemm_tuning_count(void);
+int fl_gemm_tuning_get(int64_t index, fl_gemm_choice *out);
+void fl_gemm_tuning_clear(void);
+
 /* ---- diagnostics ----------------------------------------------------------
  * Per-kernel timing for the library's main kernels ("q2_apply", "sb2st",
- * "scaled_gemm"): while enabled, HIP events are recorded on the launching
- * stream around each launch.  fl_kernel_time waits for the recorded events,
- * returns the launch count and the summed duration for `name`, and clears
- * them.  Process-wide; FL_EINVAL for NULL arguments. */
+ * "scaled_gemm", "batched_eig"): while enabled, HIP events are recorded on
+ * the launching stream around each launch (not inside a graph capture).
+ * fl_kernel_time waits for the recorded events, returns the launch count and
+ * the summed duration for `name`, and clears them; disabling the timer
+ * releases every event not yet collected.  Process-wide; FL_EINVAL for NULL
+ * arguments. */
 int fl_kernel_timing(int enable);
 int fl_kernel_time(const char *name, int64_t *count, double *total_ms);
+/* Measured ceilings of ctx's device (best of 5 timed runs after one
+ * warm-up): FP64 and FP32 matrix-core rates in TFLOP/s (independent
+ * 16x16x4 MFMA chains in every wave, two waves per SIMD) and the HBM rate of
+ * a plain copy of copy_bytes in GB/s (bytes read plus bytes written).  Any
+ * output may be NULL.  FL_EINVAL for a copy under 1 MiB.  Synchronous. */
+int fl_measure_peaks(fl_ctx *ctx, double *fp64_tflops, double *fp32_tflops, double *copy_gbs, int64_t copy_bytes);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "libfraclap.so")
 
-FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENOTSPD, FL_ENOCONV, FL_ESTATE = 0, -1, -2, -3, -4, -5, -6
+FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENOTSPD, FL_ENOCONV, FL_ESTATE, FL_EIO = 0, -1, -2, -3, -4, -5, -6, -7
 FL_ELEM_P1, FL_ELEM_Q1 = 3, 4
 FL_FP64, FL_MIXED = 0, 1
 FL_MIXED_FP32_BAND = 1
@@ -19,16 +19,20 @@ STAGES = ["potrf", "sygst", "sy2sb", "sb2st", "stedc", "q2", "q1", "trsm", "refi
 FL_NSTAGES = len(STAGES)
 
 STATUS_NAMES = {FL_OK: "FL_OK", FL_EINVAL: "FL_EINVAL", FL_ENOMEM: "FL_ENOMEM", FL_EHIP: "FL_EHIP",
-                FL_ENOTSPD: "FL_ENOTSPD", FL_ENOCONV: "FL_ENOCONV", FL_ESTATE: "FL_ESTATE"}
+                FL_ENOTSPD: "FL_ENOTSPD", FL_ENOCONV: "FL_ENOCONV", FL_ESTATE: "FL_ESTATE", FL_EIO: "FL_EIO"}
+FL_TUNE_F64, FL_TUNE_F32, FL_TUNE_SCALED = 0, 1, 2
+FL_GV_AUTO, FL_GV_SQUARE16, FL_GV_SQUARE32, FL_GV_THIN = 0, 1, 2, 3
 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTS = [
     "fl_ctx_create", "fl_ctx_set_stream", "fl_ctx_destroy", "fl_last_error",
     "fl_assemble", "fl_op_from_dense", "fl_op_n", "fl_op_matrices", "fl_op_destroy",
     "fl_eigensolve", "fl_eigensolve_batched", "fl_eigenpairs", "fl_op_set_eigenpairs",
-    "fl_apply_fractional", "fl_grad_apply",
+    "fl_op_save", "fl_op_load", "fl_op_info",
+    "fl_apply_fractional", "fl_grad_apply", "fl_apply_graph", "fl_apply_diffusion", "fl_grad_diffusion",
+    "fl_gemm_tune", "fl_gemm_tuning_set", "fl_gemm_tuning_count", "fl_gemm_tuning_get", "fl_gemm_tuning_clear",
     "fl_dgemm", "fl_dpotrf", "fl_dsygst", "fl_dstedc", "fl_dsytrd_2stage", "fl_dsyevd",
-    "fl_kernel_timing", "fl_kernel_time",
+    "fl_kernel_timing", "fl_kernel_time", "fl_measure_peaks",
 ]
 
 
@@ -48,6 +52,16 @@ class FlEigInfo(ctypes.Structure):
                 "refine_resid": self.refine_resid, "total_ms": self.total_ms,
                 "flops_nominal": self.flops_nominal,
                 "stage_ms": {s: self.stage_ms[i] for i, s in enumerate(STAGES)}}
+
+
+class FlGemmChoice(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ta", ctypes.c_int32), ("tb", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("variant", ctypes.c_int32), ("split", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class FraclapError(RuntimeError):
@@ -83,8 +97,20 @@ def load(path: str = SO_PATH):
         "fl_eigensolve_batched": ([P, i64, P, i32, P], i32),
         "fl_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_op_set_eigenpairs": ([P, P, P, i64, i32], i32),
+        "fl_op_save": ([P, ctypes.c_char_p], i32),
+        "fl_op_load": ([P, ctypes.c_char_p, pp], i32),
+        "fl_op_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                        ctypes.POINTER(dbl)], i32),
         "fl_apply_fractional": ([P, i64, P, i64, i64, P, i32, P, i64], i32),
         "fl_grad_apply": ([P, i64, P, i64, P, P, i64, P, i64, P], i32),
+        "fl_apply_graph": ([P, i64, P, i64, i64, P, i32, P, i64], i32),
+        "fl_apply_diffusion": ([P, i64, P, i64, i64, P, P, P, i32, P, i64], i32),
+        "fl_grad_diffusion": ([P, i64, P, i64, P, P, P, P, i64, P, i64, P, P, P], i32),
+        "fl_gemm_tune": ([P, i32, i32, i32, i64, i64, i64, i32, ctypes.POINTER(FlGemmChoice)], i32),
+        "fl_gemm_tuning_set": ([ctypes.POINTER(FlGemmChoice)], i32),
+        "fl_gemm_tuning_count": ([], i64),
+        "fl_gemm_tuning_get": ([i64, ctypes.POINTER(FlGemmChoice)], i32),
+        "fl_gemm_tuning_clear": ([], None),
         "fl_dgemm": ([P, i32, i32, i64, i64, i64, dbl, P, i64, P, i64, dbl, P, i64], i32),
         "fl_dpotrf": ([P, i64, P, i64, ctypes.POINTER(i64)], i32),
         "fl_dsygst": ([P, i64, P, i64, P, i64], i32),
@@ -93,6 +119,7 @@ def load(path: str = SO_PATH):
         "fl_dsyevd": ([P, i64, P, i64, i32, P, P, i64], i32),
         "fl_kernel_timing": ([i32], i32),
         "fl_kernel_time": ([ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)], i32),
+        "fl_measure_peaks": ([P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl), i64], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FlEigInfo, FlEigOpts, FraclapError
+from ._lib import FlEigInfo, FlEigOpts, FlGemmChoice, FraclapError
 
 # kept at import: module globals (sys included) may already be None when a
 # destructor runs during interpreter shutdown
@@ -95,6 +95,61 @@ class Context:
         cnt, tot = ctypes.c_int64(0), ctypes.c_double(0.0)
         self.check(self.lib.fl_kernel_time(name.encode(), ctypes.byref(cnt), ctypes.byref(tot)))
         return cnt.value, tot.value
+
+    def measure_peaks(self, copy_bytes: int = 1 << 30) -> dict:
+        """Measured FP64 / FP32 matrix-core TFLOP/s and copy GB/s."""
+        f64, f32, bw = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._sync_stream()
+        self.check(self.lib.fl_measure_peaks(self.ptr, ctypes.byref(f64), ctypes.byref(f32), ctypes.byref(bw),
+                                             copy_bytes))
+        return {"fp64_mfma_tflops": f64.value, "fp32_mfma_tflops": f32.value, "copy_gbs": bw.value,
+                "copy_bytes": copy_bytes}
+
+    # ---------------------------------------------------- launch-shape tuner
+    def gemm_tune(self, kind: str, m: int, n: int, k: int, ta: bool = False, tb: bool = False,
+                  reps: int = 3) -> dict:
+        """Time every launch shape of a product on this device and record the
+        fastest (kind "f64", "f32" or "scaled", the spectral product with
+        k == m); returns the chosen entry."""
+        kd = {"f64": _lib.FL_TUNE_F64, "f32": _lib.FL_TUNE_F32, "scaled": _lib.FL_TUNE_SCALED}[kind]
+        out = FlGemmChoice()
+        self._sync_stream()
+        self.check(self.lib.fl_gemm_tune(self.ptr, kd, int(ta), int(tb), m, n, k, reps, ctypes.byref(out)))
+        return out.as_dict()
+
+    def tuning_table(self) -> list:
+        out = []
+        for i in range(int(self.lib.fl_gemm_tuning_count())):
+            c = FlGemmChoice()
+            self.check(self.lib.fl_gemm_tuning_get(i, ctypes.byref(c)))
+            out.append(c.as_dict())
+        return out
+
+    def set_tuning(self, entries) -> None:
+        for e in entries:
+            c = FlGemmChoice(**{f: e[f] for f, _ in FlGemmChoice._fields_})
+            rc = self.lib.fl_gemm_tuning_set(ctypes.byref(c))
+            if rc != 0:
+                raise FraclapError(rc, f"malformed tuning entry {e}")
+
+    def save_tuning(self, path: str) -> None:
+        """JSON file keyed by the device architecture."""
+        import json
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName
+        with open(path, "w") as f:
+            json.dump({"arch": arch, "entries": self.tuning_table()}, f, indent=1)
+
+    def load_tuning(self, path: str) -> int:
+        """Installs the entries of a JSON tuning file written for this
+        device's architecture; returns how many (0 for another architecture)."""
+        import json
+        with open(path) as f:
+            d = json.load(f)
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName
+        if d.get("arch", "").split(":")[0] != arch.split(":")[0]:
+            return 0
+        self.set_tuning(d["entries"])
+        return len(d["entries"])
 
     def eigensolve_batched(self, ops, precision: str = "fp64"):
         """Solve every Operator in `ops` in one persistent launch (FP64,
@@ -209,6 +264,26 @@ class Operator:
                                            K.shape[0], 0, ctypes.byref(out)))
         return cls(ctx, out)
 
+    @classmethod
+    def load(cls, ctx: Context, path: str) -> "Operator":
+        """An operator (pencil and, when saved, eigenpairs) from fl_op_save."""
+        out = P()
+        ctx._sync_stream()
+        ctx.check(ctx.lib.fl_op_load(ctx.ptr, path.encode(), ctypes.byref(out)))
+        return cls(ctx, out)
+
+    def save(self, path: str) -> None:
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_op_save(self.ptr, path.encode()))
+
+    def describe(self) -> dict:
+        n, he, pr, it, rr = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self.ctx.check(self.ctx.lib.fl_op_info(self.ptr, ctypes.byref(n), ctypes.byref(he), ctypes.byref(pr),
+                                               ctypes.byref(it), ctypes.byref(rr)))
+        prec = {_lib.FL_FP64: "fp64", _lib.FL_MIXED: "mixed"}.get(pr.value)
+        return {"n": n.value, "has_eig": bool(he.value), "precision": prec, "refine_iters": it.value,
+                "refine_resid": rr.value}
+
     def close(self):
         if self.ptr:
             self.ctx.lib.fl_op_destroy(self.ptr)
@@ -271,6 +346,54 @@ class Operator:
                                                         int(paired), _ptr(U), _ld(U)))
         return U
 
+    def apply_graph(self, F, alpha, paired: bool = False, out=None) -> torch.Tensor:
+        """Same as ``apply`` (bitwise), captured once per argument set into a
+        HIP graph and replayed afterwards (F and out must keep their storage)."""
+        F = colmajor(F, self.ctx.device)
+        al = np.ascontiguousarray(np.atleast_1d(np.asarray(alpha, dtype=np.float64)))
+        nf, na = F.shape[1], al.size
+        ncol = nf if paired else nf * na
+        U = out if out is not None else empty_colmajor(self.n, ncol, self.ctx.device)
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_apply_graph(self.ptr, nf, _ptr(F), _ld(F), na, al.ctypes.data_as(P),
+                                                   int(paired), _ptr(U), _ld(U)))
+        return U
+
+    def diffuse(self, U0, alpha, t, mu=1.0, paired: bool = False, out=None) -> torch.Tensor:
+        """u(t) = sum_k exp(-mu theta_k^(alpha/2) t) (phi_k^T M u0) phi_k.
+        alpha, t, mu: one value per parameter set (t and mu broadcast)."""
+        U0 = colmajor(U0, self.ctx.device)
+        al = np.ascontiguousarray(np.atleast_1d(np.asarray(alpha, dtype=np.float64)))
+        tt = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), al.shape))
+        mu_ = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), al.shape))
+        nf, na = U0.shape[1], al.size
+        U = out if out is not None else empty_colmajor(self.n, nf if paired else nf * na, self.ctx.device)
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_apply_diffusion(self.ptr, nf, _ptr(U0), _ld(U0), na, al.ctypes.data_as(P),
+                                                       tt.ctypes.data_as(P), mu_.ctypes.data_as(P), int(paired),
+                                                       _ptr(U), _ld(U)))
+        return U
+
+    def grad_diffusion(self, U0, alpha, t, mu, GU, want_u0: bool = True, want_params: bool = True):
+        """Adjoint of the paired diffusion map: (GU0, galpha, gt, gmu)."""
+        U0 = colmajor(U0, self.ctx.device)
+        GU = colmajor(GU, self.ctx.device)
+        nb = GU.shape[1]
+        al = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, dtype=np.float64), (nb,)))
+        tt = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (nb,)))
+        mu_ = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (nb,)))
+        GU0 = empty_colmajor(self.n, nb, self.ctx.device) if want_u0 else None
+        ga, gt, gm = (np.zeros(nb), np.zeros(nb), np.zeros(nb)) if want_params else (None, None, None)
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_grad_diffusion(
+            self.ptr, nb, _ptr(U0), _ld(U0), al.ctypes.data_as(P), tt.ctypes.data_as(P), mu_.ctypes.data_as(P),
+            _ptr(GU), _ld(GU), _ptr(GU0) if want_u0 else None, _ld(GU0) if want_u0 else self.n,
+            ga.ctypes.data_as(P) if want_params else None, gt.ctypes.data_as(P) if want_params else None,
+            gm.ctypes.data_as(P) if want_params else None))
+        if not want_params:
+            return GU0, None, None, None
+        return GU0, torch.from_numpy(ga), torch.from_numpy(gt), torch.from_numpy(gm)
+
     def grad(self, F, alpha, GU, want_f: bool = True, want_alpha: bool = True):
         F = colmajor(F, self.ctx.device)
         GU = colmajor(GU, self.ctx.device)
@@ -306,3 +429,30 @@ class FracApply(torch.autograd.Function):
                          want_alpha=ctx.needs_input_grad[2])
         ga_t = ga.to(alpha.device, alpha.dtype) if ga is not None else None
         return None, GF, ga_t
+
+
+class FracDiffusion(torch.autograd.Function):
+    """u_b(t_b) of the fractional diffusion equation for paired columns
+    (u0_b, alpha_b, t_b, mu_b); backward through the hand-written adjoint
+    (fl_grad_diffusion)."""
+
+    @staticmethod
+    def forward(ctx, op: Operator, U0: torch.Tensor, alpha: torch.Tensor, t: torch.Tensor, mu: torch.Tensor):
+        ctx.op = op
+        U0c = colmajor(U0.detach(), op.ctx.device)
+        ctx.save_for_backward(U0c, alpha.detach(), t.detach(), mu.detach())
+        return op.diffuse(U0c, alpha.detach().cpu().numpy(), t.detach().cpu().numpy(), mu.detach().cpu().numpy(),
+                          paired=True)
+
+    @staticmethod
+    def backward(ctx, gU):
+        U0, alpha, t, mu = ctx.saved_tensors
+        op = ctx.op
+        want_params = any(ctx.needs_input_grad[2:5])
+        GU0, ga, gt, gm = op.grad_diffusion(U0, alpha.cpu().numpy(), t.cpu().numpy(), mu.cpu().numpy(), gU,
+                                            want_u0=ctx.needs_input_grad[1], want_params=want_params)
+
+        def back(g, like, need):
+            return g.to(like.device, like.dtype) if (need and g is not None) else None
+        return (None, GU0, back(ga, alpha, ctx.needs_input_grad[2]), back(gt, t, ctx.needs_input_grad[3]),
+                back(gm, mu, ctx.needs_input_grad[4]))

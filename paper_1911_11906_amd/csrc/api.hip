@@ -80,18 +80,6 @@ int upload_csr_and_gather(fl_op* op, const std::vector<int32_t>& rowptr, const s
     return FL_OK;
 }
 
-int ensure_ws(fl_op* op, size_t bytes) {
-    if (op->ws_bytes >= bytes) return FL_OK;
-    FL_HIP(op->ctx, hipStreamSynchronize(op->ctx->stream));
-    dev_free(op->ws);
-    op->ws = nullptr;
-    op->ws_bytes = 0;
-    int rc = dev_alloc(op->ctx, &op->ws, bytes / sizeof(double) + 1);
-    if (rc) return rc;
-    op->ws_bytes = bytes;
-    return FL_OK;
-}
-
 }  // namespace
 
 // K := L^-1 K L^-T given L and the inverses of its 128 x 128 diagonal blocks.
@@ -128,7 +116,17 @@ int fl_ctx_set_stream(fl_ctx* ctx, void* hip_stream) {
     return FL_OK;
 }
 
-void fl_ctx_destroy(fl_ctx* ctx) { delete ctx; }
+void fl_ctx_destroy(fl_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->graph_stream) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->graph_stream);
+        (void)hipStreamDestroy(ctx->graph_stream);
+    }
+    if (ctx->graph_in) (void)hipEventDestroy(ctx->graph_in);
+    if (ctx->graph_out) (void)hipEventDestroy(ctx->graph_out);
+    delete ctx;
+}
 
 const char* fl_last_error(const fl_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -147,7 +145,7 @@ void fl_op_destroy(fl_op* op) {
     dev_free(op->theta);
     dev_free(op->logtheta);
     dev_free(op->V);
-    dev_free(op->ws);
+    fl_op_release_spectral(op);
     delete op;
 }
 
@@ -378,6 +376,9 @@ int fl_op_set_eigenpairs(fl_op* op, const double* theta, const double* V, int64_
     FL_HIP(ctx, fl_log_kernel(ctx->stream, n, op->theta, op->logtheta));
     FL_HIP(ctx, hipStreamSynchronize(ctx->stream));
     op->has_eig = 1;
+    op->eig_precision = -1;
+    op->refine_iters = 0;
+    op->refine_resid = 0.0;
     return FL_OK;
 }
 
@@ -392,79 +393,6 @@ int fl_eigenpairs(const fl_op* op, double* theta, double* V, int64_t ldv, int on
     if (theta) FL_HIP(ctx, hipMemcpyAsync(theta, op->theta, op->n * 8, kind, ctx->stream));
     if (V) FL_HIP(ctx, hipMemcpy2DAsync(V, ldv * 8, op->V, op->ld * 8, op->n * 8, op->n, kind, ctx->stream));
     FL_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return FL_OK;
-}
-
-int fl_apply_fractional(fl_op* op, int64_t nf, const double* F, int64_t ldf, int64_t na, const double* alpha,
-                        int paired, double* U, int64_t ldu) {
-    if (!op) return FL_EINVAL;
-    fl_ctx* ctx = op->ctx;
-    const int64_t n = op->n;
-    if (!op->has_eig) return fl_fail(ctx, FL_ESTATE, "fl_apply_fractional: eigensolve first");
-    if (nf <= 0 || na <= 0 || !F || !U || !alpha || ldf < n || ldu < n)
-        return fl_fail(ctx, FL_EINVAL, "fl_apply_fractional: bad sizes or null pointer");
-    if (paired && nf != na) return fl_fail(ctx, FL_EINVAL, "fl_apply_fractional: paired requires nf == na");
-    for (int64_t i = 0; i < na; ++i)
-        if (!std::isfinite(alpha[i]) || alpha[i] < 0.0 || alpha[i] > 2.0)
-            return fl_fail(ctx, FL_EINVAL, "fl_apply_fractional: alpha must lie in [0, 2]");
-    int rc = set_device(ctx);
-    if (rc) return rc;
-    // workspace: G (n x nf) | C (n x nf) | W (n x na) | alpha (na)
-    size_t need = ((size_t)2 * n * nf + (size_t)n * na + na) * 8;
-    if ((rc = ensure_ws(op, need))) return rc;
-    double* G = op->ws;
-    double* C = G + (size_t)n * nf;
-    double* W = C + (size_t)n * nf;
-    double* dal = W + (size_t)n * na;
-    hipStream_t s = ctx->stream;
-    FL_HIP(ctx, hipMemcpyAsync(dal, alpha, na * 8, hipMemcpyHostToDevice, s));
-    FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, nf, F, ldf, G, n));
-    FL_HIP(ctx, fl_dgemm(s, 1, 0, n, nf, n, 1.0, op->V, op->ld, G, n, 0.0, C, n));
-    FL_HIP(ctx, fl_weights(s, n, op->logtheta, na, dal, W, n));
-    FL_HIP(ctx, fl_scaled_gemm(s, n, op->V, op->ld, W, n, C, n, nf, na, paired, U, ldu));
-    return FL_OK;
-}
-
-int fl_grad_apply(fl_op* op, int64_t nb, const double* F, int64_t ldf, const double* alpha, const double* GU,
-                  int64_t ldgu, double* GF, int64_t ldgf, double* galpha) {
-    if (!op) return FL_EINVAL;
-    fl_ctx* ctx = op->ctx;
-    const int64_t n = op->n;
-    if (!op->has_eig) return fl_fail(ctx, FL_ESTATE, "fl_grad_apply: eigensolve first");
-    if (nb <= 0 || !GU || !alpha || ldgu < n || (GF && ldgf < n) || (galpha && (!F || ldf < n)))
-        return fl_fail(ctx, FL_EINVAL, "fl_grad_apply: bad sizes or null pointer");
-    for (int64_t i = 0; i < nb; ++i)
-        if (!std::isfinite(alpha[i]) || alpha[i] < 0.0 || alpha[i] > 2.0)
-            return fl_fail(ctx, FL_EINVAL, "fl_grad_apply: alpha must lie in [0, 2]");
-    int rc = set_device(ctx);
-    if (rc) return rc;
-    // workspace: P | C | G | W | Y (n x nb each) | alpha (nb) | galpha (nb)
-    size_t need = ((size_t)5 * n * nb + 2 * nb) * 8;
-    if ((rc = ensure_ws(op, need))) return rc;
-    double* P = op->ws;
-    double* C = P + (size_t)n * nb;
-    double* G = C + (size_t)n * nb;
-    double* W = G + (size_t)n * nb;
-    double* Y = W + (size_t)n * nb;
-    double* dal = Y + (size_t)n * nb;
-    double* dga = dal + nb;
-    hipStream_t s = ctx->stream;
-    FL_HIP(ctx, hipMemcpyAsync(dal, alpha, nb * 8, hipMemcpyHostToDevice, s));
-    FL_HIP(ctx, fl_dgemm(s, 1, 0, n, nb, n, 1.0, op->V, op->ld, GU, ldgu, 0.0, P, n));
-    FL_HIP(ctx, fl_weights(s, n, op->logtheta, nb, dal, W, n));
-    if (galpha) {
-        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, nb, F, ldf, G, n));
-        FL_HIP(ctx, fl_dgemm(s, 1, 0, n, nb, n, 1.0, op->V, op->ld, G, n, 0.0, C, n));
-        FL_HIP(ctx, fl_galpha(s, n, nb, P, n, C, n, W, n, op->logtheta, dga));
-    }
-    if (GF) {
-        FL_HIP(ctx, fl_scaled_gemm(s, n, op->V, op->ld, W, n, P, n, nb, nb, 1, Y, n));
-        FL_HIP(ctx, fl_spmm_csr(s, n, op->rowptr, op->colidx, op->mval, nb, Y, n, GF, ldgf));
-    }
-    if (galpha) {
-        FL_HIP(ctx, hipMemcpyAsync(galpha, dga, nb * 8, hipMemcpyDeviceToHost, s));
-        FL_HIP(ctx, hipStreamSynchronize(s));
-    }
     return FL_OK;
 }
 

@@ -13,9 +13,10 @@
 //   Z = Q Z_T                      block reflectors (I - V T V^T), 32 at a time
 //   V = L^-T Z                     blocked triangular solve
 // then theta ascending and V = [phi_1 .. phi_n], M-orthonormal.  The dense
-// contractions use a register-tiled FP64 FMA tile (on gfx950 the FP64 vector
-// rate equals the FP64 matrix-core rate).  No workgroup waits on another:
-// the launch ends when the counter passes the last problem.
+// contractions run on the FP64 matrix cores (v_mfma_f64_16x16x4f64: eight
+// waves of 32 x 32 over a 64 x 128 workgroup tile, k-slabs of 32 staged in
+// LDS).  No workgroup waits on another: the launch ends when the counter
+// passes the last problem.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -1591,7 +1592,12 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         int code = FL_OK;
         if (st[i] > 0) code = FL_ENOTSPD;
         if (st[i] < 0) code = FL_ENOCONV;
-        if (code == FL_OK) ops[i]->has_eig = 1;
+        if (code == FL_OK) {
+            ops[i]->has_eig = 1;
+            ops[i]->eig_precision = FL_FP64;
+            ops[i]->refine_iters = 0;
+            ops[i]->refine_resid = 0.0;
+        }
         if (infos) {
             infos[i] = fl_eig_info{};
             infos[i].status = code;

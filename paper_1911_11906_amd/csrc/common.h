@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include "../../include/fraclap.h"
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -22,6 +23,33 @@ struct GemmProblem {
     double alpha, beta;
 };
 
+// Caller-provided workspace for the partial sums of a split-k product
+// (bytes == 0: never split).  Without one, a product uses a buffer owned by
+// its stream.
+struct SplitWs {
+    void* p;
+    size_t bytes;
+};
+
+// The split-k buffer owned by stream s on the current device (allocated on
+// first use, never while s is being captured; {null, 0} if unavailable).
+SplitWs fl_stream_splitk_ws(hipStream_t s);
+
+// Tuned launch shapes (tune.hip): product kind (FL_TUNE_*), variant
+// (FL_GV_*) and split factor; the enums are part of the public header.
+struct GemmChoice {
+    int variant = FL_GV_AUTO;  // FL_GV_AUTO: built-in heuristics
+    int split = 1;             // split-k factor (plain products)
+    int group = 8;             // row tiles per band of the XCD-grouped order (spectral product)
+};
+// Tuned choice for a product shape (k compared by its power-of-two bucket);
+// FL_GV_AUTO when none was recorded.
+GemmChoice tuned_choice(int kind, int ta, int tb, int64_t m, int64_t n, int64_t k);
+// One product with an explicit choice, alpha = 1, beta = 0 (for the tuner).
+hipError_t fl_gemm_choice_launch(hipStream_t s, int kind, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                                 const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc,
+                                 const GemmChoice& c);
+
 // Launchers (stream-ordered, asynchronous).  ta / tb: 0 = N, 1 = T.
 // lower != 0 skips output tiles strictly above the diagonal (SYRK-style
 // updates of a lower-stored symmetric matrix; diagonal tiles are written in
@@ -29,6 +57,10 @@ struct GemmProblem {
 hipError_t fl_dgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                     int64_t ldc, int lower = 0);
+// Same, with the split-k workspace given by the caller (nothing allocated).
+hipError_t fl_dgemm_ws(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, const SplitWs* ws);
 // GEMM with one triangular operand whose zero part is skipped tile by tile:
 // kt = FL_KT_A_LOWER (op(A)[i][k] = 0 for k > i), FL_KT_A_UPPER (for k < i),
 // FL_KT_B_LOWER (op(B)[k][j] = 0 for k < j), FL_KT_NONE (plain).  The zero

@@ -268,7 +268,9 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     if (!op) return FL_EINVAL;
     fl_ctx* ctx = op->ctx;
     if (precision != FL_FP64 && precision != FL_MIXED) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve: bad precision");
-    if (info) *info = fl_eig_info{};
+    fl_eig_info local_info{};
+    if (!info) info = &local_info;  // the refinement statistics are kept with the operator
+    *info = fl_eig_info{};
     FL_HIP(ctx, hipSetDevice(ctx->device));
     const int64_t n = op->n, ld = op->ld;
     const int band = opts ? opts->band : 0;
@@ -399,6 +401,9 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
         return fl_fail(ctx, FL_EINVAL, "fl_eigensolve: smallest eigenvalue is not positive");
     }
     op->has_eig = 1;
+    op->eig_precision = precision;
+    op->refine_iters = info->refine_iters;
+    op->refine_resid = info->refine_resid;
     return FL_OK;
 }
 

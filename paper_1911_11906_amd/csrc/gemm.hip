@@ -15,6 +15,8 @@
 // Problems with few output tiles and a long k are split along k into
 // partial products that a second kernel sums in a fixed order.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 #include "gemm_tile.h"
 
 namespace {
@@ -152,36 +154,116 @@ __global__ __launch_bounds__(NT) FL_TWO_WAVES_PER_SIMD void dgemm_batched_kernel
                                            Bs);
 }
 
-// Split-K workspace: one buffer per device, allocated once and never resized
-// (a resize could free memory that queued kernels still use); the split
-// factor is capped to what fits.
-constexpr int64_t SPLITK_WS_BYTES = 256ll << 20;
-void* splitk_ws(int dev) {
-    static void* ws[64] = {nullptr};
-    static bool failed[64] = {false};
-    if (dev < 0 || dev >= 64) return nullptr;
-    if (!ws[dev] && !failed[dev]) {
-        if (hipMalloc(&ws[dev], SPLITK_WS_BYTES) != hipSuccess) {
-            ws[dev] = nullptr;
-            failed[dev] = true;
-            (void)hipGetLastError();
-        }
+// Split-K workspace: one buffer per (device, stream), allocated on the
+// first split product queued on that stream and kept until the process ends
+// (a resize could free memory that queued kernels still use).  Products on
+// different streams therefore never share partial sums; products on one
+// stream are ordered by the stream.  The split factor is capped to what
+// fits.
+constexpr size_t SPLITK_WS_BYTES = size_t(256) << 20;
+struct StreamWs {
+    int dev;
+    hipStream_t s;
+    void* p;
+};
+std::mutex g_ws_mu;
+std::vector<StreamWs> g_ws;
+SplitWs stream_splitk_ws(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SplitWs{nullptr, 0};
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (const StreamWs& w : g_ws)
+        if (w.dev == dev && w.s == s) return SplitWs{w.p, w.p ? SPLITK_WS_BYTES : 0};
+    // never allocate while the stream is being captured into a graph
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return SplitWs{nullptr, 0};
+    void* p = nullptr;
+    if (hipMalloc(&p, SPLITK_WS_BYTES) != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
     }
-    return ws[dev];
+    g_ws.push_back(StreamWs{dev, s, p});
+    return SplitWs{p, p ? SPLITK_WS_BYTES : 0};
+}
+
+// Workspace of a split product: the caller's (ws != null; bytes == 0 means
+// no split) or the stream's own buffer.
+template <class T>
+T* split_buffer(hipStream_t s, const SplitWs* ws, int64_t& S, int64_t m, int64_t n) {
+    if (S <= 1) return nullptr;
+    SplitWs w = ws ? *ws : stream_splitk_ws(s);
+    while (S > 1 && (size_t)(S * m * n) * sizeof(T) > w.bytes) --S;
+    if (S <= 1 || !w.p) {
+        S = 1;
+        return nullptr;
+    }
+    return static_cast<T*>(w.p);
 }
 
 template <class T, bool TA, bool TB>
-hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
+hipError_t launch_thin(hipStream_t s, const Prob<T>& g, int64_t tmt, int64_t S, T* P) {
+    if (S > 1 && P) {
+        int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), TKB) * TKB;
+        S = FL_DIV_UP(g.k, kc);
+        gemm_thin_kernel<T, TA, TB><<<dim3((unsigned)tmt, 1, (unsigned)S), NT, 0, s>>>(g, kc, P);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        dim3 rg((unsigned)FL_DIV_UP(g.m, 256), (unsigned)std::min<int64_t>(g.n, 65535));
+        splitk_reduce_kernel<T><<<rg, 256, 0, s>>>(g.m, g.n, (int)S, P, g.beta, g.C, g.ldc);
+        return hipGetLastError();
+    }
+    gemm_thin_kernel<T, TA, TB><<<dim3((unsigned)tmt, 1, 1), NT, 0, s>>>(g, g.k, nullptr);
+    return hipGetLastError();
+}
+
+// 128 x 128 tiles with k-step kb (16 or 32), optionally split along k.
+template <class T, bool TA, bool TB>
+hipError_t launch_square(hipStream_t s, const Prob<T>& g, int kb, int64_t S, T* P) {
+    const int64_t tm = FL_DIV_UP(g.m, BM), tn = FL_DIV_UP(g.n, BN);
+    if (S > 1 && P) {
+        int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), GKB) * GKB;
+        S = FL_DIV_UP(g.k, kc);
+        gemm_splitk_kernel<T, TA, TB><<<dim3((unsigned)tm, (unsigned)tn, (unsigned)S), NT, 0, s>>>(g, kc, P);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        dim3 rg((unsigned)FL_DIV_UP(g.m, 256), (unsigned)std::min<int64_t>(g.n, 65535));
+        splitk_reduce_kernel<T><<<rg, 256, 0, s>>>(g.m, g.n, (int)S, P, g.beta, g.C, g.ldc);
+        return hipGetLastError();
+    }
+    dim3 grid((unsigned)tm, (unsigned)tn);
+    if (kb == 2 * GKB)
+        gemm_kernel<T, TA, TB, false, FL_KT_NONE, 2 * GKB><<<grid, NT, 0, s>>>(g);
+    else
+        gemm_kernel<T, TA, TB, false><<<grid, NT, 0, s>>>(g);
+    return hipGetLastError();
+}
+
+template <class T, bool TA, bool TB>
+hipError_t launch(hipStream_t s, const Prob<T>& g, int lower, const SplitWs* ws, const GemmChoice* forced) {
+    const GemmChoice tc = forced ? *forced
+                                 : lower ? GemmChoice{}
+                                         : tuned_choice(sizeof(T) == 8 ? FL_TUNE_F64 : FL_TUNE_F32, TA, TB, g.m, g.n,
+                                                        g.k);
+    if (tc.variant == FL_GV_THIN && g.n <= TBN) {
+        const int64_t tmt = FL_DIV_UP(g.m, TBM);
+        int64_t S = std::max<int64_t>(1, std::min<int64_t>(tc.split, g.k / TKB));
+        T* P = split_buffer<T>(s, ws, S, g.m, g.n);
+        return launch_thin<T, TA, TB>(s, g, tmt, S, P);
+    }
+    if (tc.variant == FL_GV_SQUARE16 || tc.variant == FL_GV_SQUARE32) {
+        const int kb = tc.variant == FL_GV_SQUARE32 ? 2 * GKB : GKB;
+        int64_t S = std::max<int64_t>(1, std::min<int64_t>(tc.split, g.k / kb));
+        T* P = split_buffer<T>(s, ws, S, g.m, g.n);
+        return launch_square<T, TA, TB>(s, g, kb, S, P);
+    }
     if (!lower && g.n <= TBN && g.m >= 2 * TBM) {
         const int64_t tmt = FL_DIV_UP(g.m, TBM);
         int64_t S = 1;
         T* P = nullptr;
         if (tmt < 384 && g.k >= 256) {
             S = std::min<int64_t>({FL_DIV_UP(768, tmt), g.k / 128, 32});
-            while (S > 1 && S * g.m * g.n * (int64_t)sizeof(T) > SPLITK_WS_BYTES) --S;
-            int dev = 0;
-            P = (S > 1 && hipGetDevice(&dev) == hipSuccess) ? (T*)splitk_ws(dev) : nullptr;
-            if (!P) S = 1;
+            P = split_buffer<T>(s, ws, S, g.m, g.n);
         }
         if (S > 1) {
             int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), TKB) * TKB;
@@ -201,9 +283,7 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower) {
     // few output tiles and a long k: split k so that the chip fills up
     if (!lower && tiles < 384 && g.k >= 2048) {
         int64_t S = std::min<int64_t>({FL_DIV_UP(768, tiles), g.k / 512, 32});
-        while (S > 1 && S * g.m * g.n * (int64_t)sizeof(T) > SPLITK_WS_BYTES) --S;
-        int dev = 0;
-        T* P = (S > 1 && hipGetDevice(&dev) == hipSuccess) ? (T*)splitk_ws(dev) : nullptr;
+        T* P = split_buffer<T>(s, ws, S, g.m, g.n);
         if (S > 1 && P) {
             int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), GKB) * GKB;
             S = FL_DIV_UP(g.k, kc);
@@ -254,11 +334,12 @@ hipError_t tri_any(hipStream_t s, int ta, int tb, const Prob<double>& g, int low
 }
 
 template <class T>
-hipError_t gemm_any(hipStream_t s, int ta, int tb, const Prob<T>& g, int lower) {
-    if (!ta && !tb) return launch<T, false, false>(s, g, lower);
-    if (!ta && tb) return launch<T, false, true>(s, g, lower);
-    if (ta && !tb) return launch<T, true, false>(s, g, lower);
-    return launch<T, true, true>(s, g, lower);
+hipError_t gemm_any(hipStream_t s, int ta, int tb, const Prob<T>& g, int lower, const SplitWs* ws = nullptr,
+                    const GemmChoice* forced = nullptr) {
+    if (!ta && !tb) return launch<T, false, false>(s, g, lower, ws, forced);
+    if (!ta && tb) return launch<T, false, true>(s, g, lower, ws, forced);
+    if (ta && !tb) return launch<T, true, false>(s, g, lower, ws, forced);
+    return launch<T, true, true>(s, g, lower, ws, forced);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -337,6 +418,30 @@ hipError_t fl_dgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t
     if (k <= 0 && beta == 1.0) return hipSuccess;
     Prob<double> g{m, n, k, A, lda, B, ldb, C, ldc, alpha, beta};
     return gemm_any<double>(s, ta, tb, g, lower);
+}
+
+SplitWs fl_stream_splitk_ws(hipStream_t s) { return stream_splitk_ws(s); }
+
+hipError_t fl_dgemm_ws(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, const SplitWs* ws) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (k <= 0 && beta == 1.0) return hipSuccess;
+    Prob<double> g{m, n, k, A, lda, B, ldb, C, ldc, alpha, beta};
+    SplitWs none{nullptr, 0};
+    return gemm_any<double>(s, ta, tb, g, 0, ws ? ws : &none);
+}
+
+hipError_t fl_gemm_choice_launch(hipStream_t s, int dtype, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                                 const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc,
+                                 const GemmChoice& c) {
+    if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
+    if (dtype == FL_TUNE_F32) {
+        Prob<float> g{m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc, 1.0f, 0.0f};
+        return gemm_any<float>(s, ta, tb, g, 0, nullptr, &c);
+    }
+    Prob<double> g{m, n, k, (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc, 1.0, 0.0};
+    return gemm_any<double>(s, ta, tb, g, 0, nullptr, &c);
 }
 
 hipError_t fl_dgemm_tri(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,

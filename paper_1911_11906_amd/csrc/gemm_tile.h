@@ -44,9 +44,6 @@ constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int SA = BM + 2;  // LDS row strides (doubles)
 constexpr int SB = BN + 2;
 constexpr int NT = 256;
-// LDS doubles needed by tile_gemm<.., KB, NBUF, T, WM>: WM waves along M
-// (workgroup tile 64 WM x 64 (4 / WM); WM = 2: 128 x 128, WM = 4: 256 x 64
-// for products with at most 64 columns)
 // Tile coordinates of a full (tm x tn) grid in an XCD-aware grouped order.
 // Consecutive workgroup ids go to the eight XCDs in turn, so id is first
 // split into (id mod 8, id / 8) and each XCD gets one contiguous eighth of
@@ -54,8 +51,7 @@ constexpr int NT = 256;
 // walks bands of GM row tiles column by column, so the workgroups resident
 // on one XCD at a time cover a compact GM x (resident / GM) patch and share
 // its row and column blocks in that XCD's L2.  A bijection of the grid.
-__device__ inline void xcd_grouped_tile(int64_t& bi, int64_t& bj) {
-    constexpr int64_t GM = 8;
+__device__ inline void xcd_grouped_tile(int64_t& bi, int64_t& bj, int64_t GM = 8) {
     const int64_t tm = gridDim.x, tn = gridDim.y, T = tm * tn;
     const int64_t id = blockIdx.x + tm * (int64_t)blockIdx.y;
     const int64_t L = (T % 8 == 0) ? (id % 8) * (T / 8) + id / 8 : id;
@@ -66,6 +62,9 @@ __device__ inline void xcd_grouped_tile(int64_t& bi, int64_t& bj) {
     bj = q / rows;
 }
 
+// LDS doubles needed by tile_gemm<.., KB, NBUF, T, WM>: WM waves along M
+// (workgroup tile 64 WM x 64 (4 / WM); WM = 2: 128 x 128, WM = 4: 256 x 64
+// for products with at most 64 columns)
 template <int KB, int NBUF, int WM = 2>
 struct TileLds {
     static constexpr int A = NBUF * KB * (64 * WM + 2);

@@ -14,7 +14,19 @@ struct fl_ctx {
     // freed (see band_buffer in eig.hip)
     void* band_uc = nullptr;
     size_t band_uc_bytes = 0;
+    // stream owned by the context on which captured application graphs are
+    // replayed, ordered after and before the caller's stream by two events
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t graph_in = nullptr, graph_out = nullptr;
 };
+
+// Application workspace of one operator on one stream (grown on demand).
+struct OpWs {
+    hipStream_t s;
+    double* p;
+    size_t bytes;
+};
+struct ApplyGraph;  // spectral.hip
 
 struct fl_op {
     fl_ctx* ctx = nullptr;
@@ -34,10 +46,19 @@ struct fl_op {
     double* theta = nullptr;     // n
     double* logtheta = nullptr;  // n
     double* V = nullptr;         // n x n, ld
-    // apply workspace (grown on demand)
-    double* ws = nullptr;
-    size_t ws_bytes = 0;
+    // how the eigenpairs were obtained (kept by fl_op_save)
+    int eig_precision = -1;      // FL_FP64, FL_MIXED, or -1 (installed by the caller)
+    int32_t refine_iters = 0;
+    double refine_resid = 0.0;
+    // application workspaces, one per stream, so calls queued on different
+    // streams never share intermediate buffers
+    std::vector<OpWs> ws;
+    // captured application graphs (fl_apply_graph)
+    std::vector<ApplyGraph*> graphs;
+    uint64_t graph_clock = 0;
 };
+// Releases the graphs and workspaces of an operator (device idle).
+void fl_op_release_spectral(fl_op* op);
 
 // Optional per-kernel timing (ktimer.hip): events around one launch when
 // timing is enabled; a no-op otherwise.
@@ -95,14 +116,47 @@ hipError_t fl_csr_gather(hipStream_t s, int64_t n, const int32_t* rowptr, const 
 hipError_t fl_spmm_csr(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* colidx, const double* val,
                        int64_t ncols, const double* X, int64_t ldx, double* Y, int64_t ldy);
 hipError_t fl_log_kernel(hipStream_t s, int64_t n, const double* x, double* y);
-hipError_t fl_weights(hipStream_t s, int64_t n, const double* logtheta, int64_t na, const double* alpha_dev,
-                      double* W, int64_t ldw);
-// U[:, j + i*nf] = V (W[:, i] o C[:, j])   (paired: column b uses W[:, b], C[:, b])
+// Spectral weight families and their parameters for one chunk of at most
+// FL_WCHUNK columns, passed to the kernels by value.
+enum { FL_SPEC_FRACTIONAL = 0, FL_SPEC_DIFFUSION = 1 };
+constexpr int FL_WCHUNK = 32;
+struct WeightArgs {
+    int kind;
+    int count;
+    double alpha[FL_WCHUNK];
+    double s[FL_WCHUNK];  // diffusion: mu * t
+};
+hipError_t fl_weights(hipStream_t s, int64_t n, const double* logtheta, const WeightArgs& a, double* W, int64_t ldw);
+// U[:, j + i*nf] = V (W[:, i] o C[:, j])   (paired: column b uses W[:, b], C[:, b]).
+// forced: launch shape (null: the tuned one, else the built-in default);
+// timed: recorded by the kernel timer under "scaled_gemm".
 hipError_t fl_scaled_gemm(hipStream_t s, int64_t n, const double* V, int64_t ldv, const double* W, int64_t ldw,
                           const double* C, int64_t ldc, int64_t nf, int64_t na, int paired, double* U,
-                          int64_t ldu);
-hipError_t fl_galpha(hipStream_t s, int64_t n, int64_t nb, const double* P, int64_t ldp, const double* C,
-                     int64_t ldc, const double* W, int64_t ldw, const double* logtheta, double* galpha_dev);
+                          int64_t ldu, const GemmChoice* forced = nullptr, bool timed = true);
+// Per-column derivatives of the paired map with respect to the weight
+// parameters (chunk a): ga (alpha), gs (mu t; diffusion only, may be null).
+hipError_t fl_spec_grad(hipStream_t s, int64_t n, const double* P, int64_t ldp, const double* C, int64_t ldc,
+                        const double* W, int64_t ldw, const double* logtheta, const WeightArgs& a, double* ga,
+                        double* gs);
+// One spectral application queued on stream s with workspace ws (device,
+// (2 nf + na) n doubles: G | C | W) and split-k workspace split (null: the
+// stream's own).  Queues kernels only: no allocation, no host copy, no
+// synchronisation, so it can be captured in a graph.
+struct SpecCall {
+    int kind;  // FL_SPEC_*
+    int64_t nf;
+    const double* F;
+    int64_t ldf;
+    int64_t na;
+    const double* alpha;  // host, na
+    const double* sprm;   // host, na (diffusion: mu t); null for the fractional kind
+    int paired;
+    double* U;
+    int64_t ldu;
+};
+hipError_t fl_queue_spectral(const fl_op* op, hipStream_t s, const SpecCall& c, double* ws, const SplitWs* split,
+                             bool timed);
+size_t fl_spectral_ws_doubles(int64_t n, int64_t nf, int64_t na);
 hipError_t fl_check_finite(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, int* flag_dev);
 
 // chol.hip

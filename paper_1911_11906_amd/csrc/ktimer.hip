@@ -1,7 +1,9 @@
 // Optional per-kernel timing: HIP events recorded on the launching stream
 // immediately before and after selected kernel launches, accumulated by name.
 // Off by default (no events are created); used to time the dominant kernel
-// of a run live, beside an external profiler.
+// of a run live, beside an external profiler.  Launches queued while their
+// stream is being captured into a graph are not timed (the events would
+// belong to the graph).  Disabling the timer destroys every pending event.
 #include <map>
 #include <mutex>
 #include <string>
@@ -22,11 +24,18 @@ Registry& reg() {
 }  // namespace
 
 KScope::KScope(const char* name, hipStream_t s) : name_(name), s_(s) {
+    if (!name) return;
     Registry& r = reg();
     std::lock_guard<std::mutex> g(r.mu);
     if (!r.enabled) return;
-    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) return;
-    if (hipEventRecord(a_, s_) != hipSuccess) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
+    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess || hipEventRecord(a_, s_) != hipSuccess) {
+        if (a_) (void)hipEventDestroy(a_);
+        if (b_) (void)hipEventDestroy(b_);
+        a_ = b_ = nullptr;
+        return;
+    }
     on_ = true;
 }
 
@@ -34,7 +43,12 @@ KScope::~KScope() {
     if (!on_) return;
     Registry& r = reg();
     std::lock_guard<std::mutex> g(r.mu);
-    if (hipEventRecord(b_, s_) == hipSuccess) r.ev[name_].push_back({a_, b_});
+    if (hipEventRecord(b_, s_) == hipSuccess) {
+        r.ev[name_].push_back({a_, b_});
+    } else {
+        (void)hipEventDestroy(a_);
+        (void)hipEventDestroy(b_);
+    }
 }
 
 extern "C" {
@@ -43,6 +57,15 @@ int fl_kernel_timing(int enable) {
     Registry& r = reg();
     std::lock_guard<std::mutex> g(r.mu);
     r.enabled = enable != 0;
+    if (!r.enabled) {
+        for (auto& kv : r.ev)
+            for (auto& p : kv.second) {
+                (void)hipEventSynchronize(p.second);
+                (void)hipEventDestroy(p.first);
+                (void)hipEventDestroy(p.second);
+            }
+        r.ev.clear();
+    }
     return FL_OK;
 }
 

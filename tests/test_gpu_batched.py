@@ -22,7 +22,10 @@ def note(*a):
 @pytest.fixture(scope="module")
 def ctx():
     from paper_1911_11906_amd.api import Context
-    return Context(0)
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
 
 
 def exact(mesh):

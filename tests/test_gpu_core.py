@@ -21,7 +21,10 @@ def ctx():
     import torch
     assert torch.cuda.is_available()
     from paper_1911_11906_amd.api import Context
-    return Context(0)
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
 
 
 def to_np(t):

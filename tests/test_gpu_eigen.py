@@ -6,6 +6,7 @@ eigenvalues, orthonormality, residuals, and products that reassemble the
 input.  Tolerances are multiples of eps * n * ||A||.
 """
 import numpy as np
+import torch
 import pytest
 
 from paper_1911_11906_amd import inputs
@@ -22,7 +23,10 @@ def note(*a):
 @pytest.fixture(scope="module")
 def ctx():
     from paper_1911_11906_amd.api import Context
-    return Context(0)
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
 
 
 def to_np(t):

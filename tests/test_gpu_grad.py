@@ -23,7 +23,10 @@ def note(*a):
 @pytest.fixture(scope="module")
 def ctx():
     from paper_1911_11906_amd.api import Context
-    return Context(0)
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
 
 
 def misfit(op, Mt, F, alpha, Uobs):
@@ -102,10 +105,15 @@ def test_autograd_eigenfunction_closed_form(ctx):
 def test_differentiation_config_n32761(ctx):
     """The differentiation workload at full size: Q1 on the 181 x 181
     interior grid (n = 32761), mixed-precision eigensolve, 128 seeded
-    (f, alpha) pairs with held-out observation orders.  The adjoint is
-    checked against central differences of the same GPU forward map in the
-    alpha of 4 sampled pairs and along one random direction in f."""
+    (f, alpha) pairs with held-out observation orders.  Against the exact
+    discrete closed form (separable sine transforms, oracle/closed_form.py):
+    every eigenvalue to 1e-12, 16 sampled solutions to 1e-10 in the M-norm,
+    the adjoint (GF, galpha) for a given dL/dU to 1e-10, and the misfit
+    gradient through autograd to 1e-8 (the residual u - u_obs cancels).
+    The adjoint is also checked against central differences of the GPU
+    forward map in the alpha of 4 sampled pairs and along one direction in f."""
     note("differentiation n=32761")
+    from oracle.closed_form import Q1Rectangle
     from paper_1911_11906_amd.api import Operator
     m = 181
     mesh = inputs.q1_rectangle(m, m)
@@ -114,6 +122,9 @@ def test_differentiation_config_n32761(ctx):
     op = Operator.assemble(ctx, mesh)
     info = op.eigensolve("mixed")
     assert info["refine_iters"] >= 1
+    cf = Q1Rectangle(m, m)
+    th, _ = op.eigenpairs(want_vectors=False)
+    th_err = float(np.max(np.abs(th.cpu().numpy() - cf.eigenvalues()) / cf.eigenvalues()))
     dev = ctx.device
     K, M = op.matrices()
     del K
@@ -122,12 +133,36 @@ def test_differentiation_config_n32761(ctx):
     al0 = inputs.alphas_uniform(nb, tag=51)
     al_obs = inputs.alphas_uniform(nb, tag=52)
     Uobs = op.apply(F0, al_obs, paired=True)
+    U = op.apply(F0, al0, paired=True)
+    cols = np.arange(0, nb, 8)
+    Ucf = np.stack([cf.apply(F0[:, b], [al0[b]])[:, 0] for b in cols], 1)
+    Ucf_t = torch.from_numpy(Ucf).to(dev)
+    D = U[:, cols] - Ucf_t
+    u_err = torch.sqrt((D * (M @ D)).sum(0) / (Ucf_t * (M @ Ucf_t)).sum(0)).max().item()
+    # the adjoint for one given dL/dU against the closed-form adjoint
+    GUh = np.random.default_rng(11).standard_normal((n, nb))
+    GFg, gag = op.grad(F0, al0, GUh)
+    GFc, gac, _ = cf.grad(F0, al0, GUh)
+    gf_err = float(np.abs(GFg.cpu().numpy() - GFc).max() / np.abs(GFc).max())
+    ga_err = float(np.abs(gag.numpy() - gac).max() / np.abs(gac).max())
+    note(f"c5: eig err {th_err:.3e}, solution err {u_err:.3e}, adjoint GF err {gf_err:.3e}, galpha err {ga_err:.3e}")
+    assert th_err <= 1e-12
+    assert u_err <= 1e-10
+    assert gf_err <= 1e-10 and ga_err <= 1e-10
+    # the misfit gradient through autograd against the closed form
     F = torch.from_numpy(F0).to(dev).requires_grad_(True)
     alpha = torch.from_numpy(al0).requires_grad_(True)
     L = misfit(op, M, F, alpha, Uobs)
     L.backward()
     GF = F.grad.detach()
     ga = alpha.grad.detach().numpy()
+    Uc_all = np.stack([cf.apply(F0[:, b], [al0[b]])[:, 0] for b in range(nb)], 1)
+    Uo_all = np.stack([cf.apply(F0[:, b], [al_obs[b]])[:, 0] for b in range(nb)], 1)
+    R = Uc_all - Uo_all
+    GUc = 2 * cf._synth(cf._coeffs(R), mass=True)
+    GFc2, gac2, _ = cf.grad(F0, al0, GUc)
+    assert float(np.abs(ga - gac2).max() / np.abs(gac2).max()) <= 1e-8
+    assert float((GF.cpu().numpy() - GFc2).__abs__().max() / np.abs(GFc2).max()) <= 1e-8
     h = 1e-4
     with torch.no_grad():
         Ft = torch.from_numpy(F0).to(dev)
@@ -137,7 +172,8 @@ def test_differentiation_config_n32761(ctx):
             lp = misfit(op, M, Ft, torch.from_numpy(al0 + e), Uobs).item()
             lm = misfit(op, M, Ft, torch.from_numpy(al0 - e), Uobs).item()
             assert ga[b] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-10 * abs(L.item()))
-        D = torch.from_numpy(np.random.default_rng(7).standard_normal(F0.shape)).to(dev)
-        lp = misfit(op, M, Ft + h * D, torch.from_numpy(al0), Uobs).item()
-        lm = misfit(op, M, Ft - h * D, torch.from_numpy(al0), Uobs).item()
-        assert float((GF * D).sum()) == pytest.approx((lp - lm) / (2 * h), rel=1e-6)
+        Dd = torch.from_numpy(np.random.default_rng(7).standard_normal(F0.shape)).to(dev)
+        lp = misfit(op, M, Ft + h * Dd, torch.from_numpy(al0), Uobs).item()
+        lm = misfit(op, M, Ft - h * Dd, torch.from_numpy(al0), Uobs).item()
+        assert float((GF * Dd).sum()) == pytest.approx((lp - lm) / (2 * h), rel=1e-6)
+    op.close()
