@@ -8,16 +8,22 @@ resident in HBM:
     back-transforms, V = L^-T Z, and in mixed mode (the default) FP32
     back-transforms followed by two FP64 refinement steps;
   * the fractional solutions v(alpha_i, f_j) for 1024 seeded random cubic
-    polynomial forcings x 32 orders alpha ~ U(0, 2) (32768 solutions);
+    polynomial forcings x 32 orders alpha ~ U(0, 2) (32768 solutions), as a
+    replay of the captured application graph;
   * the batched FP64 eigensolve of 256 seeded Q1 rectangles / L-shapes with
     n ~ U[64, 1024] (one persistent launch).
 value = solutions per second of the whole step (both eigensolves included).
 
-Extra fields: eigensolve seconds and nominal TFLOP/s (9 n^3) of the timed
-precision and of the other one (timed once, outside the timed region), the
-mixed-over-FP64 speedup, per-stage times, live rooflines of the timed
-kernels (HIP events on their launch stream) with the dominant one as
-`roofline`, and the CPU oracle timed on a bounded sample.
+Outside the timed region: the launch shapes of the application's products
+(tuned on the device, or read from the tuning file for this architecture);
+the measured FP64 / FP32 matrix-core and copy ceilings; the eigensolve in
+both precisions on the Q1 square and on the P1 polygon mesh with two holes
+(n = 16384), one warm-up then the median of 3 each, with nominal TFLOP/s
+(9 n^3) and the fraction of the stage-wise roofline; the application alone
+(3 warm-ups, median of 10 graph replays): fractional solves/s =
+nf na / T_apply; live per-kernel rooflines (HIP events on each kernel's
+launch stream) with the dominant kernel as `roofline`; and the CPU oracle
+timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -53,7 +59,28 @@ def parse():
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="run one plain device copy of this many MiB before the timed region "
                         "(reference reading for HBM byte counters)")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the untimed measurements (P1 mesh, medians, apply alone, peaks)")
+    p.add_argument("--tuning", default=None, help="tuning file (default: the package's file for this "
+                                                   "architecture; tuned on the device when missing)")
+    p.add_argument("--retune", action="store_true", help="tune the application's products again")
     return p.parse_args()
+
+
+def host_cpu():
+    """CPU model and physical core count of the host (lscpu)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = dict(line.split(":", 1) for line in out.splitlines() if ":" in line)
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        info["cpu_model"] = kv.get("Model name")
+        info["physical_cores"] = int(kv.get("Core(s) per socket", 0)) * int(kv.get("Socket(s)", 0)) or None
+        info["logical_cpus"] = int(kv.get("CPU(s)", 0)) or None
+    except Exception:
+        pass
+    return info
 
 
 def cpu_baseline(m: int, nf: int, na: int, budget: float):
@@ -69,6 +96,7 @@ def cpu_baseline(m: int, nf: int, na: int, budget: float):
     from paper_1911_11906_amd import inputs
 
     threads = oracle.num_threads()
+    host = host_cpu()
     # eigensolve sample
     ms = 12
     t_eig = None
@@ -99,7 +127,7 @@ def cpu_baseline(m: int, nf: int, na: int, budget: float):
     oracle.apply_fractional(th, V, M, F, al)
     dt_apply = (time.perf_counter() - t0) / 2.0
     total = t_eig_full + dt_apply * nf * na
-    return {"value": nf * na / total, "unit": "solves/s", "cores": threads, "kind": "oracle",
+    return {"value": nf * na / total, "unit": "solves/s", "cores": threads, "kind": "oracle", **host,
             "sample": (f"Jacobi eigensolve at n={t_eig[0]} ({t_eig[1]:.2f} s) scaled by (n/{t_eig[0]})^3 to "
                        f"{t_eig_full:.0f} s; oracle apply at n={n} on 2 (f, alpha) pairs "
                        f"({dt_apply:.2f} s each) scaled to {nf * na} solutions")}
@@ -152,6 +180,55 @@ def traffic_for(kernel: str):
     return None
 
 
+def eig_roofline_ms(n: int, prec: str, refine_steps: int) -> float:
+    """Stage-wise roofline time of the eigensolve: each stage's algorithmic
+    flops at the datasheet peak of its arithmetic (FP64: Cholesky n^3/3,
+    standard form n^3, band reduction 4/3 n^3, divide and conquer 4/3 n^3,
+    back-substitution n^3; both back-transforms 2 n^3 each, FP32 in mixed
+    mode; refinement 4 n^3 per step in FP64)."""
+    n3 = float(n) ** 3
+    f64 = (1 / 3 + 1 + 4 / 3 + 4 / 3 + 1) * n3 + 4.0 * n3 * refine_steps
+    bt = 4.0 * n3
+    t = f64 / (PEAK_FP64_TFLOPS * 1e12)
+    t += bt / ((PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS) * 1e12)
+    return t * 1e3
+
+
+def time_eigensolves(op, prec: str, reps: int = 3):
+    import numpy as np
+    op.eigensolve(prec)  # warm-up
+    infos = [op.eigensolve(prec) for _ in range(reps)]
+    ms = float(np.median([i["total_ms"] for i in infos]))
+    n = op.n
+    return {"s": ms / 1e3, "tflops_nominal": 9.0 * n ** 3 / (ms / 1e3) / 1e12,
+            "roofline_frac": eig_roofline_ms(n, prec, infos[0]["refine_iters"]) / ms,
+            "refine_iters": infos[0]["refine_iters"],
+            "stage_ms": {k: float(np.median([i["stage_ms"][k] for i in infos])) for k in infos[0]["stage_ms"]}}
+
+
+def setup_tuning(ctx, args, n: int, nf: int, na: int):
+    """Launch shapes of the application's two products: read from the tuning
+    file for this architecture, or measured on the device (and written)."""
+    import torch
+    arch = torch.cuda.get_device_properties(ctx.device).gcnArchName.split(":")[0]
+    path = args.tuning or os.path.join(ROOT, "paper_1911_11906_amd", "tuning", f"{arch}.json")
+    shapes = [("f64", n, nf, n, True, False), ("scaled", n, nf * na, n, False, False)]
+    if os.path.exists(path) and not args.retune:
+        ctx.load_tuning(path)
+        have = {(e["kind"], e["m"], e["n"]) for e in ctx.tuning_table()}
+        kinds = {"f64": 0, "scaled": 2}
+        if all((kinds[k], m, nn) in have for k, m, nn, _, _, _ in shapes):
+            return {"source": os.path.relpath(path, ROOT), "entries": ctx.tuning_table()}
+    for kind, m, nn, k, ta, tb in shapes:
+        ctx.gemm_tune(kind, m, nn, k, ta=ta, tb=tb, reps=3)
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        ctx.save_tuning(path)
+    except OSError:
+        pass
+    return {"source": "tuned on the device", "entries": ctx.tuning_table()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -175,13 +252,14 @@ def main():
     bops = [Operator.assemble(ctx, m) for m in bmeshes]
     bflops = sum(9.0 * m.n_dof ** 3 for m in bmeshes)
     torch.cuda.synchronize()
+    tuning = setup_tuning(ctx, args, n, args.nf, args.na)
     prec = args.precision
     other = "mixed" if prec == "fp64" else "fp64"
     binfos = []
 
     def step():
         info = op.eigensolve(prec)
-        op.apply(F, alpha, out=U)
+        op.apply_graph(F, alpha, out=U)
         if bops:
             binfos.append(ctx.eigensolve_batched(bops)[0])
         return info
@@ -194,11 +272,49 @@ def main():
         del src, dst
     for _ in range(args.warmup):
         step()
-    # the other precision, once, outside the timed region (for the comparison)
     torch.cuda.synchronize()
-    info_other = op.eigensolve(other) if not args.no_compare else None
-    torch.cuda.synchronize()
+    extra = {}
+    if not args.no_extra:
+        extra["peaks_measured"] = ctx.measure_peaks()
+        # the eigensolve alone: both precisions on both n = 16384 meshes
+        eig = {"q1_square": {p: time_eigensolves(op, p) for p in ("fp64", "mixed")}}
+        op.eigensolve(prec)  # leave the timed precision's basis in place
+        pm = inputs.p1_polygon_with_holes(16384)
+        op3 = Operator.assemble(ctx, pm)
+        eig["p1_polygon"] = {p: time_eigensolves(op3, p) for p in ("fp64", "mixed")}
+        op3.close()
+        for mk in eig:
+            eig[mk]["mixed_speedup_over_fp64"] = eig[mk]["fp64"]["s"] / eig[mk]["mixed"]["s"]
+        extra["eigensolve_n16384"] = eig
+        # the application alone: graph replays timed with events on the caller's stream
+        st = torch.cuda.current_stream(dev)
+        for _ in range(3):
+            op.apply_graph(F, alpha, out=U)
+        times = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            op.apply_graph(F, alpha, out=U)
+            e1.record(st)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        t_apply = float(np.median(times))
+        nsol = args.nf * args.na
+        extra["apply"] = {"ms": t_apply, "apply_solves_per_s": nsol / (t_apply / 1e3),
+                          "tflops": 2.0 * n * n * args.nf * (1 + args.na) / (t_apply / 1e3) / 1e12,
+                          "bound_solves_per_s": nsol / (2.0 * n * n * args.nf * (1 + args.na)
+                                                        / (PEAK_FP64_TFLOPS * 1e12))}
+    # the fused scaled product timed live on its launch stream (eager launches)
     ctx.kernel_timing(True)
+    for k in KERNELS:
+        ctx.kernel_time(k)
+    for _ in range(3):
+        op.apply(F, alpha, out=U)
+    torch.cuda.synchronize()
+    sg_cnt, sg_ms = ctx.kernel_time("scaled_gemm")
+    info_other = op.eigensolve(other) if not args.no_compare else None
+    op.eigensolve(prec)
+    torch.cuda.synchronize()
     for k in KERNELS:
         ctx.kernel_time(k)  # drop anything recorded before
     torch.cuda.synchronize()
@@ -208,8 +324,9 @@ def main():
         infos.append(step())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ctx.kernel_timing(False)
     ktime = {k: ctx.kernel_time(k) for k in KERNELS}
+    ctx.kernel_timing(False)
+    ktime["scaled_gemm"] = (sg_cnt, sg_ms)
 
     step_s = wall / args.steps
     nsol = args.nf * args.na
@@ -218,7 +335,7 @@ def main():
     stages = {k: float(np.median([i["stage_ms"][k] for i in infos])) for k in infos[0]["stage_ms"]}
     b = 64
     peak_mm = PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS
-    per_step_flops = {
+    per_launch_flops = {
         "q2_apply": q2_flops(n, b),
         "sb2st": sb2st_flops(n, b),
         "scaled_gemm": 2.0 * n * n * nsol,
@@ -228,19 +345,22 @@ def main():
     for k, (cnt, ms) in ktime.items():
         if cnt == 0:
             continue
-        fl = per_step_flops[k] * args.steps
+        fl = per_launch_flops[k] * cnt
         ach = fl / (ms / 1e3) / 1e12
         bound, peak = ("alu", PEAK_FP64_TFLOPS) if k in ("sb2st", "batched_eig") else (
             "mfma", peak_mm if k == "q2_apply" else PEAK_FP64_TFLOPS)
         kernels[k] = {"launches": cnt, "total_ms": ms, "avg_ms": ms / cnt, "flops_per_launch": fl / cnt,
                       "bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    # dominant kernel: largest time per step (the scaled product was timed
+    # on its own launches; each step launches every kernel once)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     d = kernels[dom]
     traffic = traffic_for(dom)
     roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s",
                 "frac": d["frac"], "traffic": traffic, "kernel": dom, "avg_launch_ms": d["avg_ms"],
                 "flops_per_launch": d["flops_per_launch"]}
     apply_ms = kernels.get("scaled_gemm", {}).get("avg_ms")
+    bms = [bi["total_ms"] for bi in binfos[-args.steps:]]
     out = {
         "metric": METRIC,
         "value": nsol / step_s,
@@ -255,8 +375,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"Q1 unit square {args.m}x{args.m} (n={n}): {prec} full generalized eigensolve + "
-                               f"{args.nf} cubic forcings x {args.na} alpha + batched FP64 eigensolve of "
-                               f"{args.nbatch} seeded rectangles/L-shapes (n in [64, 1024])", "n": n,
+                               f"{args.nf} cubic forcings x {args.na} alpha (graph replay) + batched FP64 "
+                               f"eigensolve of {args.nbatch} seeded rectangles/L-shapes (n in [64, 1024])", "n": n,
                    "nf": args.nf, "na": args.na, "precision": prec, "nbatch": args.nbatch},
         "eigensolve_s": eig_s,
         "eigensolve_tflops_nominal": flops_eig / eig_s / 1e12,
@@ -266,16 +386,23 @@ def main():
         "roofline": roofline,
         "batched_eigensolve": None if not bops else {
             "problems": len(bops), "n_min": min(m.n_dof for m in bmeshes), "n_max": max(m.n_dof for m in bmeshes),
-            "launch_ms": float(np.median([b["total_ms"] for b in binfos[-args.steps:]])),
-            "problems_per_s": len(bops) / (float(np.median([b["total_ms"] for b in binfos[-args.steps:]])) / 1e3),
-            "tflops_nominal": bflops / (float(np.median([b["total_ms"] for b in binfos[-args.steps:]])) / 1e3) / 1e12},
+            "launch_ms": float(np.median(bms)), "problems_per_s": len(bops) / (float(np.median(bms)) / 1e3),
+            "tflops_nominal": bflops / (float(np.median(bms)) / 1e3) / 1e12},
         "kernels": kernels,
+        "tuning": tuning,
+        **extra,
     }
     if info_other is not None:
         t_other = info_other["total_ms"] / 1e3
         out[f"eigensolve_{other}_s"] = t_other
         t64, tmx = (eig_s, t_other) if prec == "fp64" else (t_other, eig_s)
         out["mixed_speedup_over_fp64"] = t64 / tmx
+    # release every library object before the process exits
+    for o in bops:
+        o.close()
+    op.close()
+    torch.cuda.synchronize()
+    ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.m, args.nf, args.na, args.cpu_budget)
     print(json.dumps(out), flush=True)

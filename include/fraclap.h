@@ -59,6 +59,7 @@ enum {
     FL_EIO = -7       /* a file could not be read or written, or failed its checks */
 };
 enum { FL_ELEM_P1 = 3, FL_ELEM_Q1 = 4 };
+#define FL_ELEM_QP(p) (((p) + 1) * ((p) + 1))
 enum { FL_FP64 = 0, FL_MIXED = 1 };
 
 /* Eigensolve stages, in order (indices into fl_eig_info.stage_ms). */
@@ -117,13 +118,17 @@ const char *fl_last_error(const fl_ctx *ctx);
  * Assemble K and M for a mesh with homogeneous Dirichlet data (Section
  * "Accuracy"): Dirichlet nodes are eliminated, interior nodes become DOFs in
  * node order.  elem = FL_ELEM_Q1 (4 nodes, counter-clockwise, axis-aligned
- * rectangles) or FL_ELEM_P1 (3 nodes, counter-clockwise).  Exact element
- * integrals (consistent mass).  xy: host, n_nodes x 2 row-major (x, y);
+ * rectangles), FL_ELEM_P1 (3 nodes, counter-clockwise), or FL_ELEM_QP(p) =
+ * (p+1)^2 for tensor-product Lagrange elements of order 2 <= p <= 8 on
+ * axis-aligned rectangles (the order sweep of Section "Accuracy"): nodes in
+ * lexicographic order a + (p+1) b, node (a, b) at (x of (a, 0), y of (0, b)),
+ * x and y increasing.  Exact element integrals (consistent mass).  xy: host, n_nodes x 2 row-major (x, y);
  * conn: host, n_elem x elem row-major; dirichlet: host, n_nodes flags.
  * *n_dof receives n; dof_of_node (host, n_nodes, may be NULL) receives the
  * DOF index of each node or -1.  FL_EINVAL for NaN/Inf coordinates, node
  * indices out of range, clockwise or degenerate elements, non-rectangular Q1
- * elements, or no interior node. */
+ * elements, order-p elements whose nodes are not an increasing tensor
+ * lattice, or no interior node. */
 int fl_assemble(fl_ctx *ctx, int elem, int64_t n_nodes, const double *xy, int64_t n_elem,
                 const int32_t *conn, const uint8_t *dirichlet, fl_op **out, int64_t *n_dof,
                 int64_t *dof_of_node);
@@ -183,6 +188,20 @@ int fl_op_load(fl_ctx *ctx, const char *path, fl_op **out);
  * FL_FP64, FL_MIXED, or -1 when installed by fl_op_set_eigenpairs); any
  * output may be NULL. */
 int fl_op_info(const fl_op *op, int64_t *n, int *has_eig, int *precision, int *refine_iters, double *refine_resid);
+
+/* ---- eigenvalue counting (Section "Eigenvalue counting") ------------------
+ * By Sylvester's law of inertia the number of eigenvalues of
+ * K phi = theta M phi below sigma equals the number of negative pivots of an
+ * LDL^T factorisation of K - sigma M.  The pencil's pattern is renumbered to
+ * a small bandwidth (natural or reverse Cuthill-McKee numbering, whichever is
+ * narrower; a symmetric permutation keeps the inertia; computed once per
+ * operator on the host), and the banded matrix of each shift is factored
+ * without pivoting on the device, one workgroup per shift.
+ * sigma: host, nshift shifts; counts: host, nshift results (-1 where a pivot
+ * was exactly zero); bandwidth (host, may be NULL) receives the bandwidth
+ * used.  FL_EINVAL for a non-finite shift, an operator without a sparse
+ * pattern, or a bandwidth above 255.  Needs no eigenpairs.  Synchronous. */
+int fl_inertia_count(fl_op *op, int64_t nshift, const double *sigma, int64_t *counts, int64_t *bandwidth);
 
 /* ---- spectral application (the equation for v, Section "Method") ---------
  * F: device, n x nf (ld ldf).  alpha: host, na orders in [0, 2].

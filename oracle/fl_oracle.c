@@ -25,6 +25,10 @@
  *     u(t) = sum_k exp(-mu theta_k^(alpha/2) t) <u0, phi_k> phi_k (equation
  *     diffusion_solution) and its adjoint with respect to u0, alpha, t, mu.
  *
+ * Elements: linear triangles, bilinear quadrilaterals and, for the order
+ * sweep of Section "Accuracy", tensor-product Lagrange elements of order
+ * p = 2..8 on axis-aligned rectangles ((p+1)^2 nodes, lexicographic).
+ *
  * All matrices are column-major: A[i + j*lda].
  * Precision: IEEE double throughout.
  */
@@ -120,6 +124,91 @@ static int p1_element(const double *x, const double *y, double Ke[9], double Me[
     return 0;
 }
 
+/* Gauss-Legendre rule with m points on [-1, 1]: the nodes are the roots of
+ * the Legendre polynomial P_m, found by Newton's method from the estimates
+ * cos(pi (i + 3/4) / (m + 1/2)), with P_m and P_m' from the three-term
+ * recurrence (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}; the weights are
+ * 2 / ((1 - x^2) P_m'(x)^2).  Exact for polynomials of degree 2m - 1. */
+static void gauss_legendre(int m, double *x, double *w) {
+    for (int i = 0; i < m; ++i) {
+        double z = cos(acos(-1.0) * (i + 0.75) / (m + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < m; ++k) {
+                double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            /* P_m = p1, P_{m-1} = p0; P_m' = m (z P_m - P_{m-1}) / (z^2 - 1) */
+            dp = m * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* Lagrange basis through the nodes s[0..p] at t: values L[a] and
+ * derivatives D[a] (product rule over the factors (t - s_b)/(s_a - s_b)). */
+static void lagrange_basis(int p, const double *s, double t, double *L, double *D) {
+    for (int a = 0; a <= p; ++a) {
+        double v = 1.0, d = 0.0;
+        for (int b = 0; b <= p; ++b) {
+            if (b == a) continue;
+            double f = (t - s[b]) / (s[a] - s[b]);
+            d = d * f + v / (s[a] - s[b]);
+            v *= f;
+        }
+        L[a] = v;
+        D[a] = d;
+    }
+}
+
+/* Tensor-product element of order p on an axis-aligned rectangle, nodes in
+ * lexicographic order a + (p+1) b (a along x).  The reference coordinates
+ * of the nodes follow from the physical ones (bottom row for x, left column
+ * for y); the basis functions are N_ab(xi, eta) = l_a(xi) l_b(eta), and the
+ * element integrals use the (p+1) x (p+1) Gauss rule on the reference square
+ * (the integrands are polynomials of degree <= 2p in each variable).
+ * Returns -1 for a degenerate element. */
+static int qp_element(int p, const double *x, const double *y, double *Ke, double *Me) {
+    const int q = p + 1, nv = q * q;
+    double xmin = x[0], xmax = x[p], ymin = y[0], ymax = y[p * q];
+    double hx = xmax - xmin, hy = ymax - ymin;
+    if (!(hx > 0.0) || !(hy > 0.0)) return -1;
+    double sx[9], sy[9], gp[9], gw[9], Lx[9], Dx[9], Ly[9], Dy[9];
+    for (int a = 0; a <= p; ++a) {
+        sx[a] = -1.0 + 2.0 * (x[a] - xmin) / hx;
+        sy[a] = -1.0 + 2.0 * (y[a * q] - ymin) / hy;
+    }
+    gauss_legendre(q, gp, gw);
+    memset(Ke, 0, sizeof(double) * nv * nv);
+    memset(Me, 0, sizeof(double) * nv * nv);
+    const double det = 0.25 * hx * hy;
+    for (int i1 = 0; i1 < q; ++i1) {
+        lagrange_basis(p, sx, gp[i1], Lx, Dx);
+        for (int i2 = 0; i2 < q; ++i2) {
+            lagrange_basis(p, sy, gp[i2], Ly, Dy);
+            double wq = gw[i1] * gw[i2] * det;
+            for (int i = 0; i < nv; ++i) {
+                int a = i % q, b = i / q;
+                double Ni = Lx[a] * Ly[b];
+                double gxi = (2.0 / hx) * Dx[a] * Ly[b], gyi = (2.0 / hy) * Lx[a] * Dy[b];
+                for (int j = 0; j < nv; ++j) {
+                    int c = j % q, d = j / q;
+                    double Nj = Lx[c] * Ly[d];
+                    double gxj = (2.0 / hx) * Dx[c] * Ly[d], gyj = (2.0 / hy) * Lx[c] * Dy[d];
+                    Ke[i * nv + j] += wq * (gxi * gxj + gyi * gyj);
+                    Me[i * nv + j] += wq * Ni * Nj;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
 /* Assemble dense K and M (n_dof x n_dof, column-major, ld = n_dof) over the
  * interior DOFs.  dof_of_node[v] = dof index or -1 for a Dirichlet node.
  * If Kfull/Mfull are non-NULL they receive the matrices over ALL nodes
@@ -133,15 +222,26 @@ int or_assemble(int elem, int64_t n_nodes, const double *xy, int64_t n_elem,
     if (Kfull) memset(Kfull, 0, sizeof(double) * (size_t)n_nodes * (size_t)n_nodes);
     if (Mfull) memset(Mfull, 0, sizeof(double) * (size_t)n_nodes * (size_t)n_nodes);
     int nv = elem;
+    int p = 0; /* order of a tensor-product element with nv = (p+1)^2 > 4 nodes */
+    if (nv > 4) {
+        while ((p + 1) * (p + 1) < nv) ++p;
+        if ((p + 1) * (p + 1) != nv || p > 8) return -1;
+    }
+    double *Ke = (double *)malloc(sizeof(double) * 81 * 81);
+    double *Me = (double *)malloc(sizeof(double) * 81 * 81);
     for (int64_t e = 0; e < n_elem; ++e) {
-        double x[4] = {0}, y[4] = {0}, Ke[16], Me[16];  // nv (3 or 4) entries are set below
+        double x[81] = {0}, y[81] = {0};  // the first nv entries are set below
         for (int a = 0; a < nv; ++a) {
             int32_t v = conn[e * nv + a];
             x[a] = xy[2 * (size_t)v];
             y[a] = xy[2 * (size_t)v + 1];
         }
-        int rc = (nv == 4) ? q1_element(x, y, Ke, Me) : p1_element(x, y, Ke, Me);
-        if (rc) return (int)(-(1 + e));
+        int rc = (nv == 4) ? q1_element(x, y, Ke, Me) : (nv == 3) ? p1_element(x, y, Ke, Me) : qp_element(p, x, y, Ke, Me);
+        if (rc) {
+            free(Ke);
+            free(Me);
+            return (int)(-(1 + e));
+        }
         for (int a = 0; a < nv; ++a) {
             int32_t va = conn[e * nv + a];
             for (int b = 0; b < nv; ++b) {
@@ -157,6 +257,8 @@ int or_assemble(int elem, int64_t n_nodes, const double *xy, int64_t n_elem,
             }
         }
     }
+    free(Ke);
+    free(Me);
     return 0;
 }
 

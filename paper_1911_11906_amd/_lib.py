@@ -28,7 +28,7 @@ EXPORTS = [
     "fl_ctx_create", "fl_ctx_set_stream", "fl_ctx_destroy", "fl_last_error",
     "fl_assemble", "fl_op_from_dense", "fl_op_n", "fl_op_matrices", "fl_op_destroy",
     "fl_eigensolve", "fl_eigensolve_batched", "fl_eigenpairs", "fl_op_set_eigenpairs",
-    "fl_op_save", "fl_op_load", "fl_op_info",
+    "fl_op_save", "fl_op_load", "fl_op_info", "fl_inertia_count",
     "fl_apply_fractional", "fl_grad_apply", "fl_apply_graph", "fl_apply_diffusion", "fl_grad_diffusion",
     "fl_gemm_tune", "fl_gemm_tuning_set", "fl_gemm_tuning_count", "fl_gemm_tuning_get", "fl_gemm_tuning_clear",
     "fl_dgemm", "fl_dpotrf", "fl_dsygst", "fl_dstedc", "fl_dsytrd_2stage", "fl_dsyevd",
@@ -97,6 +97,7 @@ def load(path: str = SO_PATH):
         "fl_eigensolve_batched": ([P, i64, P, i32, P], i32),
         "fl_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_op_set_eigenpairs": ([P, P, P, i64, i32], i32),
+        "fl_inertia_count": ([P, i64, P, P, ctypes.POINTER(i64)], i32),
         "fl_op_save": ([P, ctypes.c_char_p], i32),
         "fl_op_load": ([P, ctypes.c_char_p, pp], i32),
         "fl_op_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),

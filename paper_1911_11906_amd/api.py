@@ -346,6 +346,17 @@ class Operator:
                                                         int(paired), _ptr(U), _ld(U)))
         return U
 
+    def inertia(self, sigma):
+        """Number of eigenvalues below each shift (Sylvester inertia of
+        K - sigma M on the device); returns (counts, bandwidth)."""
+        sg = np.ascontiguousarray(np.atleast_1d(np.asarray(sigma, dtype=np.float64)))
+        cnt = np.zeros(sg.size, dtype=np.int64)
+        bw = ctypes.c_int64(0)
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.fl_inertia_count(self.ptr, sg.size, sg.ctypes.data_as(P), cnt.ctypes.data_as(P),
+                                                     ctypes.byref(bw)))
+        return cnt, bw.value
+
     def apply_graph(self, F, alpha, paired: bool = False, out=None) -> torch.Tensor:
         """Same as ``apply`` (bitwise), captured once per argument set into a
         HIP graph and replayed afterwards (F and out must keep their storage)."""

@@ -145,6 +145,7 @@ void fl_op_destroy(fl_op* op) {
     dev_free(op->theta);
     dev_free(op->logtheta);
     dev_free(op->V);
+    dev_free(op->inert_pinv);
     fl_op_release_spectral(op);
     delete op;
 }
@@ -155,12 +156,17 @@ int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_
     if (!out || !xy || !conn || !dirichlet || n_nodes <= 0 || n_elem <= 0)
         return fl_fail(ctx, FL_EINVAL, "fl_assemble: null pointer or empty mesh");
     *out = nullptr;
-    if (elem != FL_ELEM_Q1 && elem != FL_ELEM_P1) return fl_fail(ctx, FL_EINVAL, "fl_assemble: elem must be 3 or 4");
+    int order = 0;  // tensor-product order for elem = (p + 1)^2 > 4
+    if (elem != FL_ELEM_Q1 && elem != FL_ELEM_P1) {
+        for (int p = 2; p <= 8; ++p)
+            if (elem == (p + 1) * (p + 1)) order = p;
+        if (!order) return fl_fail(ctx, FL_EINVAL, "fl_assemble: elem must be 3, 4 or (p+1)^2 with 2 <= p <= 8");
+    }
     if (!all_finite(xy, (size_t)n_nodes * 2)) return fl_fail(ctx, FL_EINVAL, "fl_assemble: non-finite coordinate");
     const int nv = elem;
     // validate elements
     for (int64_t e = 0; e < n_elem; ++e) {
-        double x[4], y[4];
+        double x[81], y[81];
         for (int a = 0; a < nv; ++a) {
             int32_t v = conn[e * nv + a];
             if (v < 0 || v >= n_nodes)
@@ -172,7 +178,7 @@ int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_
             double det = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
             if (!(det > 0.0))
                 return fl_fail(ctx, FL_EINVAL, "fl_assemble: triangle " + std::to_string(e) + " is clockwise or degenerate");
-        } else {
+        } else if (nv == 4) {
             double xmin = std::min(std::min(x[0], x[1]), std::min(x[2], x[3]));
             double xmax = std::max(std::max(x[0], x[1]), std::max(x[2], x[3]));
             double ymin = std::min(std::min(y[0], y[1]), std::min(y[2], y[3]));
@@ -191,6 +197,21 @@ int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_
                 return fl_fail(ctx, FL_EINVAL,
                                "fl_assemble: quadrilateral " + std::to_string(e) +
                                    " is not a counter-clockwise axis-aligned rectangle");
+        } else {
+            // tensor lattice: node (a, b) at (x of (a, 0), y of (0, b)), both increasing
+            const int q = order + 1;
+            bool ok = true;
+            for (int b = 0; b < q && ok; ++b)
+                for (int a = 0; a < q && ok; ++a) {
+                    const int i = a + q * b;
+                    if (x[i] != x[a] || y[i] != y[q * b]) ok = false;
+                    if (a > 0 && !(x[a] > x[a - 1])) ok = false;
+                    if (b > 0 && !(y[q * b] > y[q * (b - 1)])) ok = false;
+                }
+            if (!ok)
+                return fl_fail(ctx, FL_EINVAL,
+                               "fl_assemble: order-" + std::to_string(order) + " element " + std::to_string(e) +
+                                   " is not an increasing tensor lattice on an axis-aligned rectangle");
         }
     }
     std::vector<int64_t> dof(n_nodes, -1);

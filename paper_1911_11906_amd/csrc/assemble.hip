@@ -6,7 +6,13 @@
 //    of the 1-D linear-element matrices k = (1/h)[[1,-1],[-1,1]] and
 //    m = (h/6)[[2,1],[1,2]]:  Ke = kx (x) my + mx (x) ky,  Me = mx (x) my;
 //  * linear triangle of area A with barycentric gradients g_i:
-//    Ke_ij = A g_i . g_j,  Me_ij = (A/12)(1 + delta_ij).
+//    Ke_ij = A g_i . g_j,  Me_ij = (A/12)(1 + delta_ij);
+//  * tensor-product element of order p = 2..8 on an axis-aligned rectangle
+//    ((p+1)^2 nodes, lexicographic a + (p+1) b): the same tensor-product form
+//    with the 1-D order-p matrices k_ac = int l_a' l_c' and m_ac = int l_a l_c
+//    of the Lagrange basis through the element's node positions, integrated
+//    by the (p+1)-point Gauss rule (exact for degree 2p + 1) computed in the
+//    kernel; one workgroup per element.
 // Elements arrive grouped by colour (no two elements of a colour share a
 // node), so the scatter-add into the dense matrices needs no atomics and the
 // result is bitwise reproducible.
@@ -78,6 +84,111 @@ __global__ void assemble_kernel(const double* __restrict__ xy, const int32_t* __
     }
 }
 
+// Nodes and weights of the Q-point Gauss-Legendre rule: thread i < Q finds
+// root i of P_Q by Newton's method (P_Q and P_Q' by the three-term
+// recurrence) from the estimate cos(pi (i + 3/4) / (Q + 1/2)).
+template <int Q>
+__device__ void gauss_rule(double* gp, double* gw) {
+    const int i = threadIdx.x;
+    if (i >= Q) return;
+    double z = cos(3.141592653589793 * (i + 0.75) / (Q + 0.5)), dpq = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double pm = 1.0, pq = z;  // P_{k-1}, P_k
+        for (int k = 1; k < Q; ++k) {
+            const double pn = ((2 * k + 1) * z * pq - k * pm) / (k + 1);
+            pm = pq;
+            pq = pn;
+        }
+        dpq = Q * (z * pq - pm) / (z * z - 1.0);
+        const double dz = pq / dpq;
+        z -= dz;
+        if (fabs(dz) <= 1e-16) break;
+    }
+    gp[i] = z;
+    gw[i] = 2.0 / ((1.0 - z * z) * dpq * dpq);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void assemble_qp_kernel(const double* __restrict__ xy, const int32_t* __restrict__ conn,
+                                                          int64_t e0, const int64_t* __restrict__ dof, int64_t ld,
+                                                          double* K, double* M) {
+    constexpr int Q = P + 1, NV = Q * Q;
+    __shared__ double gp[Q], gw[Q], sx[Q], sy[Q], box[4];
+    __shared__ double Lx[Q][Q], Dx[Q][Q], Ly[Q][Q], Dy[Q][Q];  // [quadrature point][basis function]
+    __shared__ double kx[Q][Q], mx[Q][Q], ky[Q][Q], my[Q][Q];
+    __shared__ int64_t g[NV];
+    const int64_t e = e0 + blockIdx.x;
+    const int t = threadIdx.x;
+    const int32_t* cn = conn + e * NV;
+    if (t < NV) g[t] = dof[cn[t]];
+    if (t == 0) {
+        box[0] = xy[2 * (int64_t)cn[0]];
+        box[1] = xy[2 * (int64_t)cn[P]];
+        box[2] = xy[2 * (int64_t)cn[0] + 1];
+        box[3] = xy[2 * (int64_t)cn[P * Q] + 1];
+    }
+    gauss_rule<Q>(gp, gw);
+    __syncthreads();
+    const double hx = box[1] - box[0], hy = box[3] - box[2];
+    if (t < Q) {
+        sx[t] = -1.0 + 2.0 * (xy[2 * (int64_t)cn[t]] - box[0]) / hx;
+        sy[t] = -1.0 + 2.0 * (xy[2 * (int64_t)cn[t * Q] + 1] - box[2]) / hy;
+    }
+    __syncthreads();
+    // Lagrange basis function a (and its derivative) at quadrature point q
+    if (t < 2 * Q * Q) {
+        const int dir = t / (Q * Q), q = (t % (Q * Q)) / Q, a = t % Q;
+        const double* s = dir ? sy : sx;
+        const double z = gp[q];
+        double v = 1.0, d = 0.0;
+        for (int b = 0; b < Q; ++b) {
+            if (b == a) continue;
+            const double f = (z - s[b]) / (s[a] - s[b]);
+            d = d * f + v / (s[a] - s[b]);
+            v *= f;
+        }
+        if (dir) {
+            Ly[q][a] = v;
+            Dy[q][a] = d;
+        } else {
+            Lx[q][a] = v;
+            Dx[q][a] = d;
+        }
+    }
+    __syncthreads();
+    // 1-D element matrices (reference interval [-1, 1] of length h / 2 per unit)
+    if (t < 2 * Q * Q) {
+        const int dir = t / (Q * Q), a = (t % (Q * Q)) / Q, c = t % Q;
+        const double h = dir ? hy : hx;
+        double kk = 0.0, mm = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            if (dir) {
+                kk += gw[q] * Dy[q][a] * Dy[q][c];
+                mm += gw[q] * Ly[q][a] * Ly[q][c];
+            } else {
+                kk += gw[q] * Dx[q][a] * Dx[q][c];
+                mm += gw[q] * Lx[q][a] * Lx[q][c];
+            }
+        }
+        if (dir) {
+            ky[a][c] = (2.0 / h) * kk;
+            my[a][c] = 0.5 * h * mm;
+        } else {
+            kx[a][c] = (2.0 / h) * kk;
+            mx[a][c] = 0.5 * h * mm;
+        }
+    }
+    __syncthreads();
+    for (int idx = t; idx < NV * NV; idx += 256) {
+        const int i = idx % NV, j = idx / NV;
+        const int64_t gi = g[i], gj = g[j];
+        if (gi < 0 || gj < 0) continue;
+        const int a = i % Q, b = i / Q, c = j % Q, d = j / Q;
+        K[gi + gj * ld] += kx[a][c] * my[b][d] + mx[a][c] * ky[b][d];
+        M[gi + gj * ld] += mx[a][c] * my[b][d];
+    }
+}
+
 __global__ void csr_gather_kernel(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
                                   const double* __restrict__ K, const double* __restrict__ M, int64_t ld,
                                   double* kval, double* mval) {
@@ -99,10 +210,19 @@ hipError_t fl_assemble_launch(hipStream_t s, int elem, const double* xy, const i
         int64_t e0 = color_start[c], e1 = color_start[c + 1];
         if (e1 <= e0) continue;
         unsigned blocks = (unsigned)FL_DIV_UP(e1 - e0, 128);
-        if (elem == 4)
-            assemble_kernel<4><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, ld, K, M);
-        else
-            assemble_kernel<3><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, ld, K, M);
+        const unsigned eb = (unsigned)(e1 - e0);
+        switch (elem) {
+            case 3: assemble_kernel<3><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, ld, K, M); break;
+            case 4: assemble_kernel<4><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, ld, K, M); break;
+            case 9: assemble_qp_kernel<2><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            case 16: assemble_qp_kernel<3><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            case 25: assemble_qp_kernel<4><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            case 36: assemble_qp_kernel<5><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            case 49: assemble_qp_kernel<6><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            case 64: assemble_qp_kernel<7><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            case 81: assemble_qp_kernel<8><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            default: return hipErrorInvalidValue;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -53,6 +53,10 @@ struct fl_op {
     // application workspaces, one per stream, so calls queued on different
     // streams never share intermediate buffers
     std::vector<OpWs> ws;
+    // bandwidth-reducing numbering of the pattern for eigenvalue counting
+    // (new index of each old one; device), and the bandwidth under it
+    int32_t* inert_pinv = nullptr;
+    int64_t inert_bw = -1;
     // captured application graphs (fl_apply_graph)
     std::vector<ApplyGraph*> graphs;
     uint64_t graph_clock = 0;

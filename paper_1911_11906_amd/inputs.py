@@ -31,7 +31,7 @@ def rng_for(tag: int, *extra: int) -> np.random.Generator:
 
 @dataclass
 class Mesh:
-    elem: int                 # Q1 or P1
+    elem: int                 # nodes per element: P1 (3), Q1 (4) or (p+1)^2 for order p
     xy: np.ndarray            # (n_nodes, 2) float64
     conn: np.ndarray          # (n_elem, elem) int32, CCW
     dirichlet: np.ndarray     # (n_nodes,) uint8, 1 = boundary node (eliminated)
@@ -86,6 +86,39 @@ def q1_rectangle(mx: int, my: int, x0: float = 0.0, y0: float = 0.0,
     bnd = ((ii == 0) | (ii == nx - 1) | (jj == 0) | (jj == ny - 1)).ravel()
     return Mesh(Q1, xy, conn, bnd.astype(np.uint8), name=f"q1_rect_{mx}x{my}",
                 meta={"mx": mx, "my": my, "lx": lx, "ly": ly})
+
+
+def gll_points(p: int) -> np.ndarray:
+    """The p + 1 Gauss-Lobatto-Legendre points on [-1, 1] (the endpoints and
+    the roots of P_p'), ascending: the node positions of an order-p element
+    along each direction."""
+    if p == 1:
+        return np.array([-1.0, 1.0])
+    inner = np.polynomial.legendre.Legendre.basis(p).deriv().roots()
+    return np.concatenate([[-1.0], np.sort(inner.real), [1.0]])
+
+
+def qp_rectangle(ex: int, ey: int, p: int, lx: float = 1.0, ly: float = 1.0) -> Mesh:
+    """ex x ey elements of order p (2 <= p <= 8) on [0,lx]x[0,ly]: each element
+    carries the (p+1) x (p+1) tensor lattice of Gauss-Lobatto-Legendre points
+    mapped to it, numbered lexicographically (a + (p+1) b, a along x);
+    elements share their edge nodes.  Global nodes: the (ex p + 1) x (ey p + 1)
+    lattice, x fastest; the boundary lattice nodes are Dirichlet."""
+    if not 2 <= p <= 8:
+        raise ValueError("order must be in [2, 8]")
+    g = 0.5 * (gll_points(p) + 1.0)                     # on [0, 1]
+    xs = np.concatenate([(i + g[:-1]) * lx / ex for i in range(ex)] + [[lx]])
+    ys = np.concatenate([(j + g[:-1]) * ly / ey for j in range(ey)] + [[ly]])
+    nx, ny = xs.size, ys.size
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float64)
+    a = np.arange(p + 1)
+    loc = (a[None, :] + nx * a[:, None]).ravel()          # local (a, b) -> offset, a fastest
+    conn = np.array([loc + (i * p) + nx * (j * p) for j in range(ey) for i in range(ex)], dtype=np.int32)
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    bnd = ((ii == 0) | (ii == nx - 1) | (jj == 0) | (jj == ny - 1)).ravel()
+    return Mesh((p + 1) ** 2, xy, conn, bnd.astype(np.uint8), name=f"q{p}_rect_{ex}x{ey}",
+                meta={"ex": ex, "ey": ey, "p": p, "lx": lx, "ly": ly})
 
 
 def q1_lshape(m: int) -> Mesh:
