@@ -236,6 +236,19 @@ int fl_grad_apply(fl_op *op, int64_t nb, const double *F, int64_t ldf, const dou
 int fl_apply_graph(fl_op *op, int64_t nf, const double *F, int64_t ldf, int64_t na, const double *alpha,
                    int paired, double *U, int64_t ldu);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same result as
+ * fl_apply_fractional, with every intermediate (G, C, W and the split-k
+ * partial sums of V^T G) in one fixed device array of the library of
+ * FL_NOALLOC_SCRATCH_BYTES per device, held until the process ends.  Nothing
+ * is allocated and nothing synchronises.  FL_EINVAL when (2 nf + na) n
+ * doubles exceed the array (checked before any device work).  All calls on
+ * one device share its array: calls that overlap on a device (different
+ * streams or threads) race; calls on one stream are ordered.  Asynchronous. */
+#define FL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fl_apply_fractional_noalloc(fl_op *op, int64_t nf, const double *F, int64_t ldf, int64_t na, const double *alpha,
+                                int paired, double *U, int64_t ldu);
+
 /* ---- fractional diffusion (Section "Method", equations model_diffusion and
  * diffusion_solution; the exact solution of Section "Accuracy", equations
  * diffusion_ics and diffusion_sols) ------------------------------------------

@@ -29,7 +29,7 @@ EXPORTS = [
     "fl_assemble", "fl_op_from_dense", "fl_op_n", "fl_op_matrices", "fl_op_destroy",
     "fl_eigensolve", "fl_eigensolve_batched", "fl_eigenpairs", "fl_op_set_eigenpairs",
     "fl_op_save", "fl_op_load", "fl_op_info", "fl_inertia_count",
-    "fl_apply_fractional", "fl_grad_apply", "fl_apply_graph", "fl_apply_diffusion", "fl_grad_diffusion",
+    "fl_apply_fractional", "fl_apply_fractional_noalloc", "fl_grad_apply", "fl_apply_graph", "fl_apply_diffusion", "fl_grad_diffusion",
     "fl_gemm_tune", "fl_gemm_tuning_set", "fl_gemm_tuning_count", "fl_gemm_tuning_get", "fl_gemm_tuning_clear",
     "fl_dgemm", "fl_dpotrf", "fl_dsygst", "fl_dstedc", "fl_dsytrd_2stage", "fl_dsyevd",
     "fl_kernel_timing", "fl_kernel_time", "fl_measure_peaks",
@@ -105,6 +105,7 @@ def load(path: str = SO_PATH):
         "fl_apply_fractional": ([P, i64, P, i64, i64, P, i32, P, i64], i32),
         "fl_grad_apply": ([P, i64, P, i64, P, P, i64, P, i64, P], i32),
         "fl_apply_graph": ([P, i64, P, i64, i64, P, i32, P, i64], i32),
+        "fl_apply_fractional_noalloc": ([P, i64, P, i64, i64, P, i32, P, i64], i32),
         "fl_apply_diffusion": ([P, i64, P, i64, i64, P, P, P, i32, P, i64], i32),
         "fl_grad_diffusion": ([P, i64, P, i64, P, P, P, P, i64, P, i64, P, P, P], i32),
         "fl_gemm_tune": ([P, i32, i32, i32, i64, i64, i64, i32, ctypes.POINTER(FlGemmChoice)], i32),
