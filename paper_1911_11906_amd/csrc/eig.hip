@@ -107,50 +107,100 @@ int grid_for_sb2st(int64_t n, int b) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(useful, cus));
 }
 
-}  // namespace
+// The two-stage tridiagonalisation shared by every eigensolve entry point:
+// band reduction (FP64 or FP32) -> band (FP64) -> bulge chase (FP64), and the
+// two back-transforms Z := Q1 Q2 Z in the precision of Z.  Owns every buffer
+// of the sequence; V1 (the band reduction's block reflectors) is kept in the
+// precision of the back-transforms that will read it (FP64 reflectors are
+// rounded to FP32 when the back-transforms run in FP32).
+struct TwoStage {
+    fl_ctx* ctx;
+    hipStream_t s;
+    int64_t n;
+    int b;
+    int64_t ldab, np, maxt, nsw;
+    DevBuf bAB, bV2, btau2, bprog, be, bT2, bcnt;
+    DevBuf bV1, bT1;  // reflectors for the back-transforms (FP64 or FP32)
+    bool q_fp32 = false;
+    double* AB = nullptr;
+    int* abort_flag = nullptr;
 
-// Two-stage tridiagonalisation + D&C + back-transforms of the symmetric A
-// (full storage, destroyed).  w (n) ascending, Z (n x n, ld ldz).
-int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* w, double* Z, int64_t ldz,
-                    fl_eig_info* info, int leaf, StageTimer* tm_ext = nullptr);
-
-int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* w, double* Z, int64_t ldz,
-                    fl_eig_info* info, int leaf, StageTimer* tm) {
-    hipStream_t s = ctx->stream;
-    const int b = clamp_band(n, band);
-    const int64_t ldab = 2 * b + 1;
-    const int64_t np = std::max<int64_t>(1, fl_sy2sb_panels(n, b));
-    const int64_t maxt = fl_sb2st_maxt(n, b);
-    const int64_t nsw = std::max<int64_t>(1, n - 2);
-    DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
-    double* ABp = band_buffer(ctx, sizeof(double) * ldab * n);
-    if (!ABp) {
-        FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
-        ABp = bAB.as<double>();
+    TwoStage(fl_ctx* c, int64_t n_, int band) : ctx(c), s(c->stream), n(n_), b(clamp_band(n_, band)) {
+        ldab = 2 * (int64_t)b + 1;
+        np = std::max<int64_t>(1, fl_sy2sb_panels(n, b));
+        maxt = fl_sb2st_maxt(n, b);
+        nsw = std::max<int64_t>(1, n - 2);
     }
-    FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
-    FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(double) * (size_t)n * n, s));  // Q1 reads above each panel
-    FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
-    FL_HIP(ctx, btau1.alloc(sizeof(double) * (n + b)));
-    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), fl_q1_work_elems(n, b, n))));
-    FL_HIP(ctx, bpart.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
-    FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
-    FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
-    FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
-    FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
-    FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
-    double* e = be.as<double>();
-    int* abort_flag = bprog.as<int>() + 2 * n + 1;
-    FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
+    double* e() const { return be.as<double>(); }
 
-    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
-    FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, bV1.as<double>(), n, bT1.as<double>(), btau1.as<double>(),
-                         bwork.as<double>(), bpart.as<double>(), bcnt.as<unsigned>(), abort_flag));
-    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, ABp, ldab));
-    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
-    FL_HIP(ctx, fl_sb2st(s, n, b, ABp, ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
-                         grid_for_sb2st(n, b), abort_flag));
-    {
+    // common buffers; q_in_fp32: the back-transforms will run in FP32
+    int init(bool q_in_fp32) {
+        q_fp32 = q_in_fp32;
+        AB = band_buffer(ctx, sizeof(double) * ldab * n);
+        if (!AB) {
+            FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
+            AB = bAB.as<double>();
+        }
+        const size_t esz = q_fp32 ? sizeof(float) : sizeof(double);
+        FL_HIP(ctx, bV1.alloc(esz * (size_t)n * n));
+        FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, esz * (size_t)n * n, s));  // Q1 reads above each panel
+        FL_HIP(ctx, bT1.alloc(esz * np * b * b));
+        FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
+        FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
+        FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
+        FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
+        FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
+        abort_flag = bprog.as<int>() + 2 * n + 1;
+        FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
+        return FL_OK;
+    }
+
+    // A (full symmetric storage, FP64, destroyed) -> band; the reflectors are
+    // kept for the back-transforms (rounded to FP32 if they run in FP32)
+    int reduce(double* A, int64_t lda) {
+        DevBuf tau, work, part, V1d, T1d;
+        FL_HIP(ctx, tau.alloc(sizeof(double) * (n + b)));
+        FL_HIP(ctx, work.alloc(sizeof(double) * fl_sy2sb_work_elems(n, b)));
+        FL_HIP(ctx, part.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
+        double* V1 = bV1.as<double>();
+        double* T1 = bT1.as<double>();
+        if (q_fp32) {
+            FL_HIP(ctx, V1d.alloc(sizeof(double) * (size_t)n * n));
+            FL_HIP(ctx, hipMemsetAsync(V1d.p, 0, sizeof(double) * (size_t)n * n, s));
+            FL_HIP(ctx, T1d.alloc(sizeof(double) * np * b * b));
+            V1 = V1d.as<double>();
+            T1 = T1d.as<double>();
+        }
+        FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, V1, n, T1, tau.as<double>(), work.as<double>(), part.as<double>(),
+                             bcnt.as<unsigned>(), abort_flag));
+        FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, AB, ldab));
+        if (q_fp32) {
+            FL_HIP(ctx, fl_d2s(s, n, n, V1, n, bV1.as<float>(), n));
+            FL_HIP(ctx, fl_d2s(s, np * b, b, T1, np * b, bT1.as<float>(), np * b));
+        }
+        FL_HIP(ctx, hipStreamSynchronize(s));  // the scoped buffers are released at return
+        return FL_OK;
+    }
+
+    // A (full symmetric storage, FP32, destroyed) -> band; FP32 reflectors
+    int reduce(float* A, int64_t lda) {
+        if (!q_fp32) return fl_fail(ctx, FL_EINVAL, "two-stage: an FP32 band reduction needs FP32 back-transforms");
+        DevBuf tau, work, part;
+        FL_HIP(ctx, tau.alloc(sizeof(float) * (n + b)));
+        FL_HIP(ctx, work.alloc(sizeof(float) * fl_sy2sb_work_elems(n, b)));
+        FL_HIP(ctx, part.alloc(sizeof(float) * fl_sy2sb_part_elems(n)));
+        FL_HIP(ctx, fl_ssy2sb(s, n, b, A, lda, bV1.as<float>(), n, bT1.as<float>(), tau.as<float>(),
+                              work.as<float>(), part.as<float>(), bcnt.as<unsigned>(), abort_flag));
+        FL_HIP(ctx, fl_extract_band_f(s, n, b, A, lda, AB, ldab));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        return FL_OK;
+    }
+
+    // band -> d (n), e() (n - 1), reflectors V2; FL_ENOCONV if a cooperative
+    // wait of the band reduction or of the bulge chase was abandoned
+    int chase(double* d, fl_eig_info* info) {
+        FL_HIP(ctx, fl_sb2st(s, n, b, AB, ldab, d, e(), bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
+                             grid_for_sb2st(n, b), abort_flag));
         int ab = 0;
         FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
         FL_HIP(ctx, hipStreamSynchronize(s));
@@ -158,20 +208,61 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
             if (info) info->index = FL_STAGE_SB2ST;
             return fl_fail(ctx, FL_ENOCONV, "tridiagonalisation: a cooperative wait was abandoned");
         }
+        return FL_OK;
     }
+
+    int apply_q2(double* Z, int64_t ldz, int64_t ncols) {
+        FL_HIP(ctx, bT2.alloc(sizeof(double) * fl_q2_t_elems(n, b, maxt)));
+        FL_HIP(ctx, fl_q2_apply(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<double>(), Z, ldz, ncols));
+        return FL_OK;
+    }
+    int apply_q2(float* Z, int64_t ldz, int64_t ncols) {
+        FL_HIP(ctx, bT2.alloc(sizeof(float) * fl_q2_t_elems(n, b, maxt)));
+        FL_HIP(ctx, fl_q2_apply_f(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<float>(), Z, ldz, ncols));
+        return FL_OK;
+    }
+    int apply_q1(double* Z, int64_t ldz, int64_t ncols) {
+        if (q_fp32) return fl_fail(ctx, FL_EINVAL, "two-stage: FP32 reflectors applied to FP64 vectors");
+        DevBuf work;
+        FL_HIP(ctx, work.alloc(sizeof(double) * fl_q1_work_elems(n, b, ncols)));
+        FL_HIP(ctx, fl_q1_apply(s, n, b, bV1.as<double>(), n, bT1.as<double>(), Z, ldz, ncols, work.as<double>()));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        return FL_OK;
+    }
+    int apply_q1(float* Z, int64_t ldz, int64_t ncols) {
+        if (!q_fp32) return fl_fail(ctx, FL_EINVAL, "two-stage: FP64 reflectors applied to FP32 vectors");
+        DevBuf work;
+        FL_HIP(ctx, work.alloc(sizeof(float) * fl_q1_work_elems(n, b, ncols)));
+        FL_HIP(ctx, fl_q1_apply_f(s, n, b, bV1.as<float>(), n, bT1.as<float>(), Z, ldz, ncols, work.as<float>()));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        return FL_OK;
+    }
+};
+
+}  // namespace
+
+// Two-stage tridiagonalisation + D&C + back-transforms of the symmetric A
+// (full storage, destroyed).  w (n) ascending, Z (n x n, ld ldz).
+int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, double* w, double* Z, int64_t ldz,
+                    fl_eig_info* info, int leaf, StageTimer* tm) {
+    TwoStage ts(ctx, n, band);
+    int rc;
+    if ((rc = ts.init(false))) return rc;
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
+    if ((rc = ts.reduce(A, lda))) return rc;
+    if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
+    if ((rc = ts.chase(w, info))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_STEDC));
-    int rc = fl_stedc_device(ctx, n, w, e, Z, ldz, leaf);
-    if (rc) {
+    if ((rc = fl_stedc_device(ctx, n, w, ts.e(), Z, ldz, leaf))) {
         if (info) info->index = FL_STAGE_STEDC;
         return rc;
     }
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q2));
-    FL_HIP(ctx, bT2.alloc(sizeof(double) * fl_q2_t_elems(n, b, maxt)));
-    FL_HIP(ctx, fl_q2_apply(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<double>(), Z, ldz, n));
+    if ((rc = ts.apply_q2(Z, ldz, n))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q1));
-    FL_HIP(ctx, fl_q1_apply(s, n, b, bV1.as<double>(), n, bT1.as<double>(), Z, ldz, n, bwork.as<double>()));
+    if ((rc = ts.apply_q1(Z, ldz, n))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(-1));
-    FL_HIP(ctx, hipStreamSynchronize(s));
+    FL_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return FL_OK;
 }
 
@@ -181,82 +272,33 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
 int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int band, int fp32_band, double* w,
                           double* Z, int64_t ldz, fl_eig_info* info, int leaf, StageTimer* tm) {
     hipStream_t s = ctx->stream;
-    const int b = clamp_band(n, band);
-    const int64_t ldab = 2 * b + 1;
-    const int64_t np = std::max<int64_t>(1, fl_sy2sb_panels(n, b));
-    const int64_t maxt = fl_sb2st_maxt(n, b);
-    const int64_t nsw = std::max<int64_t>(1, n - 2);
-    DevBuf bA, bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
+    TwoStage ts(ctx, n, band);
+    DevBuf bA;  // FP32 copy of C for an FP32 band reduction, then the FP32 vectors
     FL_HIP(ctx, bA.alloc(sizeof(float) * (size_t)n * n));
-    double* ABp = band_buffer(ctx, sizeof(double) * ldab * n);
-    if (!ABp) {
-        FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
-        ABp = bAB.as<double>();
-    }
-    FL_HIP(ctx, bV1.alloc(sizeof(float) * (size_t)n * n));
-    FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(float) * (size_t)n * n, s));  // Q1 reads above each panel
-    FL_HIP(ctx, bT1.alloc(sizeof(float) * np * b * b));
-    FL_HIP(ctx, btau1.alloc(sizeof(float) * (n + b)));
-    FL_HIP(ctx, bwork.alloc(sizeof(float) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), fl_q1_work_elems(n, b, n))));
-    FL_HIP(ctx, bpart.alloc(sizeof(float) * fl_sy2sb_part_elems(n)));
-    FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
-    FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
-    FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
-    FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
-    FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
-    double* e = be.as<double>();
-    float* A = bA.as<float>();
-    int* abort_flag = bprog.as<int>() + 2 * n + 1;
-    FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
-
+    float* Af = bA.as<float>();
+    int rc;
+    if ((rc = ts.init(true))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
     if (fp32_band) {
-        FL_HIP(ctx, fl_d2s(s, n, n, C, ldc, A, n));
-        FL_HIP(ctx, fl_ssy2sb(s, n, b, A, n, bV1.as<float>(), n, bT1.as<float>(), btau1.as<float>(),
-                              bwork.as<float>(), bpart.as<float>(), bcnt.as<unsigned>(), abort_flag));
-        FL_HIP(ctx, fl_extract_band_f(s, n, b, A, n, ABp, ldab));
+        FL_HIP(ctx, fl_d2s(s, n, n, C, ldc, Af, n));
+        rc = ts.reduce(Af, n);
     } else {
-        // FP64 band reduction; its block reflectors are rounded to FP32 for Q1
-        DevBuf bV1d, bT1d, btau1d, bworkd, bpartd;
-        FL_HIP(ctx, bV1d.alloc(sizeof(double) * (size_t)n * n));
-        FL_HIP(ctx, hipMemsetAsync(bV1d.p, 0, sizeof(double) * (size_t)n * n, s));
-        FL_HIP(ctx, bT1d.alloc(sizeof(double) * np * b * b));
-        FL_HIP(ctx, btau1d.alloc(sizeof(double) * (n + b)));
-        FL_HIP(ctx, bworkd.alloc(sizeof(double) * fl_sy2sb_work_elems(n, b)));
-        FL_HIP(ctx, bpartd.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
-        FL_HIP(ctx, fl_sy2sb(s, n, b, C, ldc, bV1d.as<double>(), n, bT1d.as<double>(), btau1d.as<double>(),
-                             bworkd.as<double>(), bpartd.as<double>(), bcnt.as<unsigned>(), abort_flag));
-        FL_HIP(ctx, fl_extract_band(s, n, b, C, ldc, ABp, ldab));
-        FL_HIP(ctx, fl_d2s(s, n, n, bV1d.as<double>(), n, bV1.as<float>(), n));
-        FL_HIP(ctx, fl_d2s(s, np * b, b, bT1d.as<double>(), np * b, bT1.as<float>(), np * b));
-        FL_HIP(ctx, hipStreamSynchronize(s));  // the FP64 buffers are released at scope exit
+        rc = ts.reduce(C, ldc);
     }
+    if (rc) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
-    FL_HIP(ctx, fl_sb2st(s, n, b, ABp, ldab, w, e, bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
-                         grid_for_sb2st(n, b), abort_flag));
-    {
-        int ab = 0;
-        FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-        FL_HIP(ctx, hipStreamSynchronize(s));
-        if (ab) {
-            if (info) info->index = FL_STAGE_SB2ST;
-            return fl_fail(ctx, FL_ENOCONV, "tridiagonalisation: a cooperative wait was abandoned");
-        }
-    }
+    if ((rc = ts.chase(w, info))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_STEDC));
-    int rc = fl_stedc_device(ctx, n, w, e, Z, ldz, leaf);
-    if (rc) {
+    if ((rc = fl_stedc_device(ctx, n, w, ts.e(), Z, ldz, leaf))) {
         if (info) info->index = FL_STAGE_STEDC;
         return rc;
     }
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q2));
-    float* Zf = A;  // the reduced matrix is no longer needed
-    FL_HIP(ctx, fl_d2s(s, n, n, Z, ldz, Zf, n));
-    FL_HIP(ctx, bT2.alloc(sizeof(float) * fl_q2_t_elems(n, b, maxt)));
-    FL_HIP(ctx, fl_q2_apply_f(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<float>(), Zf, n, n));
+    FL_HIP(ctx, fl_d2s(s, n, n, Z, ldz, Af, n));  // the reduced matrix is no longer needed
+    if ((rc = ts.apply_q2(Af, n, n))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_Q1));
-    FL_HIP(ctx, fl_q1_apply_f(s, n, b, bV1.as<float>(), n, bT1.as<float>(), Zf, n, n, bwork.as<float>()));
-    FL_HIP(ctx, fl_s2d(s, n, n, Zf, n, Z, ldz));
+    if ((rc = ts.apply_q1(Af, n, n))) return rc;
+    FL_HIP(ctx, fl_s2d(s, n, n, Af, n, Z, ldz));
     if (tm) FL_HIP(ctx, tm->mark(-1));
     FL_HIP(ctx, hipStreamSynchronize(s));
     return FL_OK;
@@ -268,6 +310,8 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     if (!op) return FL_EINVAL;
     fl_ctx* ctx = op->ctx;
     if (precision != FL_FP64 && precision != FL_MIXED) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve: bad precision");
+    if (!op->K || !op->M)
+        return fl_fail(ctx, FL_ESTATE, "fl_eigensolve: the operator holds no dense pencil (assembled sparse)");
     fl_eig_info local_info{};
     if (!info) info = &local_info;  // the refinement statistics are kept with the operator
     *info = fl_eig_info{};
@@ -432,47 +476,13 @@ int fl_dsytrd_2stage(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, d
     if (n <= 0 || !A || !d || !e || lda < n || (Q && ldq < n)) return fl_fail(ctx, FL_EINVAL, "fl_dsytrd_2stage: bad arguments");
     FL_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const int b = clamp_band(n, band);
-    const int64_t ldab = 2 * b + 1;
-    const int64_t np = std::max<int64_t>(1, fl_sy2sb_panels(n, b));
-    const int64_t maxt = fl_sb2st_maxt(n, b);
-    const int64_t nsw = std::max<int64_t>(1, n - 2);
-    DevBuf bAB, bV1, bT1, btau1, bwork, bpart, bcnt, bV2, btau2, bprog, bT2, be;
-    double* ABp = band_buffer(ctx, sizeof(double) * ldab * n);
-    if (!ABp) {
-        FL_HIP(ctx, bAB.alloc(sizeof(double) * ldab * n));
-        ABp = bAB.as<double>();
-    }
-    FL_HIP(ctx, bV1.alloc(sizeof(double) * (size_t)n * n));
-    FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, sizeof(double) * (size_t)n * n, s));  // Q1 reads above each panel
-    FL_HIP(ctx, bT1.alloc(sizeof(double) * np * b * b));
-    FL_HIP(ctx, btau1.alloc(sizeof(double) * (n + b)));
-    FL_HIP(ctx, bwork.alloc(sizeof(double) * std::max<int64_t>(fl_sy2sb_work_elems(n, b), fl_q1_work_elems(n, b, n))));
-    FL_HIP(ctx, bpart.alloc(sizeof(double) * fl_sy2sb_part_elems(n)));
-    FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
-    FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
-    FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
-    FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
-    FL_HIP(ctx, be.alloc(sizeof(double) * (n + 1)));
-    int* abort_flag = bprog.as<int>() + 2 * n + 1;
-    FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
-    FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, bV1.as<double>(), n, bT1.as<double>(), btau1.as<double>(), bwork.as<double>(),
-                         bpart.as<double>(), bcnt.as<unsigned>(), abort_flag));
-    FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, ABp, ldab));
-    FL_HIP(ctx, fl_sb2st(s, n, b, ABp, ldab, d, be.as<double>(), bV2.as<double>(), btau2.as<double>(),
-                         bprog.as<int>(), grid_for_sb2st(n, b), abort_flag));
-    {
-        int ab = 0;
-        FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-        FL_HIP(ctx, hipStreamSynchronize(s));
-        if (ab) return fl_fail(ctx, FL_ENOCONV, "tridiagonalisation: a cooperative wait was abandoned");
-    }
-    if (n > 1) FL_HIP(ctx, hipMemcpyAsync(e, be.p, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, s));
+    TwoStage ts(ctx, n, band);
+    int rc;
+    if ((rc = ts.init(false)) || (rc = ts.reduce(A, lda)) || (rc = ts.chase(d, nullptr))) return rc;
+    if (n > 1) FL_HIP(ctx, hipMemcpyAsync(e, ts.e(), sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, s));
     if (Q) {
         FL_HIP(ctx, fl_set_identity(s, n, Q, ldq));
-        FL_HIP(ctx, bT2.alloc(sizeof(double) * fl_q2_t_elems(n, b, maxt)));
-        FL_HIP(ctx, fl_q2_apply(s, n, b, bV2.as<double>(), btau2.as<double>(), maxt, bT2.as<double>(), Q, ldq, n));
-        FL_HIP(ctx, fl_q1_apply(s, n, b, bV1.as<double>(), n, bT1.as<double>(), Q, ldq, n, bwork.as<double>()));
+        if ((rc = ts.apply_q2(Q, ldq, n)) || (rc = ts.apply_q1(Q, ldq, n))) return rc;
     }
     FL_HIP(ctx, hipStreamSynchronize(s));
     return FL_OK;
