@@ -132,6 +132,15 @@ const char *fl_last_error(const fl_ctx *ctx);
 int fl_assemble(fl_ctx *ctx, int elem, int64_t n_nodes, const double *xy, int64_t n_elem,
                 const int32_t *conn, const uint8_t *dirichlet, fl_op **out, int64_t *n_dof,
                 int64_t *dof_of_node);
+/* Same mesh input, for pencils too large for dense storage: the element
+ * contributions go straight into the values of the CSR pattern (bitwise the
+ * CSR copies fl_assemble makes), and no dense K or M is kept.  Such an
+ * operator serves fl_inertia_count, fl_eigensolve_interval, fl_op_save and,
+ * once eigenpairs are installed, the applications; fl_eigensolve,
+ * fl_eigensolve_batched and fl_op_matrices refuse it with FL_ESTATE. */
+int fl_assemble_sparse(fl_ctx *ctx, int elem, int64_t n_nodes, const double *xy, int64_t n_elem,
+                       const int32_t *conn, const uint8_t *dirichlet, fl_op **out, int64_t *n_dof,
+                       int64_t *dof_of_node);
 /* Wrap an existing symmetric pencil.  K, M: n x n, leading dimension ld,
  * host (on_device = 0) or device (1).  FL_EINVAL for NaN/Inf entries. */
 int fl_op_from_dense(fl_ctx *ctx, int64_t n, const double *K, const double *M, int64_t ld, int on_device,
@@ -174,12 +183,14 @@ int fl_op_set_eigenpairs(fl_op *op, const double *theta, const double *V, int64_
 
 /* ---- persistence: the basis is computed once and reused for every later
  * forcing (Section "Method", the paragraph after the equation for v) --------
- * fl_op_save writes the pencil (its CSR pattern and the K and M values), and
+ * fl_op_save writes the pencil (its CSR pattern and the K and M values, and
+ * whether the operator keeps a dense copy), and
  * theta, V and how they were obtained (precision, refinement steps, last
  * refinement residual) when present, with a SHA-256 of the pencil and one of
  * the whole file; the file is written under path + ".part" and renamed when
  * complete.  fl_op_load reads such a file into a new operator of ctx's device
- * (dense K and M rebuilt from the pattern), after checking the magic, the
+ * (dense K and M rebuilt from the pattern unless the saved operator had
+ * none), after checking the magic, the
  * version, the sizes, the pattern's indices and the file checksum: FL_EIO on
  * any failure (nothing is created).  Both synchronous. */
 int fl_op_save(const fl_op *op, const char *path);
@@ -200,8 +211,35 @@ int fl_op_info(const fl_op *op, int64_t *n, int *has_eig, int *precision, int *r
  * sigma: host, nshift shifts; counts: host, nshift results (-1 where a pivot
  * was exactly zero); bandwidth (host, may be NULL) receives the bandwidth
  * used.  FL_EINVAL for a non-finite shift, an operator without a sparse
- * pattern, or a bandwidth above 255.  Needs no eigenpairs.  Synchronous. */
+ * pattern, or a bandwidth above 511.  Needs no eigenpairs.  Synchronous. */
 int fl_inertia_count(fl_op *op, int64_t nshift, const double *sigma, int64_t *counts, int64_t *bandwidth);
+
+/* ---- spectrum slicing (Sections "Solving for all eigenpairs in an
+ * interval", "Partitioning" (greedy partitioning) and "Post-processing") ---
+ * All eigenpairs with lo <= theta < hi, for pencils of any size held in
+ * sparse form (see fl_assemble_sparse): the interval's count from inertia
+ * counts; greedy partitioning into slices of at most max_per_slice
+ * (<= 500) eigenvalues (7 rounds of batched counts below every split
+ * point, splits moved to equal shares of the piecewise-linear cumulative
+ * count, the best partition kept, overloaded slices halved); per slice one
+ * banded LDL^T of K - sigma_s M at its midpoint and shift-invert subspace
+ * iteration with 2 m_s + 16 vectors and Rayleigh-Ritz on the batched
+ * eigensolver, all slices together, until each slice holds exactly its m_s
+ * Ritz pairs with relative residuals ||K x - theta M x|| / (max(theta, b_s)
+ * ||M x||) below tol (b_s: the slice's upper end; the m_s eigenvalues inside
+ * are known from the counts), then one Newton-Schulz step V := V (3 I -
+ * V^T M V) / 2 over all returned vectors.  theta (device, cap) receives the eigenvalues ascending and V
+ * (device, n x cap, ld ldv) M-orthonormal eigenvectors.  info (may be NULL)
+ * receives the count (also when it exceeds cap: then FL_EINVAL), the number
+ * of slices, the largest slice load, partitioning rounds, iterations and the
+ * largest residual.  FL_ENOCONV if the iteration did not converge within
+ * 200 steps.  Synchronous. */
+typedef struct fl_slice_info {
+    int64_t count, slices, max_load, partition_rounds, iterations;
+    double max_residual;
+} fl_slice_info;
+int fl_eigensolve_interval(fl_op *op, double lo, double hi, int64_t max_per_slice, double tol, int64_t cap,
+                           double *theta, double *V, int64_t ldv, fl_slice_info *info);
 
 /* ---- spectral application (the equation for v, Section "Method") ---------
  * F: device, n x nf (ld ldf).  alpha: host, na orders in [0, 2].

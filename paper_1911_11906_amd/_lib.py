@@ -26,9 +26,9 @@ FL_GV_AUTO, FL_GV_SQUARE16, FL_GV_SQUARE32, FL_GV_THIN = 0, 1, 2, 3
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTS = [
     "fl_ctx_create", "fl_ctx_set_stream", "fl_ctx_destroy", "fl_last_error",
-    "fl_assemble", "fl_op_from_dense", "fl_op_n", "fl_op_matrices", "fl_op_destroy",
+    "fl_assemble", "fl_assemble_sparse", "fl_op_from_dense", "fl_op_n", "fl_op_matrices", "fl_op_destroy",
     "fl_eigensolve", "fl_eigensolve_batched", "fl_eigenpairs", "fl_op_set_eigenpairs",
-    "fl_op_save", "fl_op_load", "fl_op_info", "fl_inertia_count",
+    "fl_op_save", "fl_op_load", "fl_op_info", "fl_inertia_count", "fl_eigensolve_interval",
     "fl_apply_fractional", "fl_apply_fractional_noalloc", "fl_grad_apply", "fl_apply_graph", "fl_apply_diffusion", "fl_grad_diffusion",
     "fl_gemm_tune", "fl_gemm_tuning_set", "fl_gemm_tuning_count", "fl_gemm_tuning_get", "fl_gemm_tuning_clear",
     "fl_dgemm", "fl_dpotrf", "fl_dsygst", "fl_dstedc", "fl_dsytrd_2stage", "fl_dsyevd",
@@ -52,6 +52,15 @@ class FlEigInfo(ctypes.Structure):
                 "refine_resid": self.refine_resid, "total_ms": self.total_ms,
                 "flops_nominal": self.flops_nominal,
                 "stage_ms": {s: self.stage_ms[i] for i, s in enumerate(STAGES)}}
+
+
+class FlSliceInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("slices", ctypes.c_int64), ("max_load", ctypes.c_int64),
+                ("partition_rounds", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("max_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class FlGemmChoice(ctypes.Structure):
@@ -89,6 +98,7 @@ def load(path: str = SO_PATH):
         "fl_ctx_destroy": ([P], None),
         "fl_last_error": ([P], ctypes.c_char_p),
         "fl_assemble": ([P, i32, i64, P, i64, P, P, pp, ctypes.POINTER(i64), P], i32),
+        "fl_assemble_sparse": ([P, i32, i64, P, i64, P, P, pp, ctypes.POINTER(i64), P], i32),
         "fl_op_from_dense": ([P, i64, P, P, i64, i32, pp], i32),
         "fl_op_n": ([P], i64),
         "fl_op_matrices": ([P, P, P, i64, i32], i32),
@@ -98,6 +108,7 @@ def load(path: str = SO_PATH):
         "fl_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_op_set_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_inertia_count": ([P, i64, P, P, ctypes.POINTER(i64)], i32),
+        "fl_eigensolve_interval": ([P, dbl, dbl, i64, dbl, i64, P, P, i64, ctypes.POINTER(FlSliceInfo)], i32),
         "fl_op_save": ([P, ctypes.c_char_p], i32),
         "fl_op_load": ([P, ctypes.c_char_p, pp], i32),
         "fl_op_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),

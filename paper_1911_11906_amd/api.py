@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FlEigInfo, FlEigOpts, FlGemmChoice, FraclapError
+from ._lib import FlEigInfo, FlEigOpts, FlGemmChoice, FlSliceInfo, FraclapError
 
 # kept at import: module globals (sys included) may already be None when a
 # destructor runs during interpreter shutdown
@@ -241,7 +241,8 @@ class Operator:
         self.info = None
 
     @classmethod
-    def assemble(cls, ctx: Context, mesh) -> "Operator":
+    def assemble(cls, ctx: Context, mesh, sparse: bool = False) -> "Operator":
+        """sparse: keep only the CSR pencil (for n beyond dense storage)."""
         xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
         conn = np.ascontiguousarray(mesh.conn, dtype=np.int32)
         dirichlet = np.ascontiguousarray(mesh.dirichlet, dtype=np.uint8)
@@ -249,7 +250,8 @@ class Operator:
         n = ctypes.c_int64(0)
         dof = np.zeros(xy.shape[0], dtype=np.int64)
         ctx._sync_stream()
-        ctx.check(ctx.lib.fl_assemble(ctx.ptr, int(mesh.elem), xy.shape[0], xy.ctypes.data_as(P), conn.shape[0],
+        fn = ctx.lib.fl_assemble_sparse if sparse else ctx.lib.fl_assemble
+        ctx.check(fn(ctx.ptr, int(mesh.elem), xy.shape[0], xy.ctypes.data_as(P), conn.shape[0],
                                       conn.ctypes.data_as(P), dirichlet.ctypes.data_as(P), ctypes.byref(out),
                                       ctypes.byref(n), dof.ctypes.data_as(P)))
         return cls(ctx, out, dof)
@@ -356,6 +358,26 @@ class Operator:
         self.ctx.check(self.ctx.lib.fl_inertia_count(self.ptr, sg.size, sg.ctypes.data_as(P), cnt.ctypes.data_as(P),
                                                      ctypes.byref(bw)))
         return cnt, bw.value
+
+    def eigensolve_interval(self, lo: float, hi: float, max_per_slice: int = 128, tol: float = 1e-11,
+                            cap: int = None):
+        """All eigenpairs with lo <= theta < hi by spectrum slicing; returns
+        (theta, V, info) with V n x count (M-orthonormal)."""
+        if cap is None:
+            cnt, _ = self.inertia([lo, hi])
+            cap = max(int(cnt[1] - cnt[0]), 0)
+        theta = torch.empty(max(cap, 1), dtype=torch.float64, device=self.ctx.device)
+        V = empty_colmajor(self.n, max(cap, 1), self.ctx.device)
+        info = FlSliceInfo()
+        self.ctx._sync_stream()
+        rc = self.ctx.lib.fl_eigensolve_interval(self.ptr, float(lo), float(hi), int(max_per_slice), float(tol),
+                                                 int(cap), _ptr(theta), _ptr(V), _ld(V), ctypes.byref(info))
+        d = info.as_dict()
+        if rc != 0:
+            err = FraclapError(rc, self.ctx.lib.fl_last_error(self.ctx.ptr).decode())
+            err.info = d
+            raise err
+        return theta[:d["count"]], V[:, :d["count"]], d
 
     def apply_graph(self, F, alpha, paired: bool = False, out=None) -> torch.Tensor:
         """Same as ``apply`` (bitwise), captured once per argument set into a

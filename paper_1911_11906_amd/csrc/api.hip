@@ -150,8 +150,13 @@ void fl_op_destroy(fl_op* op) {
     delete op;
 }
 
-int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_t n_elem, const int32_t* conn,
-                const uint8_t* dirichlet, fl_op** out, int64_t* n_dof, int64_t* dof_of_node) {
+}  // extern "C"
+
+// Assembly into dense K and M plus their CSR copies (dense = true), or into
+// the CSR values only (dense = false: pencils too large for dense storage).
+static int assemble_impl(fl_ctx* ctx, bool dense, int elem, int64_t n_nodes, const double* xy, int64_t n_elem,
+                         const int32_t* conn, const uint8_t* dirichlet, fl_op** out, int64_t* n_dof,
+                         int64_t* dof_of_node) {
     if (!ctx) return FL_EINVAL;
     if (!out || !xy || !conn || !dirichlet || n_nodes <= 0 || n_elem <= 0)
         return fl_fail(ctx, FL_EINVAL, "fl_assemble: null pointer or empty mesh");
@@ -265,7 +270,7 @@ int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_
         dev_free(dconn);
         dev_free(ddof);
     };
-    if ((rc = dev_alloc(ctx, &op->K, nn)) || (rc = dev_alloc(ctx, &op->M, nn)) ||
+    if ((dense && ((rc = dev_alloc(ctx, &op->K, nn)) || (rc = dev_alloc(ctx, &op->M, nn)))) ||
         (rc = dev_alloc(ctx, &dxy, (size_t)n_nodes * 2)) || (rc = dev_alloc(ctx, &dconn, sorted.size())) ||
         (rc = dev_alloc(ctx, &ddof, (size_t)n_nodes))) {
         cleanup();
@@ -274,18 +279,40 @@ int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_
     }
     hipStream_t s = ctx->stream;
     hipError_t he = hipSuccess;
-    if ((he = hipMemsetAsync(op->K, 0, nn * 8, s)) || (he = hipMemsetAsync(op->M, 0, nn * 8, s)) ||
-        (he = hipMemcpyAsync(dxy, xy, (size_t)n_nodes * 16, hipMemcpyHostToDevice, s)) ||
+    if ((he = hipMemcpyAsync(dxy, xy, (size_t)n_nodes * 16, hipMemcpyHostToDevice, s)) ||
         (he = hipMemcpyAsync(dconn, sorted.data(), sorted.size() * 4, hipMemcpyHostToDevice, s)) ||
-        (he = hipMemcpyAsync(ddof, dof.data(), (size_t)n_nodes * 8, hipMemcpyHostToDevice, s)) ||
-        (he = fl_assemble_launch(s, elem, dxy, dconn, cstart.data(), ncolor, ddof, n, op->ld, op->K, op->M)) ||
-        (he = hipStreamSynchronize(s))) {
+        (he = hipMemcpyAsync(ddof, dof.data(), (size_t)n_nodes * 8, hipMemcpyHostToDevice, s))) {
         cleanup();
         fl_op_destroy(op);
         return fl_fail(ctx, FL_EHIP, std::string("fl_assemble: ") + hipGetErrorString(he));
     }
-    cleanup();
-    rc = upload_csr_and_gather(op, rowptr, colidx);
+    if (dense) {
+        if ((he = hipMemsetAsync(op->K, 0, nn * 8, s)) || (he = hipMemsetAsync(op->M, 0, nn * 8, s)) ||
+            (he = fl_assemble_launch(s, elem, dxy, dconn, cstart.data(), ncolor, ddof, n, op->ld, op->K, op->M)) ||
+            (he = hipStreamSynchronize(s))) {
+            cleanup();
+            fl_op_destroy(op);
+            return fl_fail(ctx, FL_EHIP, std::string("fl_assemble: ") + hipGetErrorString(he));
+        }
+        cleanup();
+        rc = upload_csr_and_gather(op, rowptr, colidx);
+    } else {
+        // the pattern first, then the element contributions straight into its values
+        op->nnz = (int64_t)colidx.size();
+        if (!(rc = dev_alloc(ctx, &op->rowptr, rowptr.size())) && !(rc = dev_alloc(ctx, &op->colidx, colidx.size())) &&
+            !(rc = dev_alloc(ctx, &op->kval, colidx.size())) && !(rc = dev_alloc(ctx, &op->mval, colidx.size()))) {
+            if ((he = hipMemcpyAsync(op->rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice, s)) ||
+                (he = hipMemcpyAsync(op->colidx, colidx.data(), colidx.size() * 4, hipMemcpyHostToDevice, s)) ||
+                (he = hipMemsetAsync(op->kval, 0, colidx.size() * 8, s)) ||
+                (he = hipMemsetAsync(op->mval, 0, colidx.size() * 8, s)) ||
+                (he = fl_assemble_csr_launch(s, elem, dxy, dconn, cstart.data(), ncolor, ddof, op->rowptr, op->colidx,
+                                             op->kval, op->mval)))
+                rc = fl_fail(ctx, FL_EHIP, std::string("fl_assemble_sparse: ") + hipGetErrorString(he));
+        }
+        if (!rc && (he = hipStreamSynchronize(s)) != hipSuccess)
+            rc = fl_fail(ctx, FL_EHIP, std::string("fl_assemble_sparse: ") + hipGetErrorString(he));
+        cleanup();
+    }
     if (!rc) {
         he = hipStreamSynchronize(s);
         if (he != hipSuccess) rc = fl_fail(ctx, FL_EHIP, std::string("fl_assemble: ") + hipGetErrorString(he));
@@ -296,6 +323,18 @@ int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_
     }
     *out = op;
     return FL_OK;
+}
+
+extern "C" {
+
+int fl_assemble(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_t n_elem, const int32_t* conn,
+                const uint8_t* dirichlet, fl_op** out, int64_t* n_dof, int64_t* dof_of_node) {
+    return assemble_impl(ctx, true, elem, n_nodes, xy, n_elem, conn, dirichlet, out, n_dof, dof_of_node);
+}
+
+int fl_assemble_sparse(fl_ctx* ctx, int elem, int64_t n_nodes, const double* xy, int64_t n_elem, const int32_t* conn,
+                       const uint8_t* dirichlet, fl_op** out, int64_t* n_dof, int64_t* dof_of_node) {
+    return assemble_impl(ctx, false, elem, n_nodes, xy, n_elem, conn, dirichlet, out, n_dof, dof_of_node);
 }
 
 int fl_op_from_dense(fl_ctx* ctx, int64_t n, const double* K, const double* M, int64_t ld, int on_device,
@@ -355,6 +394,7 @@ int fl_op_from_dense(fl_ctx* ctx, int64_t n, const double* K, const double* M, i
 int fl_op_matrices(const fl_op* op, double* K, double* M, int64_t ld, int on_device) {
     if (!op) return FL_EINVAL;
     fl_ctx* ctx = op->ctx;
+    if (!op->K || !op->M) return fl_fail(ctx, FL_ESTATE, "fl_op_matrices: the operator holds no dense pencil");
     if (ld < op->n) return fl_fail(ctx, FL_EINVAL, "fl_op_matrices: ld < n");
     int rc = set_device(ctx);
     if (rc) return rc;

@@ -14,15 +14,45 @@
 //    by the (p+1)-point Gauss rule (exact for degree 2p + 1) computed in the
 //    kernel; one workgroup per element.
 // Elements arrive grouped by colour (no two elements of a colour share a
-// node), so the scatter-add into the dense matrices needs no atomics and the
-// result is bitwise reproducible.
+// node), so the scatter-add needs no atomics and the result is bitwise
+// reproducible.  The contributions go into dense K and M, or (for pencils
+// too large for dense storage) straight into the values of the CSR pattern.
 #include "internal.h"
 
 namespace {
 
-template <int NV>
+// Where element contributions go: dense column-major K, M, or the values of
+// the CSR pattern (entry (i, j) found by a binary search of row i's sorted
+// column indices).
+struct DenseSink {
+    double* K;
+    double* M;
+    int64_t ld;
+    __device__ inline void add(int64_t i, int64_t j, double k, double m) const {
+        K[i + j * ld] += k;
+        M[i + j * ld] += m;
+    }
+};
+struct CsrSink {
+    const int32_t* rowptr;
+    const int32_t* colidx;
+    double* kval;
+    double* mval;
+    __device__ inline void add(int64_t i, int64_t j, double k, double m) const {
+        int32_t lo = rowptr[i], hi = rowptr[i + 1] - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (colidx[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        kval[lo] += k;
+        mval[lo] += m;
+    }
+};
+
+template <int NV, class Sink>
 __global__ void assemble_kernel(const double* __restrict__ xy, const int32_t* __restrict__ conn, int64_t e0,
-                                int64_t e1, const int64_t* __restrict__ dof, int64_t ld, double* K, double* M) {
+                                int64_t e1, const int64_t* __restrict__ dof, Sink sink) {
     int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= e1) return;
     double x[NV], y[NV];
@@ -78,8 +108,7 @@ __global__ void assemble_kernel(const double* __restrict__ xy, const int32_t* __
 #pragma unroll
         for (int b = 0; b < NV; ++b) {
             if (g[b] < 0) continue;
-            K[g[a] + g[b] * ld] += Ke[a][b];
-            M[g[a] + g[b] * ld] += Me[a][b];
+            sink.add(g[a], g[b], Ke[a][b], Me[a][b]);
         }
     }
 }
@@ -108,10 +137,9 @@ __device__ void gauss_rule(double* gp, double* gw) {
     gw[i] = 2.0 / ((1.0 - z * z) * dpq * dpq);
 }
 
-template <int P>
+template <int P, class Sink>
 __global__ __launch_bounds__(256) void assemble_qp_kernel(const double* __restrict__ xy, const int32_t* __restrict__ conn,
-                                                          int64_t e0, const int64_t* __restrict__ dof, int64_t ld,
-                                                          double* K, double* M) {
+                                                          int64_t e0, const int64_t* __restrict__ dof, Sink sink) {
     constexpr int Q = P + 1, NV = Q * Q;
     __shared__ double gp[Q], gw[Q], sx[Q], sy[Q], box[4];
     __shared__ double Lx[Q][Q], Dx[Q][Q], Ly[Q][Q], Dy[Q][Q];  // [quadrature point][basis function]
@@ -184,8 +212,7 @@ __global__ __launch_bounds__(256) void assemble_qp_kernel(const double* __restri
         const int64_t gi = g[i], gj = g[j];
         if (gi < 0 || gj < 0) continue;
         const int a = i % Q, b = i / Q, c = j % Q, d = j / Q;
-        K[gi + gj * ld] += kx[a][c] * my[b][d] + mx[a][c] * ky[b][d];
-        M[gi + gj * ld] += mx[a][c] * my[b][d];
+        sink.add(gi, gj, kx[a][c] * my[b][d] + mx[a][c] * ky[b][d], mx[a][c] * my[b][d]);
     }
 }
 
@@ -203,30 +230,45 @@ __global__ void csr_gather_kernel(int64_t n, const int32_t* __restrict__ rowptr,
 
 }  // namespace
 
-hipError_t fl_assemble_launch(hipStream_t s, int elem, const double* xy, const int32_t* conn_sorted,
-                              const int64_t* color_start, int ncolor, const int64_t* dof, int64_t n, int64_t ld,
-                              double* K, double* M) {
+namespace {
+template <class Sink>
+hipError_t assemble_colours(hipStream_t s, int elem, const double* xy, const int32_t* conn_sorted,
+                            const int64_t* color_start, int ncolor, const int64_t* dof, const Sink& sink) {
     for (int c = 0; c < ncolor; ++c) {
         int64_t e0 = color_start[c], e1 = color_start[c + 1];
         if (e1 <= e0) continue;
         unsigned blocks = (unsigned)FL_DIV_UP(e1 - e0, 128);
         const unsigned eb = (unsigned)(e1 - e0);
         switch (elem) {
-            case 3: assemble_kernel<3><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, ld, K, M); break;
-            case 4: assemble_kernel<4><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, ld, K, M); break;
-            case 9: assemble_qp_kernel<2><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
-            case 16: assemble_qp_kernel<3><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
-            case 25: assemble_qp_kernel<4><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
-            case 36: assemble_qp_kernel<5><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
-            case 49: assemble_qp_kernel<6><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
-            case 64: assemble_qp_kernel<7><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
-            case 81: assemble_qp_kernel<8><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, ld, K, M); break;
+            case 3: assemble_kernel<3><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, sink); break;
+            case 4: assemble_kernel<4><<<blocks, 128, 0, s>>>(xy, conn_sorted, e0, e1, dof, sink); break;
+            case 9: assemble_qp_kernel<2><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, sink); break;
+            case 16: assemble_qp_kernel<3><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, sink); break;
+            case 25: assemble_qp_kernel<4><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, sink); break;
+            case 36: assemble_qp_kernel<5><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, sink); break;
+            case 49: assemble_qp_kernel<6><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, sink); break;
+            case 64: assemble_qp_kernel<7><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, sink); break;
+            case 81: assemble_qp_kernel<8><<<eb, 256, 0, s>>>(xy, conn_sorted, e0, dof, sink); break;
             default: return hipErrorInvalidValue;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+}  // namespace
+
+hipError_t fl_assemble_launch(hipStream_t s, int elem, const double* xy, const int32_t* conn_sorted,
+                              const int64_t* color_start, int ncolor, const int64_t* dof, int64_t n, int64_t ld,
+                              double* K, double* M) {
+    return assemble_colours(s, elem, xy, conn_sorted, color_start, ncolor, dof, DenseSink{K, M, ld});
+}
+
+hipError_t fl_assemble_csr_launch(hipStream_t s, int elem, const double* xy, const int32_t* conn_sorted,
+                                  const int64_t* color_start, int ncolor, const int64_t* dof, const int32_t* rowptr,
+                                  const int32_t* colidx, double* kval, double* mval) {
+    return assemble_colours(s, elem, xy, conn_sorted, color_start, ncolor, dof,
+                            CsrSink{rowptr, colidx, kval, mval});
 }
 
 hipError_t fl_csr_gather(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* colidx, const double* K,

@@ -1505,6 +1505,8 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         const fl_op* op = ops[i];
         if (!op || op->device != ctx->device)
             return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: null operator or operator of another device");
+        if (!op->K || !op->M)
+            return fl_fail(ctx, FL_ESTATE, "fl_eigensolve_batched: an operator holds no dense pencil");
         if (op->n < 1 || op->n > NMAX)
             return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: each n must be in [1, 1024]");
         for (int64_t j = 0; j < i; ++j)

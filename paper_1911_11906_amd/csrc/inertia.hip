@@ -14,7 +14,8 @@
 // columns kept unscaled: P[r][c] = l_rc d_c), then the panel's rank-NB
 // update is applied to the band of the next bw columns in device memory
 // (each entry's NB-term sum read from LDS).  Only the signs of the pivots are
-// kept.  An exactly zero pivot makes the count for that shift -1.
+// kept (or, for the solves of spectrum slicing, the whole factor).  An
+// exactly zero pivot makes the count for that shift -1.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -27,7 +28,7 @@ namespace {
 
 constexpr int INB = 32;     // columns per block
 constexpr int INT = 256;    // threads per workgroup
-constexpr int IBWMAX = 255; // largest bandwidth (panel rows bw + NB fit in LDS)
+constexpr int IBWMAX = FL_BAND_MAX; // largest bandwidth (panel rows bw + NB fit in LDS)
 constexpr int IPR = IBWMAX + INB + 1;  // LDS row stride of the panel
 
 // The band of K - sigma_s M for every shift s (scattered from the CSR
@@ -57,12 +58,17 @@ __device__ inline void wg_mem_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-__global__ __launch_bounds__(INT) void ldl_count_kernel(int64_t n, int bw, int64_t ldb, int64_t stride, double* band,
-                                                       int64_t* counts) {
+// STORE: the factor is kept for solves: the band (column layout) receives
+// L below the diagonal and D on it, and Lrow (row layout, element (r, c) at
+// (bw - (r - c)) + r ldb) the same entries by rows.
+template <bool STORE>
+__global__ __launch_bounds__(INT) void ldl_kernel(int64_t n, int bw, int64_t ldb, int64_t stride, double* band,
+                                                  double* lrow, int64_t* counts) {
     __shared__ double P[IPR * INB];
     __shared__ double inv_d[INB];
     __shared__ int neg_s, zero_s;
     double* B = band + (int64_t)blockIdx.x * stride;
+    double* R = STORE ? lrow + (int64_t)blockIdx.x * stride : nullptr;
     const int t = threadIdx.x;
     if (t == 0) {
         neg_s = 0;
@@ -99,6 +105,16 @@ __global__ __launch_bounds__(INT) void ldl_count_kernel(int64_t n, int bw, int64
         }
         __syncthreads();
         if (zero_s) break;
+        if (STORE) {
+            // the block's columns of L and D, in both layouts
+            for (int e = t; e < rows * jb; e += INT) {
+                const int r = e % rows, c = e / rows;
+                if (r < c || r - c > bw) continue;
+                const double v = (r == c) ? P[c + c * IPR] : P[r + c * IPR] * inv_d[c];
+                B[(r - c) + (j0 + c) * ldb] = v;
+                R[(bw - (r - c)) + (j0 + r) * ldb] = v;
+            }
+        }
         // ---- rank-jb update of the next bw columns: A(r, q) -= sum_c P[r][c] P[q][c] / d_c
         // for q_l in [jb, jb + bw), r_l in [q_l, min(jb - 1 + bw, n - 1 - j0)]
         const int qn = (int)std::min<int64_t>(bw, n - j0 - jb);
@@ -218,6 +234,25 @@ int prepare_ordering(fl_op* op) {
 
 }  // namespace
 
+int fl_inertia_prepare(fl_op* op) { return prepare_ordering(op); }
+
+int64_t fl_band_ldb(int64_t bw) { return std::max<int64_t>(bw, 1) + 1; }
+int64_t fl_band_stride(int64_t n, int64_t bw) { return ((fl_band_ldb(bw) * n + 31) / 32) * 32; }
+
+hipError_t fl_band_factor(hipStream_t s, const fl_op* op, int64_t nshift, const double* sigma_dev, double* band,
+                          double* lrow, int64_t* neg_dev) {
+    const int64_t n = op->n, bw = std::max<int64_t>(op->inert_bw, 1);
+    const int64_t ldb = fl_band_ldb(bw), stride = fl_band_stride(n, bw);
+    hipError_t e = hipMemsetAsync(band, 0, (size_t)(nshift * stride) * 8, s);
+    if (e != hipSuccess) return e;
+    if ((e = hipMemsetAsync(lrow, 0, (size_t)(nshift * stride) * 8, s)) != hipSuccess) return e;
+    band_build_kernel<<<dim3((unsigned)FL_DIV_UP(n, 256), (unsigned)nshift), 256, 0, s>>>(
+        n, op->rowptr, op->colidx, op->kval, op->mval, op->inert_pinv, sigma_dev, ldb, stride, band);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    ldl_kernel<true><<<(unsigned)nshift, INT, 0, s>>>(n, (int)bw, ldb, stride, band, lrow, neg_dev);
+    return hipGetLastError();
+}
+
 extern "C" {
 
 int fl_inertia_count(fl_op* op, int64_t nshift, const double* sigma, int64_t* counts, int64_t* bandwidth_out) {
@@ -254,7 +289,8 @@ int fl_inertia_count(fl_op* op, int64_t nshift, const double* sigma, int64_t* co
             n, op->rowptr, op->colidx, op->kval, op->mval, op->inert_pinv, bsig.as<double>(), ldb, stride,
             bband.as<double>());
         FL_HIP(ctx, hipGetLastError());
-        ldl_count_kernel<<<(unsigned)ns, INT, 0, s>>>(n, (int)bw, ldb, stride, bband.as<double>(), bcnt.as<int64_t>());
+        ldl_kernel<false><<<(unsigned)ns, INT, 0, s>>>(n, (int)bw, ldb, stride, bband.as<double>(), nullptr,
+                                                         bcnt.as<int64_t>());
         FL_HIP(ctx, hipGetLastError());
         FL_HIP(ctx, hipMemcpyAsync(counts + s0, bcnt.p, ns * 8, hipMemcpyDeviceToHost, s));
         FL_HIP(ctx, hipStreamSynchronize(s));

@@ -113,6 +113,9 @@ struct DevBuf {
 hipError_t fl_assemble_launch(hipStream_t s, int elem, const double* xy, const int32_t* conn_sorted,
                               const int64_t* color_start, int ncolor, const int64_t* dof_of_node, int64_t n,
                               int64_t ld, double* K, double* M);
+hipError_t fl_assemble_csr_launch(hipStream_t s, int elem, const double* xy, const int32_t* conn_sorted,
+                                  const int64_t* color_start, int ncolor, const int64_t* dof, const int32_t* rowptr,
+                                  const int32_t* colidx, double* kval, double* mval);
 hipError_t fl_csr_gather(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* colidx, const double* K,
                          const double* M, int64_t ld, double* kval, double* mval);
 
@@ -185,6 +188,18 @@ int fl_sygst_device(fl_ctx* ctx, int64_t n, const double* L, int64_t ldl, const 
                     int64_t ldk, double* work);
 // work size (doubles) needed by the TRSMs for an RHS block with `cols` columns / rows
 int64_t fl_trsm_work_elems(int64_t n, int64_t other);
+
+// inertia.hip: banded LDL^T of K - sigma M in the operator's bandwidth-reducing
+// numbering (new index = inert_pinv[old]).  Bandwidths up to FL_BAND_MAX.
+constexpr int FL_BAND_MAX = 511;
+int fl_inertia_prepare(fl_op* op);
+int64_t fl_band_ldb(int64_t bw);
+int64_t fl_band_stride(int64_t n, int64_t bw);
+// Factors K - sigma_s M for nshift shifts (sigma_dev: device) into band
+// (column layout: L below the diagonal, D on it) and lrow (row layout), each
+// nshift * fl_band_stride doubles; neg_dev[s] = negative pivots (or -1).
+hipError_t fl_band_factor(hipStream_t s, const fl_op* op, int64_t nshift, const double* sigma_dev, double* band,
+                          double* lrow, int64_t* neg_dev);
 
 // sy2sb.hip: number of band-reduction panels for band width b
 int64_t fl_sy2sb_panels(int64_t n, int b);

@@ -4,15 +4,17 @@
 // eigenpairs, after which each solve is a sum over them).
 //
 // File layout (little-endian, as the host writes it):
-//   "FRACLAP\0", u32 version (1), u32 flags (bit 0: eigenpairs present),
+//   "FRACLAP\0", u32 version (1), u32 flags (bit 0: eigenpairs present;
+//   bit 1: the operator keeps no dense pencil),
 //   i64 n, i64 nnz, i32 precision (FL_FP64, FL_MIXED or -1), i32 refinement
 //   steps, f64 last refinement residual, 32-byte SHA-256 of the pencil
 //   (the CSR arrays below, in order), then the CSR arrays
 //   rowptr (n + 1 i32), colidx (nnz i32), K values (nnz f64), M values
 //   (nnz f64), then theta (n f64) and V (n x n f64, column-major, ld = n)
 //   when present, and a 32-byte SHA-256 of every preceding byte.
-// The dense K and M of a loaded operator are scattered back from the CSR
-// arrays on the device (they hold exactly the pattern's entries).
+// The dense K and M of a loaded operator (unless bit 1 is set) are scattered
+// back from the CSR arrays on the device (they hold exactly the pattern's
+// entries).
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -197,7 +199,7 @@ int fl_op_save(const fl_op* op, const char* path) {
     Header h{};
     std::memcpy(h.magic, MAGIC, 8);
     h.version = VERSION;
-    h.flags = op->has_eig ? 1u : 0u;
+    h.flags = (op->has_eig ? 1u : 0u) | (op->K ? 0u : 2u);
     h.n = n;
     h.nnz = nnz;
     h.precision = op->eig_precision;
@@ -250,7 +252,7 @@ int fl_op_load(fl_ctx* ctx, const char* path, fl_op** out) {
     };
     if (!r.ok || std::memcmp(h.magic, MAGIC, 8) != 0) return bad("not an operator file");
     if (h.version != VERSION) return bad("unsupported version " + std::to_string(h.version));
-    if (h.n <= 0 || h.n > (int64_t(1) << 31) || h.nnz <= 0 || h.nnz > h.n * h.n || (h.flags & ~1u))
+    if (h.n <= 0 || h.n > (int64_t(1) << 31) || h.nnz <= 0 || h.nnz > h.n * h.n || (h.flags & ~3u))
         return bad("corrupt header");
     const int64_t n = h.n, nnz = h.nnz;
     std::vector<int32_t> rowptr(n + 1), colidx(nnz);
@@ -288,8 +290,10 @@ int fl_op_load(fl_ctx* ctx, const char* path, fl_op** out) {
     op->refine_iters = h.refine_iters;
     op->refine_resid = h.refine_resid;
     const size_t nn = (size_t)op->ld * n;
+    const bool dense = !(h.flags & 2u);
     int rc;
-    if ((rc = dalloc(ctx, &op->K, nn)) || (rc = dalloc(ctx, &op->M, nn)) || (rc = dalloc(ctx, &op->rowptr, n + 1)) ||
+    if ((dense && ((rc = dalloc(ctx, &op->K, nn)) || (rc = dalloc(ctx, &op->M, nn)))) ||
+        (rc = dalloc(ctx, &op->rowptr, n + 1)) ||
         (rc = dalloc(ctx, &op->colidx, nnz)) || (rc = dalloc(ctx, &op->kval, nnz)) ||
         (rc = dalloc(ctx, &op->mval, nnz)) ||
         ((h.flags & 1u) && ((rc = dalloc(ctx, &op->theta, n)) || (rc = dalloc(ctx, &op->logtheta, n)) ||
@@ -299,7 +303,7 @@ int fl_op_load(fl_ctx* ctx, const char* path, fl_op** out) {
     }
     hipStream_t s = ctx->stream;
     hipError_t e = hipSuccess;
-    if ((e = hipMemsetAsync(op->K, 0, nn * 8, s)) || (e = hipMemsetAsync(op->M, 0, nn * 8, s)) ||
+    if ((dense && ((e = hipMemsetAsync(op->K, 0, nn * 8, s)) || (e = hipMemsetAsync(op->M, 0, nn * 8, s)))) ||
         (e = hipMemcpyAsync(op->rowptr, rowptr.data(), 4 * (n + 1), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(op->colidx, colidx.data(), 4 * nnz, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(op->kval, kval.data(), 8 * nnz, hipMemcpyHostToDevice, s)) ||
@@ -307,9 +311,11 @@ int fl_op_load(fl_ctx* ctx, const char* path, fl_op** out) {
         fl_op_destroy(op);
         return fl_fail(ctx, FL_EHIP, std::string("fl_op_load: ") + hipGetErrorString(e));
     }
-    csr_scatter_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, op->rowptr, op->colidx, op->kval, op->mval,
-                                                                     op->ld, op->K, op->M);
-    e = hipGetLastError();
+    if (dense) {
+        csr_scatter_kernel<<<(unsigned)FL_DIV_UP(n, 256), 256, 0, s>>>(n, op->rowptr, op->colidx, op->kval, op->mval,
+                                                                         op->ld, op->K, op->M);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess && (h.flags & 1u)) {
         if ((e = hipMemcpyAsync(op->theta, theta.data(), 8 * n, hipMemcpyHostToDevice, s)) == hipSuccess &&
             (e = hipMemcpy2DAsync(op->V, op->ld * 8, V.data(), n * 8, n * 8, n, hipMemcpyHostToDevice, s)) ==

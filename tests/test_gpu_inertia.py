@@ -94,8 +94,8 @@ def test_counts_at_full_size_p1(ctx):
 def test_inertia_rejects_dense_pencils_and_bad_shifts(ctx):
     from paper_1911_11906_amd.api import FraclapError, Operator
     rng = np.random.default_rng(0)
-    X = rng.standard_normal((300, 300))
-    op = Operator.from_dense(ctx, X @ X.T + 300 * np.eye(300), np.eye(300))
+    X = rng.standard_normal((600, 600))
+    op = Operator.from_dense(ctx, X @ X.T + 600 * np.eye(600), np.eye(600))
     with pytest.raises(FraclapError, match="bandwidth"):
         op.inertia([1.0])
     mesh = inputs.q1_rectangle(8, 8)
