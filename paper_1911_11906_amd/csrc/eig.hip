@@ -11,12 +11,16 @@
 
 // sy2sb.hip
 hipError_t fl_sy2sb(hipStream_t s, int64_t n, int b, double* A, int64_t lda, double* V1, int64_t ldv, double* T1,
-                    double* tau1, double* work, double* part, unsigned* cnt, int* abort);
+                    double* tau1, double* work, double* part, int* abort);
 int64_t fl_sy2sb_work_elems(int64_t n, int b);
 int64_t fl_sy2sb_part_elems(int64_t n);
 hipError_t fl_extract_band(hipStream_t s, int64_t n, int b, const double* A, int64_t lda, double* AB, int64_t ldab);
 // sb2st.hip
 int64_t fl_sb2st_maxt(int64_t n, int b);
+bool fl_sb2st_ring_fits(int64_t n, int b);
+int64_t fl_sb2st_ring_msg_elems(int64_t n);
+hipError_t fl_sb2st_ring(hipStream_t s, int64_t n, const double* AB, int64_t ldab, double* d, double* e, double* V2,
+                         double* tau2, double* RM, int* abort);
 hipError_t fl_sb2st(hipStream_t s, int64_t n, int b, double* AB, int64_t ldab, double* d, double* e, double* V2,
                     double* tau2, int* prog, int grid, int* abort);
 // backtrans.hip
@@ -27,7 +31,7 @@ hipError_t fl_q2_apply(hipStream_t s, int64_t n, int b, const double* V2, const 
 hipError_t fl_q1_apply(hipStream_t s, int64_t n, int b, const double* V1, int64_t ldv, const double* T1, double* Z,
                        int64_t ldz, int64_t ncols, double* work);
 hipError_t fl_ssy2sb(hipStream_t s, int64_t n, int b, float* A, int64_t lda, float* V1, int64_t ldv, float* T1,
-                     float* tau1, float* work, float* part, unsigned* cnt, int* abort);
+                     float* tau1, float* work, float* part, int* abort);
 hipError_t fl_extract_band_f(hipStream_t s, int64_t n, int b, const float* A, int64_t lda, double* AB, int64_t ldab);
 hipError_t fl_q2_apply_f(hipStream_t s, int64_t n, int b, const double* V2, const double* tau2, int64_t maxt,
                          float* work, float* Z, int64_t ldz, int64_t ncols);
@@ -119,7 +123,7 @@ struct TwoStage {
     int64_t n;
     int b;
     int64_t ldab, np, maxt, nsw;
-    DevBuf bAB, bV2, btau2, bprog, be, bT2, bcnt;
+    DevBuf bAB, bV2, btau2, bprog, be, bT2;
     DevBuf bV1, bT1;  // reflectors for the back-transforms (FP64 or FP32)
     bool q_fp32 = false;
     double* AB = nullptr;
@@ -145,7 +149,6 @@ struct TwoStage {
         FL_HIP(ctx, bV1.alloc(esz * (size_t)n * n));
         FL_HIP(ctx, hipMemsetAsync(bV1.p, 0, esz * (size_t)n * n, s));  // Q1 reads above each panel
         FL_HIP(ctx, bT1.alloc(esz * np * b * b));
-        FL_HIP(ctx, bcnt.alloc(sizeof(unsigned) * np));
         FL_HIP(ctx, bV2.alloc(sizeof(double) * nsw * maxt * b));
         FL_HIP(ctx, btau2.alloc(sizeof(double) * nsw * maxt));
         FL_HIP(ctx, bprog.alloc(sizeof(int) * (2 * n + 2)));
@@ -172,7 +175,7 @@ struct TwoStage {
             T1 = T1d.as<double>();
         }
         FL_HIP(ctx, fl_sy2sb(s, n, b, A, lda, V1, n, T1, tau.as<double>(), work.as<double>(), part.as<double>(),
-                             bcnt.as<unsigned>(), abort_flag));
+                             abort_flag));
         FL_HIP(ctx, fl_extract_band(s, n, b, A, lda, AB, ldab));
         if (q_fp32) {
             FL_HIP(ctx, fl_d2s(s, n, n, V1, n, bV1.as<float>(), n));
@@ -190,7 +193,7 @@ struct TwoStage {
         FL_HIP(ctx, work.alloc(sizeof(float) * fl_sy2sb_work_elems(n, b)));
         FL_HIP(ctx, part.alloc(sizeof(float) * fl_sy2sb_part_elems(n)));
         FL_HIP(ctx, fl_ssy2sb(s, n, b, A, lda, bV1.as<float>(), n, bT1.as<float>(), tau.as<float>(),
-                              work.as<float>(), part.as<float>(), bcnt.as<unsigned>(), abort_flag));
+                              work.as<float>(), part.as<float>(), abort_flag));
         FL_HIP(ctx, fl_extract_band_f(s, n, b, A, lda, AB, ldab));
         FL_HIP(ctx, hipStreamSynchronize(s));
         return FL_OK;
@@ -198,9 +201,19 @@ struct TwoStage {
 
     // band -> d (n), e() (n - 1), reflectors V2; FL_ENOCONV if a cooperative
     // wait of the band reduction or of the bulge chase was abandoned
+    // (the stationary chase when b = 64 and every block column fits on the
+    // device at once, else the sweep-per-workgroup chase)
     int chase(double* d, fl_eig_info* info) {
-        FL_HIP(ctx, fl_sb2st(s, n, b, AB, ldab, d, e(), bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
-                             grid_for_sb2st(n, b), abort_flag));
+        if (fl_sb2st_ring_fits(n, b)) {
+            DevBuf rm;
+            FL_HIP(ctx, rm.alloc(sizeof(double) * fl_sb2st_ring_msg_elems(n)));
+            FL_HIP(ctx, fl_sb2st_ring(s, n, AB, ldab, d, e(), bV2.as<double>(), btau2.as<double>(), rm.as<double>(),
+                                      abort_flag));
+            FL_HIP(ctx, hipStreamSynchronize(s));  // rm is released at return
+        } else {
+            FL_HIP(ctx, fl_sb2st(s, n, b, AB, ldab, d, e(), bV2.as<double>(), btau2.as<double>(), bprog.as<int>(),
+                                 grid_for_sb2st(n, b), abort_flag));
+        }
         int ab = 0;
         FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
         FL_HIP(ctx, hipStreamSynchronize(s));

@@ -220,6 +220,250 @@ __global__ __launch_bounds__(NTH) void sb2st_kernel(int64_t n, int b, double* AB
     }
 }
 
+// ---------------------------------------------------------------------------
+// Stationary bulge chase for b = 64.  Workgroup j owns the rows
+// R_j(i) = [i+1+jb, i+(j+1)b] of every sweep i: the symmetric block
+// S_j = A[R_j, R_j] and the block to its left B_j = A[R_j, R_{j-1}] stay in
+// LDS for the whole launch.  Task (i, j) is then
+//   B_j := B_j H_{i,j-1}                     (right reflector of task (i, j-1))
+//   H_{i,j} from column 0 of B_j             (column i itself for j = 0)
+//   B_j := H_{i,j} B_j,  S_j := H_{i,j} S_j H_{i,j}
+// and the only data crossing workgroups are the reflector (to j+1) and, for
+// the move of every block down by one row and column at the next sweep, the
+// first row of B_j and S_j (to j-1): the dropped row/column of S_j becomes
+// the new last column of B_j, the new last row/column of S_j is workgroup
+// j+1's first row, and the new last row of B_j is zero except for j+1's
+// beta.  A ring index (logical row r at physical (r + i) mod 64) makes that
+// move free.  Every task (i, j) reads only tasks (i, j-1) and (i-1, j+1),
+// so all of them are ready by t = 2i + j and the launch is a wavefront of
+// 2n steps, each one message hand-off long.
+//
+// Hand-off without flags: every message word is written once (reflectors go
+// straight to their place in V2 / tau2, rows to RM), all of them pre-filled
+// with a signalling-NaN sentinel that arithmetic never produces; the reader
+// polls the words themselves with agent-scope relaxed atomics, which bypass
+// the non-coherent caches, so no release/acquire fence (and no L2 write-back
+// or invalidation) is on the chain.
+constexpr int RB = 64;
+constexpr int RLD = RB + 1;
+constexpr int RTH = 256;
+constexpr long long RING_SENTINEL = 0x7FF4A5A5A5A5A5A5ll;
+constexpr long RING_SPIN_CAP = 4000000;
+
+__device__ inline bool ring_unset(double v) { return __double_as_longlong(v) == RING_SENTINEL; }
+
+// One wave polls the 64 words at p (lane k: p[k]) and the word px until none
+// holds the sentinel; false if the wait was abandoned (abort raised).
+__device__ bool ring_poll(const double* p, const double* px, int lane, double& a, double& x, int* abort) {
+    for (long spins = 0;; ++spins) {
+        a = __hip_atomic_load(p + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = __hip_atomic_load(px, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__all(!ring_unset(a) && !ring_unset(x))) return true;
+        if ((spins & 63) == 63) {
+            const int ab = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__any(ab != 0) || spins > RING_SPIN_CAP) {
+                if (lane == 0) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ inline void ring_put(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(RTH) void chase_ring_kernel(int64_t n, const double* __restrict__ AB, int64_t ldab,
+                                                         double* d, double* e, double* V2, double* tau2, int64_t maxt,
+                                                         double* RM, int64_t nwg, int* abort) {
+    __shared__ double S[RB * RLD], Bk[RB * RLD];
+    __shared__ double vin[RB], vv[RB], wvec[RB], msg[RB + 1];
+    __shared__ double red[RTH / 64][RB], red2[RTH / 64][RB];
+    __shared__ double tin_s, tau_s;
+    __shared__ int quit;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t j = blockIdx.x;
+    // sweep 0: S_j = A[R_j, R_j], B_j = A[R_j, R_{j-1}] (band rows only; zero
+    // beyond the matrix), ring offset 0
+    {
+        const int64_t r00 = 1 + j * RB;
+        for (int q = t; q < RB * RB; q += RTH) {
+            const int r = q & (RB - 1), c = q >> 6;
+            const int64_t gr = r00 + r, gc = r00 + c, gb = r00 - RB + c;
+            double sv = 0.0, bv = 0.0;
+            if (gr < n && gc < n) sv = (gr >= gc) ? AB[(gr - gc) + gc * ldab] : AB[(gc - gr) + gr * ldab];
+            if (gr < n && gb >= 0 && r <= c) bv = AB[(gr - gb) + gb * ldab];
+            S[r + c * RLD] = sv;
+            Bk[r + c * RLD] = bv;
+        }
+        if (j == 0 && t == 0) d[0] = AB[0];
+        if (t == 0) quit = 0;
+    }
+    __syncthreads();
+    const int64_t last = n - 2 - j * RB;  // the last sweep whose R_j starts inside the matrix
+    for (int64_t i = 0; i <= last; ++i) {
+        const int off = (int)(i & (RB - 1));      // physical index of logical row / column 0
+        const int q = (off + RB - 1) & (RB - 1);  // physical index of logical row / column b - 1
+        const int64_t r0 = i + 1 + j * RB;
+        const int L = (int)((n - r0) < RB ? (n - r0) : RB);
+        // ---- inputs: wave 0 the reflector of task (i, j-1), wave 1 the first
+        // row of task (i-1, j+1) (zero when R_{j+1} lay beyond the matrix)
+        if (wave == 0 && j > 0) {
+            double a, x;
+            if (!ring_poll(V2 + (i * maxt + (j - 1)) * RB, tau2 + i * maxt + (j - 1), lane, a, x, abort)) {
+                if (lane == 0) quit = 1;
+            } else {
+                vin[(lane + off) & (RB - 1)] = a;
+                if (lane == 0) tin_s = x;
+            }
+        }
+        if (wave == 1 && i > 0) {
+            if (i + (j + 1) * RB <= n - 1) {
+                const double* pm = RM + ((i - 1) * nwg + (j + 1)) * (RB + 1);
+                double a, x;
+                if (!ring_poll(pm, pm + RB, lane, a, x, abort)) {
+                    if (lane == 0) quit = 1;
+                } else {
+                    msg[lane] = a;
+                    if (lane == 0) msg[RB] = x;
+                }
+            } else {
+                msg[lane] = 0.0;
+                if (lane == 0) msg[RB] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (quit) return;
+        // ---- move down one row and column: physical q leaves as logical 0
+        // and comes back as logical b - 1
+        if (i > 0) {
+            if (t < RB) {
+                if (t != q) {
+                    const double old = S[t + q * RLD];
+                    const double nv = msg[(t - q) & (RB - 1)];
+                    Bk[t + q * RLD] = old;
+                    Bk[q + t * RLD] = 0.0;
+                    S[t + q * RLD] = nv;
+                    S[q + t * RLD] = nv;
+                } else {
+                    if (j == 0) d[i] = S[q + q * RLD];
+                    Bk[q + q * RLD] = msg[0];
+                    S[q + q * RLD] = msg[RB];
+                }
+            }
+            __syncthreads();
+        }
+        // ---- right reflector of task (i, j-1): B := B - tau (B v) v^T
+        if (j > 0) {
+            const double ti = tin_s;
+            double part = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int c = wave * 16 + k;
+                part += Bk[lane + c * RLD] * vin[c];
+            }
+            red[wave][lane] = part;
+            __syncthreads();
+            if (ti != 0.0) {
+                const double w = ti * (red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int c = wave * 16 + k;
+                    Bk[lane + c * RLD] -= w * vin[c];
+                }
+            }
+            __syncthreads();
+        }
+        // ---- Householder of the target column (logical 0; for j = 0 the
+        // column i itself, logical b - 1), by wave 0; the reflector goes out
+        // at once
+        const int tc = (j == 0) ? q : off;
+        if (wave == 0) {
+            const int lr = (lane - off) & (RB - 1);
+            const double xr = (lr < L) ? Bk[lane + tc * RLD] : 0.0;
+            double s2 = (lr >= 1) ? xr * xr : 0.0;
+            for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+            const double x0 = __shfl(xr, off, 64);
+            double beta, tau, scale;
+            if (s2 == 0.0 || L < 2) {
+                beta = x0;
+                tau = 0.0;
+                scale = 0.0;
+            } else {
+                const double nrm = sqrt(x0 * x0 + s2);
+                beta = (x0 >= 0.0) ? -nrm : nrm;
+                tau = (beta - x0) / beta;
+                scale = 1.0 / (x0 - beta);
+            }
+            const double v = (lr == 0) ? 1.0 : (lr < L ? xr * scale : 0.0);
+            vv[lane] = v;
+            Bk[lane + tc * RLD] = (lr == 0) ? beta : 0.0;
+            if (L >= 2) {
+                ring_put(V2 + (i * maxt + j) * RB + lr, v);
+                if (lane == 0) ring_put(tau2 + i * maxt + j, tau);
+            }
+            if (lane == 0) {
+                tau_s = tau;
+                if (j == 0) e[i] = beta;
+            }
+        }
+        __syncthreads();
+        // ---- left reflector on B (columns other than the target) and the
+        // two-sided update of S, column c = lane, rows 16 wave .. 16 wave + 15
+        const double tau = tau_s;
+        if (tau != 0.0) {
+            double pl = 0.0, ps = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int r = wave * 16 + k;
+                const double vr = vv[r];
+                if (j > 0) pl += vr * Bk[r + lane * RLD];
+                ps += vr * S[r + lane * RLD];
+            }
+            red[wave][lane] = pl;
+            red2[wave][lane] = ps;
+            __syncthreads();
+            // y_c = v^T B[:, c];  p = tau S v;  w = p - (tau / 2)(v^T p) v
+            const double y = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+            const double p = tau * (red2[0][lane] + red2[1][lane] + red2[2][lane] + red2[3][lane]);
+            double a = vv[lane] * p;
+            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+            const double w = p - 0.5 * tau * a * vv[lane];
+            if (wave == 0) wvec[lane] = w;
+            __syncthreads();
+            const double vc = vv[lane];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int r = wave * 16 + k;
+                const double vr = vv[r], wr = wvec[r];
+                if (j > 0 && lane != tc) Bk[r + lane * RLD] -= tau * vr * y;
+                S[r + lane * RLD] -= vr * w + wr * vc;
+            }
+        }
+        // ---- first row out, for workgroup j-1's next sweep: (beta, B[0, 1..],
+        // S[0, 0]); each word is read by the thread that last wrote it
+        if (j > 0 && wave == (off >> 4)) {
+            double* pm = RM + (i * nwg + j) * (RB + 1);
+            ring_put(pm + ((lane - off) & (RB - 1)), Bk[off + lane * RLD]);
+            if (lane == off) ring_put(pm + RB, S[off + off * RLD]);
+        }
+    }
+    if (j == 0) {
+        __syncthreads();
+        if (t == 0) {
+            const int o = (int)(last & (RB - 1));
+            d[n - 1] = S[o + o * RLD];
+        }
+    }
+}
+
+__global__ void ring_fill_kernel(int64_t count, double* p) {
+    const double s = __longlong_as_double(RING_SENTINEL);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = s;
+}
+
 __global__ void band_to_tridiag_kernel(int64_t n, const double* __restrict__ AB, int64_t ldab, double* d, double* e) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) d[i] = AB[i * ldab];
@@ -229,6 +473,38 @@ __global__ void band_to_tridiag_kernel(int64_t n, const double* __restrict__ AB,
 }  // namespace
 
 int64_t fl_sb2st_maxt(int64_t n, int b) { return n >= 3 ? 1 + (n - 3) / b : 1; }
+
+int64_t fl_sb2st_ring_groups(int64_t n) { return n >= 3 ? 1 + (n - 2) / RB : 0; }
+int64_t fl_sb2st_ring_msg_elems(int64_t n) { return n >= 3 ? (n - 1) * fl_sb2st_ring_groups(n) * (RB + 1) : 0; }
+
+// Whether the stationary chase can run: b = 64 and one workgroup per block
+// column resident at once.
+bool fl_sb2st_ring_fits(int64_t n, int b) {
+    if (b != RB || n < 3) return false;
+    int dev = 0, per = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chase_ring_kernel, RTH, 0) != hipSuccess) return false;
+    return fl_sb2st_ring_groups(n) <= (int64_t)per * p.multiProcessorCount;
+}
+
+// The stationary chase (b = 64): d, e and the reflectors V2 / tau2 (the same
+// layout as fl_sb2st); RM: fl_sb2st_ring_msg_elems(n) doubles of row
+// messages.  AB is only read.  V2, tau2 and RM are filled with the sentinel
+// first (on s), so no word of an earlier call can be taken for a message.
+hipError_t fl_sb2st_ring(hipStream_t s, int64_t n, const double* AB, int64_t ldab, double* d, double* e, double* V2,
+                         double* tau2, double* RM, int* abort) {
+    const int64_t maxt = fl_sb2st_maxt(n, RB), nsw = n - 2, nwg = fl_sb2st_ring_groups(n);
+    ring_fill_kernel<<<2048, 256, 0, s>>>(nsw * maxt * RB, V2);
+    ring_fill_kernel<<<256, 256, 0, s>>>(nsw * maxt, tau2);
+    ring_fill_kernel<<<2048, 256, 0, s>>>(fl_sb2st_ring_msg_elems(n), RM);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    int64_t nn = n, lda = ldab, mt = maxt, ng = nwg;
+    void* args[] = {&nn, (void*)&AB, &lda, &d, &e, &V2, &tau2, &mt, &RM, &ng, &abort};
+    KScope ks("sb2st", s);
+    return hipLaunchCooperativeKernel((const void*)chase_ring_kernel, dim3((unsigned)nwg), dim3(RTH), args, 0, s);
+}
 
 // Band AB (lower, ld ldab >= 2b+1, zero below the first b+1 diagonals) ->
 // d, e.  V2 (n-2 sweeps x maxt tasks x b) and tau2 receive the reflectors.

@@ -11,9 +11,14 @@
 // the current matrix through them: its own columns get the pending update
 // before the QR, and A22 V = A22_stale V - [V W] ([W V]^T V).
 // The panel QR is one cooperative kernel: each workgroup keeps a 128-row slab
-// of the panel in registers; per column one grid barrier exchanges the
-// partial dot products (every workgroup then reduces them itself, in a fixed
-// order, so the result is deterministic).
+// of the panel in registers; per column (or pair of columns) one exchange
+// shares the partial dot products (every workgroup then reduces them
+// itself, in a fixed order, so the result is deterministic).  An exchange
+// has a region of its own, written once and pre-filled with a
+// signalling-NaN sentinel that arithmetic never produces: every workgroup
+// polls the words themselves with agent-scope relaxed atomics (which bypass
+// the non-coherent caches), so no counter, release or acquire (no L2
+// write-back or invalidation) sits between two columns.
 #include "internal.h"
 
 namespace {
@@ -23,30 +28,38 @@ constexpr int NGRP = PNT / 64;  // row groups (one wave each)
 constexpr int PRPT = 32;   // panel rows per thread-row-group
 constexpr int PROWS = NGRP * PRPT;  // rows per workgroup slab (NGRP groups of 64 column lanes)
 
-constexpr long SPIN_CAP = 20000000;  // bounded wait: every wave exits even if a peer never arrives
+constexpr long SPIN_CAP = 2000000;  // bounded wait: every wave exits even if a peer never arrives
 
-// Grid-wide barrier on a monotone counter.  Returns false (and raises *abort)
-// if the wait exceeded SPIN_CAP polls or another workgroup already aborted.
-__device__ inline bool grid_barrier(unsigned* counter, unsigned target, int* abort) {
-    __shared__ int ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ok = 1;
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        long spins = 0;
-        // poll relaxed (no cache invalidation per poll), acquire once
-        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > SPIN_CAP || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    return ok != 0;
+// Exchange words: a signalling NaN of the element type marks "not yet written".
+template <class T> struct Unset;
+template <> struct Unset<double> {
+    static constexpr long long bits = 0x7FF4A5A5A5A5A5A5ll;
+    __device__ static double value() { return __longlong_as_double(bits); }
+    __device__ static bool is(double v) { return __double_as_longlong(v) == bits; }
+};
+template <> struct Unset<float> {
+    static constexpr int bits = 0x7FA5A5A5;
+    __device__ static float value() { return __int_as_float(bits); }
+    __device__ static bool is(float v) { return __float_as_int(v) == bits; }
+};
+
+template <class T>
+__device__ inline void xput(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline T xget(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Words of exchange k: the partial sums of G workgroups (128 each), then
+// rows c and c+1 of the panel (64 each).
+__host__ __device__ inline int64_t exch_elems(int64_t G) { return G * 128 + 128; }
+
+template <class T>
+__global__ void unset_fill_kernel(int64_t count, T* p) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = Unset<T>::value();
 }
 
 // QR of the m x kb panel P (ld lda) with kref reflectors.  On exit P holds R
@@ -68,17 +81,17 @@ __device__ inline bool grid_barrier(unsigned* counter, unsigned target, int* abo
 // ~4 eps / PAIR_MIN.  The decision is made on the same reduced sums in every
 // workgroup, in a fixed summation order: the result is deterministic.
 //
-// part: scratch of 2 * G * 128 doubles; prow: 2 * 128; counter: zeroed;
-// abort: raised when a barrier wait is abandoned (the result is then invalid).
+// part: kref exchange regions of exch_elems(G) words, all unset on entry;
+// abort: raised when a wait is abandoned (the result is then invalid).
 constexpr double PAIR_MIN = 1.0 / 64;
 template <class T>
 __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kref, T* P, int64_t lda, T* Vx,
-                                                       int64_t ldv, T* tau, T* part, T* prow, unsigned* counter,
-                                                       int* abort) {
+                                                       int64_t ldv, T* tau, T* part, int* abort) {
     __shared__ T xc[PROWS];   // pivot column c (this slab's rows)
     __shared__ T xd[PROWS];   // column c+1: before reflector c (Gram row), after it (second update)
     __shared__ T red[NGRP][64], red2[NGRP][64];
     __shared__ T wv[64], gv[64];
+    __shared__ T rows[128];  // rows c and c+1 of the panel
     __shared__ T sc[8];  // scale, tau, beta, | scale', tau', beta', pair flag
     const int t = threadIdx.x;
     const int lane = t & 63;   // panel column handled by this thread
@@ -93,7 +106,7 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
     }
     unsigned k = 0;  // exchanges so far
     for (int c = 0; c < kref;) {
-        const int par = k & 1;
+        T* ex = part + (int64_t)k * exch_elems(G);
         const bool try2 = c + 1 < kref;
         // pivot column (and column c+1) into LDS
         if (lane == c) {
@@ -121,44 +134,55 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
             const int64_t row = c + h;
             if ((h == 0 || try2) && slab0 <= row && row < slab0 + PROWS) {
                 int lr = (int)(row - slab0);
-                if (grp == lr % NGRP) prow[par * 128 + h * 64 + lane] = v[lr / NGRP];
+                if (grp == lr % NGRP) xput(ex + G * 128 + h * 64 + lane, v[lr / NGRP]);
             }
         }
         __syncthreads();
         if (t < 64) {
-            T* pw = part + (size_t)par * G * 128 + (size_t)blockIdx.x * 128;
+            T* pw = ex + (size_t)blockIdx.x * 128;
             T a = T(0), a2 = T(0);
 #pragma unroll
             for (int q = 0; q < NGRP; ++q) {
                 a += red[q][t];
                 a2 += red2[q][t];
             }
-            pw[t] = a;
-            pw[64 + t] = a2;
+            xput(pw + t, a);
+            xput(pw + 64 + t, a2);
         }
-        // every wave waits for its own stores (partials, published rows); the
-        // barrier's single agent-scope release then writes the L2 back once
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // red is reused below
         ++k;
-        if (!grid_barrier(counter, k * G, abort)) return;
         // reduce the partials of all workgroups in a fixed order (the same in
         // every workgroup): row group q sums workgroups q, q+NGRP, ..., the
-        // NGRP sums are added in LDS.  The loads (which miss the cache after the
-        // barrier) are issued RB at a time before the additions, from
-        // clamped, always valid addresses.
+        // NGRP sums are added in LDS.  The words are polled RB workgroups at
+        // a time (loads issued before any test), from clamped, always valid
+        // addresses, until none is unset.
+        int bad = 0;
         {
             constexpr int RB = 16;
             T acc = T(0), acc2 = T(0);
-            const T* pp = part + (size_t)par * G * 128 + lane;
-            for (unsigned w0 = (unsigned)grp; w0 < G; w0 += NGRP * RB) {
+            const T* pp = ex + lane;
+            for (unsigned w0 = (unsigned)grp; w0 < G && !bad; w0 += NGRP * RB) {
                 T buf[RB], buf2[RB];
+                for (long spins = 0;; ++spins) {
 #pragma unroll
-                for (int q = 0; q < RB; ++q) {
-                    const unsigned w = w0 + NGRP * q;
-                    const size_t o = (size_t)(w < G ? w : 0) * 128;
-                    buf[q] = pp[o];
-                    buf2[q] = pp[o + 64];
+                    for (int q = 0; q < RB; ++q) {
+                        const unsigned w = w0 + NGRP * q;
+                        const size_t o = (size_t)(w < G ? w : 0) * 128;
+                        buf[q] = xget(pp + o);
+                        buf2[q] = xget(pp + o + 64);
+                    }
+                    bool ready = true;
+#pragma unroll
+                    for (int q = 0; q < RB; ++q)
+                        ready = ready && (w0 + NGRP * q >= G || (!Unset<T>::is(buf[q]) && !Unset<T>::is(buf2[q])));
+                    if (ready) break;
+                    if ((spins & 63) == 63 &&
+                        (spins > SPIN_CAP || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        bad = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
                 }
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
@@ -169,7 +193,23 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
             red[grp][lane] = acc;
             red2[grp][lane] = acc2;
         }
-        __syncthreads();
+        // rows c and c+1
+        if (t < (try2 ? 128 : 64) && !bad) {
+            T r;
+            for (long spins = 0;; ++spins) {
+                r = xget(ex + G * 128 + t);
+                if (!Unset<T>::is(r)) break;
+                if ((spins & 63) == 63 &&
+                    (spins > SPIN_CAP || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bad = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            rows[t] = r;
+        }
+        if (__syncthreads_or(bad)) return;
         if (t < 64) {
             T a = T(0), a2 = T(0);
 #pragma unroll
@@ -181,8 +221,8 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
             gv[t] = a2;
         }
         __syncthreads();
-        const T* r0v = prow + par * 128;       // row c
-        const T* r1v = prow + par * 128 + 64;  // row c+1
+        const T* r0v = rows;       // row c
+        const T* r1v = rows + 64;  // row c+1
         if (t == 0) {
             const T x0 = r0v[c];
             const T sig = wv[c];  // |x(rows > c)|^2
@@ -373,13 +413,9 @@ constexpr int QL = 8;  // panels per deferred trailing update
 
 template <class T>
 hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, int64_t ldv, T* T1, T* tau1, T* work,
-                   T* part, unsigned* cnt, int* abort) {
+                   T* part, int* abort) {
     const int64_t np = fl_sy2sb_panels(n, b);
     hipError_t e;
-    if (np > 0) {
-        e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * np, s);
-        if (e != hipSuccess) return e;
-    }
     const int64_t kw = 2 * (int64_t)QL * b;  // columns of [V W] and [W V]
     T* Gm = work;                            // b x b
     T* S = Gm + (int64_t)b * b;              // b x b
@@ -405,12 +441,13 @@ hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, in
         T* tp = tau1 + c0;
         const unsigned G = (unsigned)FL_DIV_UP(m, PROWS);
         {
+            const int64_t fill = (int64_t)kref * exch_elems(G);
+            unset_fill_kernel<T><<<(unsigned)std::min<int64_t>(FL_DIV_UP(fill, 256), 1024), 256, 0, s>>>(fill, part);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
             int64_t mm = m;
             int kbb = kb, krf = kref;
             int64_t ldaa = lda, ldvv = ldv;
-            T* prow = part + 2 * FL_DIV_UP(n, PROWS) * 128;
-            unsigned* counter = cnt + p;
-            void* args[] = {&mm, &kbb, &krf, &Pn, &ldaa, &Vp, &ldvv, &tp, &part, &prow, &counter, &abort};
+            void* args[] = {&mm, &kbb, &krf, &Pn, &ldaa, &Vp, &ldvv, &tp, &part, &abort};
             e = hipLaunchCooperativeKernel((const void*)panel_qr_kernel<T>, dim3(G), dim3(PNT), args, 0, s);
             if (e != hipSuccess) return e;
         }
@@ -469,22 +506,24 @@ int64_t fl_sy2sb_panels(int64_t n, int b) {
 // ld ldv) receives the explicit reflectors of every panel at the panel's own
 // rows/columns (its entries above each panel must be zero on entry), T1 (np
 // blocks of b x b) their T factors.  work: fl_sy2sb_work_elems(n, b) elements
-// (about 4 QL n b); part: fl_sy2sb_part_elems(n) doubles; cnt: >= np unsigned;
+// (about 4 QL n b); part: fl_sy2sb_part_elems(n) elements;
 // abort: device flag raised if a cooperative wait was abandoned.
 hipError_t fl_sy2sb(hipStream_t s, int64_t n, int b, double* A, int64_t lda, double* V1, int64_t ldv, double* T1,
-                    double* tau1, double* work, double* part, unsigned* cnt, int* abort) {
-    return sy2sb_t<double>(s, n, b, A, lda, V1, ldv, T1, tau1, work, part, cnt, abort);
+                    double* tau1, double* work, double* part, int* abort) {
+    return sy2sb_t<double>(s, n, b, A, lda, V1, ldv, T1, tau1, work, part, abort);
 }
 hipError_t fl_ssy2sb(hipStream_t s, int64_t n, int b, float* A, int64_t lda, float* V1, int64_t ldv, float* T1,
-                     float* tau1, float* work, float* part, unsigned* cnt, int* abort) {
-    return sy2sb_t<float>(s, n, b, A, lda, V1, ldv, T1, tau1, work, part, cnt, abort);
+                     float* tau1, float* work, float* part, int* abort) {
+    return sy2sb_t<float>(s, n, b, A, lda, V1, ldv, T1, tau1, work, part, abort);
 }
 
 int64_t fl_sy2sb_work_elems(int64_t n, int b) {
     const int64_t kw = 2 * (int64_t)QL * b;
     return 3 * (int64_t)b * b + 2 * n * (int64_t)b + 2 * n * kw + kw * b;
 }
-int64_t fl_sy2sb_part_elems(int64_t n) { return 2 * FL_DIV_UP(n, PROWS) * 128 + 256; }
+// exchange regions of the panel QR: at most 64 exchanges of a panel of at
+// most ceil(n / PROWS) workgroups
+int64_t fl_sy2sb_part_elems(int64_t n) { return 64 * exch_elems(FL_DIV_UP(n, PROWS)); }
 
 hipError_t fl_extract_band(hipStream_t s, int64_t n, int b, const double* A, int64_t lda, double* AB, int64_t ldab) {
     if (n <= 0) return hipSuccess;

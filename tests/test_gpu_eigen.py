@@ -80,7 +80,8 @@ def random_sym(n, rng, spread=False):
     return A
 
 
-@pytest.mark.parametrize("n,b", [(3, 2), (10, 4), (100, 8), (257, 32), (300, 64), (600, 64)])
+@pytest.mark.parametrize("n,b", [(3, 2), (10, 4), (100, 8), (257, 32), (4, 64), (66, 64), (130, 64), (259, 64),
+                                 (300, 64), (600, 64)])
 def test_sytrd_2stage(ctx, oracle_mod, n, b):
     note("sytrd_2stage", n, b)
     rng = np.random.default_rng(7 * n + b)
