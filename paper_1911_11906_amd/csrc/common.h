@@ -77,7 +77,7 @@ hipError_t fl_dgemm_batched(hipStream_t s, int ta, int tb, const GemmProblem* de
 // FP32 GEMM (mixed-precision mode): same conventions.
 hipError_t fl_sgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, float alpha,
                     const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
-                    int64_t ldc);
+                    int64_t ldc, int lower = 0);
 
 hipError_t fl_d2s(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, float* B, int64_t ldb);
 hipError_t fl_s2d(hipStream_t s, int64_t m, int64_t n, const float* A, int64_t lda, double* B, int64_t ldb);
@@ -85,13 +85,13 @@ hipError_t fl_s2d(hipStream_t s, int64_t m, int64_t n, const float* A, int64_t l
 // type-dispatched GEMM (FP64 or FP32 matrix cores)
 inline hipError_t fl_gemm_t(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
                             const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                            int64_t ldc) {
-    return fl_dgemm(s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+                            int64_t ldc, int lower = 0) {
+    return fl_dgemm(s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lower);
 }
 inline hipError_t fl_gemm_t(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
                             const float* A, int64_t lda, const float* B, int64_t ldb, double beta, float* C,
-                            int64_t ldc) {
-    return fl_sgemm(s, ta, tb, m, n, k, (float)alpha, A, lda, B, ldb, (float)beta, C, ldc);
+                            int64_t ldc, int lower = 0) {
+    return fl_sgemm(s, ta, tb, m, n, k, (float)alpha, A, lda, B, ldb, (float)beta, C, ldc, lower);
 }
 
 // small helpers
@@ -102,4 +102,11 @@ hipError_t fl_transpose(hipStream_t s, int64_t m, int64_t n, const double* A, in
 hipError_t fl_fill(hipStream_t s, int64_t m, int64_t n, double v, double* A, int64_t lda);
 // upper triangle of the n x n A := transpose of its strict lower triangle
 hipError_t fl_mirror_lower(hipStream_t s, int64_t n, double* A, int64_t lda);
+hipError_t fl_mirror_lower_f(hipStream_t s, int64_t n, float* A, int64_t lda);
+inline hipError_t fl_mirror_lower_t(hipStream_t s, int64_t n, double* A, int64_t lda) {
+    return fl_mirror_lower(s, n, A, lda);
+}
+inline hipError_t fl_mirror_lower_t(hipStream_t s, int64_t n, float* A, int64_t lda) {
+    return fl_mirror_lower_f(s, n, A, lda);
+}
 hipError_t fl_set_identity(hipStream_t s, int64_t n, double* A, int64_t lda);

@@ -136,6 +136,7 @@ __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int S, const T* __res
     if (i >= m) return;
     for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
         T acc = T(0);
+#pragma unroll 8
         for (int z = 0; z < S; ++z) acc += P[(int64_t)z * m * n + i + j * m];
         T* c = C + i + j * ldc;
         *c = (beta != T(0)) ? beta * (*c) + acc : acc;
@@ -280,9 +281,11 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower, const SplitWs* ws,
     }
     const int64_t tm = FL_DIV_UP(g.m, BM), tn = FL_DIV_UP(g.n, BN);
     const int64_t tiles = tm * tn;
-    // few output tiles and a long k: split k so that the chip fills up
-    if (!lower && tiles < 384 && g.k >= 2048) {
-        int64_t S = std::min<int64_t>({FL_DIV_UP(768, tiles), g.k / 512, 32});
+    // few output tiles and a long k: split k so that the chip fills up (down
+    // to k-slices of 128 for the smallest outputs, e.g. the 64 x 64 Gram
+    // matrices of the band reduction)
+    if (!lower && tiles < 384 && g.k >= 1024) {
+        int64_t S = std::min<int64_t>({FL_DIV_UP(1024, tiles), g.k / 128, 256});
         T* P = split_buffer<T>(s, ws, S, g.m, g.n);
         if (S > 1 && P) {
             int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), GKB) * GKB;
@@ -376,8 +379,9 @@ __global__ void transpose_kernel(int64_t m, int64_t n, const double* __restrict_
 }
 
 // A(i, j) = A(j, i) for i < j (upper from lower), 32 x 32 tiles through LDS.
-__global__ void mirror_lower_kernel(int64_t n, double* A, int64_t lda) {
-    __shared__ double tile[32][33];
+template <class T>
+__global__ void mirror_lower_kernel(int64_t n, T* A, int64_t lda) {
+    __shared__ T tile[32][33];
     const int64_t bi = blockIdx.x, bj = blockIdx.y;  // source tile (bi, bj) with bi >= bj
     if (bi < bj) return;
     const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
@@ -474,11 +478,11 @@ hipError_t fl_dgemm_batched(hipStream_t s, int ta, int tb, const GemmProblem* pr
 }
 
 hipError_t fl_sgemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, float alpha, const float* A,
-                    int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc) {
+                    int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int lower) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if (k <= 0 && beta == 1.0f) return hipSuccess;
     Prob<float> g{m, n, k, A, lda, B, ldb, C, ldc, alpha, beta};
-    return gemm_any<float>(s, ta, tb, g, 0);
+    return gemm_any<float>(s, ta, tb, g, lower);
 }
 
 hipError_t fl_d2s(hipStream_t s, int64_t m, int64_t n, const double* A, int64_t lda, float* B, int64_t ldb) {
@@ -511,7 +515,13 @@ hipError_t fl_transpose(hipStream_t s, int64_t m, int64_t n, const double* A, in
 hipError_t fl_mirror_lower(hipStream_t s, int64_t n, double* A, int64_t lda) {
     if (n <= 1) return hipSuccess;
     dim3 grid((unsigned)FL_DIV_UP(n, 32), (unsigned)FL_DIV_UP(n, 32));
-    mirror_lower_kernel<<<grid, dim3(32, 8), 0, s>>>(n, A, lda);
+    mirror_lower_kernel<double><<<grid, dim3(32, 8), 0, s>>>(n, A, lda);
+    return hipGetLastError();
+}
+hipError_t fl_mirror_lower_f(hipStream_t s, int64_t n, float* A, int64_t lda) {
+    if (n <= 1) return hipSuccess;
+    dim3 grid((unsigned)FL_DIV_UP(n, 32), (unsigned)FL_DIV_UP(n, 32));
+    mirror_lower_kernel<float><<<grid, dim3(32, 8), 0, s>>>(n, A, lda);
     return hipGetLastError();
 }
 

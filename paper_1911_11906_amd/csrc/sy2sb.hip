@@ -3,14 +3,15 @@
 // Panel p (columns c0 .. c0+b) is QR-factored below the band:
 // A[c0+b:n, c0:c0+b] = (I - V T V^T) [R; 0].  The trailing block is then
 // updated two-sidedly on the matrix cores:
-//     X = A22 V T,  W = X - 1/2 V (T^T V^T X),  A22 -= V W^T + W V^T.
+//     X = A22 V T,  W = X - 1/2 V (T^T V^T X),  A22 -= V W^T + W V^T
+// (the lower triangle by the matrix cores, the upper one copied from it).
 // The rank-2b updates of up to QL consecutive panels are deferred and applied
 // as one rank-2 QL b product (a k of 2 b = 128 leaves each output tile's
 // load and store of C unamortised).  Until then the pending pairs (V_k, W_k)
 // are kept side by side in [V W] and [W V] (absolute rows), and a panel sees
 // the current matrix through them: its own columns get the pending update
 // before the QR, and A22 V = A22_stale V - [V W] ([W V]^T V).
-// The panel QR is one cooperative kernel: each workgroup keeps a 128-row slab
+// The panel QR is one cooperative kernel: each workgroup keeps a 256-row slab
 // of the panel in registers; per column (or pair of columns) one exchange
 // shares the partial dot products (every workgroup then reduces them
 // itself, in a fixed order, so the result is deterministic).  An exchange
@@ -23,7 +24,8 @@
 
 namespace {
 
-constexpr int PNT = 256;   // threads per panel workgroup
+constexpr int PNT = 512;   // threads per panel workgroup (256-row slabs: every exchange is read by each
+                           // workgroup in full, so fewer, larger slabs mean less exchange traffic)
 constexpr int NGRP = PNT / 64;  // row groups (one wave each)
 constexpr int PRPT = 32;   // panel rows per thread-row-group
 constexpr int PROWS = NGRP * PRPT;  // rows per workgroup slab (NGRP groups of 64 column lanes)
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         // addresses, until none is unset.
         int bad = 0;
         {
-            constexpr int RB = 16;
+            constexpr int RB = 8;
             T acc = T(0), acc2 = T(0);
             const T* pp = ex + lane;
             for (unsigned w0 = (unsigned)grp; w0 < G && !bad; w0 += NGRP * RB) {
@@ -484,9 +486,12 @@ hipError_t sy2sb_t(hipStream_t s, int64_t n, int b, T* A, int64_t lda, T* V1, in
         if ((e = copy_t<T>(s, m, kref, Vp, ldv, vw + r0, n))) return e;
         if ((e = copy_t<T>(s, m, kref, vw + b * n + r0, n, wv + r0, n))) return e;
         if ((e = copy_t<T>(s, m, kref, Vp, ldv, wv + b * n + r0, n))) return e;
-        // trailing update of the group: A[r0:n, r0:n] -= [V W] [W V]^T
+        // trailing update of the group: A[r0:n, r0:n] -= [V W] [W V]^T on the
+        // tiles on and below the diagonal (the update is symmetric), then the
+        // upper triangle from the lower one
         if (p + 1 - p0 == QL || p + 1 == np) {
-            if ((e = fl_gemm_t(s, 0, 1, m, m, kp + 2 * b, -1.0, VW + r0, n, WV + r0, n, 1.0, A22, lda))) return e;
+            if ((e = fl_gemm_t(s, 0, 1, m, m, kp + 2 * b, -1.0, VW + r0, n, WV + r0, n, 1.0, A22, lda, 1))) return e;
+            if ((e = fl_mirror_lower_t(s, m, A22, lda))) return e;
             p0 = p + 1;
         }
     }
