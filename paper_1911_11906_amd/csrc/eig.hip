@@ -182,7 +182,18 @@ struct TwoStage {
             FL_HIP(ctx, fl_d2s(s, np * b, b, T1, np * b, bT1.as<float>(), np * b));
         }
         FL_HIP(ctx, hipStreamSynchronize(s));  // the scoped buffers are released at return
-        return FL_OK;
+        return check_abort("band reduction");
+    }
+
+    // FL_ENOCONV if a cooperative wait of the last stage was abandoned (the
+    // flag is cleared for the next stage)
+    int check_abort(const char* stage) {
+        int ab = 0;
+        FL_HIP(ctx, hipMemcpyAsync(&ab, abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        if (!ab) return FL_OK;
+        FL_HIP(ctx, hipMemsetAsync(abort_flag, 0, sizeof(int), s));
+        return fl_fail(ctx, FL_ENOCONV, std::string(stage) + ": a cooperative wait was abandoned");
     }
 
     // A (full symmetric storage, FP32, destroyed) -> band; FP32 reflectors
@@ -196,7 +207,7 @@ struct TwoStage {
                               work.as<float>(), part.as<float>(), abort_flag));
         FL_HIP(ctx, fl_extract_band_f(s, n, b, A, lda, AB, ldab));
         FL_HIP(ctx, hipStreamSynchronize(s));
-        return FL_OK;
+        return check_abort("band reduction");
     }
 
     // band -> d (n), e() (n - 1), reflectors V2; FL_ENOCONV if a cooperative
@@ -262,7 +273,10 @@ int fl_syevd_device(fl_ctx* ctx, int64_t n, double* A, int64_t lda, int band, do
     int rc;
     if ((rc = ts.init(false))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SY2SB));
-    if ((rc = ts.reduce(A, lda))) return rc;
+    if ((rc = ts.reduce(A, lda))) {
+        if (info) info->index = FL_STAGE_SY2SB;
+        return rc;
+    }
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
     if ((rc = ts.chase(w, info))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_STEDC));
@@ -298,7 +312,10 @@ int fl_syevd_mixed_device(fl_ctx* ctx, int64_t n, double* C, int64_t ldc, int ba
     } else {
         rc = ts.reduce(C, ldc);
     }
-    if (rc) return rc;
+    if (rc) {
+        if (info) info->index = FL_STAGE_SY2SB;
+        return rc;
+    }
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_SB2ST));
     if ((rc = ts.chase(w, info))) return rc;
     if (tm) FL_HIP(ctx, tm->mark(FL_STAGE_STEDC));

@@ -100,44 +100,52 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
     const int grp = t >> 6;    // row group
     const unsigned G = gridDim.x;
     const int64_t slab0 = (int64_t)blockIdx.x * PROWS;
+    // rows of this thread: slab0 + grp + NGRP q, addressed from one base with
+    // constant offsets (no per-row 64-bit addresses kept live)
+    const int rows_here = (int)std::min<int64_t>(m - slab0, PROWS);
+    const bool col_ok = lane < kb;
     T v[PRPT];
+    {
+        const T* Pb = P + (slab0 + grp) + (int64_t)(col_ok ? lane : 0) * lda;
 #pragma unroll
-    for (int q = 0; q < PRPT; ++q) {
-        int64_t r = slab0 + grp + NGRP * q;
-        v[q] = (r < m && lane < kb) ? P[r + lane * lda] : T(0);
+        for (int q = 0; q < PRPT; ++q) v[q] = (grp + NGRP * q < rows_here && col_ok) ? Pb[NGRP * q] : T(0);
     }
     unsigned k = 0;  // exchanges so far
     for (int c = 0; c < kref;) {
         T* ex = part + (int64_t)k * exch_elems(G);
         const bool try2 = c + 1 < kref;
-        // pivot column (and column c+1) into LDS
+        // row indices relative to the slab: r = grp + NGRP q against the
+        // slab-relative pivot lc (32-bit)
+        const int lc = (int)std::max<int64_t>(-2, std::min<int64_t>(c - slab0, PROWS + 2));
+        // pivot column (and column c+1) into LDS, zero at and above rows c
+        // (c+1), so that every sum and update below runs over all rows
         if (lane == c) {
 #pragma unroll
-            for (int q = 0; q < PRPT; ++q) xc[grp + NGRP * q] = v[q];
+            for (int q = 0; q < PRPT; ++q) xc[grp + NGRP * q] = (grp + NGRP * q > lc) ? v[q] : T(0);
         }
         if (try2 && lane == c + 1) {
 #pragma unroll
-            for (int q = 0; q < PRPT; ++q) xd[grp + NGRP * q] = v[q];
+            for (int q = 0; q < PRPT; ++q) xd[grp + NGRP * q] = (grp + NGRP * q > lc + 1) ? v[q] : T(0);
         }
         __syncthreads();
-        // partial sums over this slab: s_j (rows > c), g_j (rows > c+1)
+        // partial sums over this slab: s_j (rows > c), g_j (rows > c+1); rows
+        // beyond the panel hold zeros
         T s = T(0), g = T(0);
 #pragma unroll
         for (int q = 0; q < PRPT; ++q) {
-            int64_t r = slab0 + grp + NGRP * q;
-            if (r > c && r < m) s += xc[grp + NGRP * q] * v[q];
-            if (try2 && r > c + 1 && r < m) g += xd[grp + NGRP * q] * v[q];
+            s += xc[grp + NGRP * q] * v[q];
+            g += xd[grp + NGRP * q] * v[q];
         }
+        if (!try2) g = T(0);
         red[grp][lane] = s;
         red2[grp][lane] = g;
-        // the workgroups owning rows c and c+1 publish them
+        // the workgroups owning rows c and c+1 publish them (v is indexed
+        // with constants only, so that it stays in registers)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t row = c + h;
-            if ((h == 0 || try2) && slab0 <= row && row < slab0 + PROWS) {
-                int lr = (int)(row - slab0);
-                if (grp == lr % NGRP) xput(ex + G * 128 + h * 64 + lane, v[lr / NGRP]);
-            }
+        for (int q = 0; q < PRPT; ++q) {
+            const int64_t r = slab0 + grp + NGRP * q;
+            if (r == c) xput(ex + G * 128 + lane, v[q]);
+            if (try2 && r == c + 1) xput(ex + G * 128 + 64 + lane, v[q]);
         }
         __syncthreads();
         if (t < 64) {
@@ -281,16 +289,17 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         const bool pair = red[0][0] != T(0);
         // w_j = v^T a_j = a_j[c] + scale * s_j   (j > c)
         const T wj = (lane > c && lane < kb) ? (r0v[lane] + scale * wv[lane]) : T(0);
+        // column c becomes (beta, reflector entries); columns j > c get
+        // a_j -= tau v w_j with v = (1 at row c, scale x below)
+        {
+            const bool piv = lane == c;
+            const T f = (lane > c && lane < kb) ? tauc * wj : T(0);
 #pragma unroll
-        for (int q = 0; q < PRPT; ++q) {
-            int64_t r = slab0 + grp + NGRP * q;
-            if (r >= m) continue;
-            if (lane == c) {
-                if (r > c) v[q] = scale * v[q];          // reflector entry
-                else if (r == c) v[q] = beta;
-            } else if (lane > c && lane < kb) {
-                T vr = (r > c) ? scale * xc[grp + NGRP * q] : (r == c ? T(1) : T(0));
-                v[q] -= tauc * vr * wj;
+            for (int q = 0; q < PRPT; ++q) {
+                const int r = grp + NGRP * q;
+                const T vr = scale * xc[r] + (r == lc ? T(1) : T(0));
+                const T pv = (r > lc) ? scale * v[q] : (r == lc ? beta : v[q]);
+                v[q] = piv ? pv : v[q] - f * vr;
             }
         }
         if (!pair) {
@@ -312,31 +321,35 @@ __global__ __launch_bounds__(PNT) void panel_qr_kernel(int64_t m, int kb, int kr
         // column c+1 after reflector c, for the second update
         if (lane == c + 1) {
 #pragma unroll
-            for (int q = 0; q < PRPT; ++q) xd[grp + NGRP * q] = v[q];
+            for (int q = 0; q < PRPT; ++q) xd[grp + NGRP * q] = (grp + NGRP * q > lc + 1) ? v[q] : T(0);
         }
         __syncthreads();
+        {
+            const bool piv2 = lane == c + 1;
+            const T f = (lane > c + 1 && lane < kb) ? tau2 * wj2 : T(0);
 #pragma unroll
-        for (int q = 0; q < PRPT; ++q) {
-            int64_t r = slab0 + grp + NGRP * q;
-            if (r >= m) continue;
-            if (lane == c + 1) {
-                if (r > c + 1) v[q] = scale2 * v[q];
-                else if (r == c + 1) v[q] = beta2;
-            } else if (lane > c + 1 && lane < kb) {
-                T vr = (r > c + 1) ? scale2 * xd[grp + NGRP * q] : (r == c + 1 ? T(1) : T(0));
-                v[q] -= tau2 * vr * wj2;
+            for (int q = 0; q < PRPT; ++q) {
+                const int r = grp + NGRP * q;
+                const T vr = scale2 * xd[r] + (r == lc + 1 ? T(1) : T(0));
+                const T pv = (r > lc + 1) ? scale2 * v[q] : (r == lc + 1 ? beta2 : v[q]);
+                v[q] = piv2 ? pv : v[q] - f * vr;
             }
         }
         __syncthreads();
         c += 2;
     }
     // write back the factored panel and the explicit reflectors
+    if (col_ok) {
+        T* Pb = P + (slab0 + grp) + (int64_t)lane * lda;
+        T* Vb = Vx + (slab0 + grp) + (int64_t)lane * ldv;
+        const int ll = (int)std::max<int64_t>(-1, std::min<int64_t>(lane - slab0, PROWS));  // lane's diagonal row, slab-relative
 #pragma unroll
-    for (int q = 0; q < PRPT; ++q) {
-        int64_t r = slab0 + grp + NGRP * q;
-        if (r < m && lane < kb) {
-            P[r + lane * lda] = v[q];
-            if (lane < kref) Vx[r + lane * ldv] = (r > lane) ? v[q] : (r == lane ? T(1) : T(0));
+        for (int q = 0; q < PRPT; ++q) {
+            const int r = grp + NGRP * q;
+            if (r < rows_here) {
+                Pb[NGRP * q] = v[q];
+                if (lane < kref) Vb[NGRP * q] = (r > ll) ? v[q] : (r == ll ? T(1) : T(0));
+            }
         }
     }
 }
