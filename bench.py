@@ -172,11 +172,14 @@ def traffic_for(kernel: str):
     for line in open(path):
         f = line.split()
         if len(f) == 4 and f[0] == kernel:
-            src = os.path.join(ROOT, "paper_1911_11906_amd", "csrc", f[1])
-            if not os.path.exists(src):
-                return None
-            h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-            return float(f[3]) if h == f[2] else None
+            # f[1]: the kernel's source files joined by '+', hashed in that order
+            h = hashlib.sha256()
+            for name in f[1].split("+"):
+                src = os.path.join(ROOT, "paper_1911_11906_amd", "csrc", name)
+                if not os.path.exists(src):
+                    return None
+                h.update(open(src, "rb").read())
+            return float(f[3]) if h.hexdigest()[:16] == f[2] else None
     return None
 
 
@@ -305,6 +308,8 @@ def main():
                           "bound_solves_per_s": nsol / (2.0 * n * n * args.nf * (1 + args.na)
                                                         / (PEAK_FP64_TFLOPS * 1e12))}
     # the fused scaled product timed live on its launch stream (eager launches)
+    if args.warmup == 0 and args.no_extra:
+        op.eigensolve(prec)  # the application needs a basis
     ctx.kernel_timing(True)
     for k in KERNELS:
         ctx.kernel_time(k)

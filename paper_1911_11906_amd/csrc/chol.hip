@@ -6,6 +6,7 @@
 // diagonal block, factored in LDS by one workgroup that also inverts it in
 // place.  Off-diagonal work is GEMM (matrix cores); a triangular solve at a
 // leaf is a GEMM with the stored leaf inverse.
+#include <algorithm>
 #include "internal.h"
 
 namespace {
@@ -241,6 +242,76 @@ hipError_t fl_trtri_inplace(hipStream_t s, int64_t n, double* L, int64_t ldl, co
     if ((e = fl_dgemm_tri(s, 0, 0, n2, n1, n1, 1.0, L + n1, ldl, L, ldl, 0.0, work, n2, 0, FL_KT_B_LOWER))) return e;
     if ((e = fl_dgemm_tri(s, 0, 0, n2, n1, n2, -1.0, L22, ldl, work, n2, 0.0, L + n1, ldl, 0, FL_KT_A_LOWER))) return e;
     return fl_fill(s, n1, n2, 0.0, L + n1 * ldl, ldl);
+}
+
+// ---------------------------------------------------------------- banded M
+// For a mass matrix whose half-bandwidth bw is small against n, the factor
+// keeps the band (a product L_ik L_jk^T is non-zero only if both lie in the
+// band), so everything runs on 128-row block rows of the band: q =
+// ceil(bw / 128) blocks below each diagonal block.  The diagonal blocks are
+// the same 128 x 128 leaves (factored and inverted in LDS); the rest are
+// GEMMs of one block row against at most q neighbouring block rows.
+
+// Left-looking block Cholesky restricted to the band: for each block column
+// j, S = A_jj - L_j,k L_j,k^T (k in [j-q, j)), L_jj = chol(S) with its
+// inverse, then the q blocks below: L_ij = (A_ij - L_i,k L_j,k^T) L_jj^-T.
+// Entries outside the band must be zero on entry and stay zero.
+hipError_t fl_potrf_band(hipStream_t s, int64_t n, int64_t q, double* A, int64_t lda, double* Linv, int64_t* info,
+                         double* work) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nbk = FL_DIV_UP(n, LB);
+    hipError_t e;
+    for (int64_t j = 0; j < nbk; ++j) {
+        const int64_t j0 = j * LB, nb = std::min<int64_t>(LB, n - j0);
+        const int64_t k0 = std::max<int64_t>(0, j - q) * LB, w = j0 - k0;  // columns of the left neighbours
+        double* Ajj = A + j0 + j0 * lda;
+        if (w > 0 && (e = fl_dgemm(s, 0, 1, nb, nb, w, -1.0, A + j0 + k0 * lda, lda, A + j0 + k0 * lda, lda, 1.0, Ajj,
+                                   lda, 1)))
+            return e;
+        potrf_leaf_kernel<<<1, LT, 0, s>>>(Ajj, lda, (int)nb, j0, Linv + j * LB * LB, info);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t r1 = j0 + nb, mr = std::min<int64_t>(q * LB, n - r1);  // rows of the blocks below
+        if (mr <= 0) continue;
+        if (w > 0 && (e = fl_dgemm(s, 0, 1, mr, nb, w, -1.0, A + r1 + k0 * lda, lda, A + j0 + k0 * lda, lda, 1.0,
+                                   A + r1 + j0 * lda, lda)))
+            return e;
+        if ((e = fl_trsm_rlt(s, mr, nb, Ajj, lda, Linv + j * LB * LB, A + r1 + j0 * lda, lda, work))) return e;
+    }
+    return hipSuccess;
+}
+
+// L X = B (B: n x m, overwritten by X) for the banded factor: block row i,
+// X_i = L_ii^-1 (B_i - L_i,k X_k), k in [i-q, i).  work: >= 128 m doubles.
+hipError_t fl_trsm_lln_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
+                            double* B, int64_t ldb, int64_t m, double* work) {
+    if (n <= 0 || m <= 0) return hipSuccess;
+    const int64_t nbk = FL_DIV_UP(n, LB);
+    hipError_t e;
+    for (int64_t i = 0; i < nbk; ++i) {
+        const int64_t i0 = i * LB, nb = std::min<int64_t>(LB, n - i0);
+        const int64_t k0 = std::max<int64_t>(0, i - q) * LB, w = i0 - k0;
+        if (w > 0 && (e = fl_dgemm(s, 0, 0, nb, m, w, -1.0, L + i0 + k0 * ldl, ldl, B + k0, ldb, 1.0, B + i0, ldb)))
+            return e;
+        if ((e = fl_trsm_lln(s, nb, m, L + i0 + i0 * ldl, ldl, Linv + i * LB * LB, B + i0, ldb, work))) return e;
+    }
+    return hipSuccess;
+}
+
+// L^T X = B (B: n x m, overwritten by X) for the banded factor: block row i
+// from the last, X_i = L_ii^-T (B_i - L_k,i^T X_k), k in (i, i+q].
+hipError_t fl_trsm_llt_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
+                            double* B, int64_t ldb, int64_t m, double* work) {
+    if (n <= 0 || m <= 0) return hipSuccess;
+    const int64_t nbk = FL_DIV_UP(n, LB);
+    hipError_t e;
+    for (int64_t i = nbk - 1; i >= 0; --i) {
+        const int64_t i0 = i * LB, nb = std::min<int64_t>(LB, n - i0);
+        const int64_t r1 = i0 + nb, w = std::min<int64_t>(q * LB, n - r1);  // rows of the blocks below
+        if (w > 0 && (e = fl_dgemm(s, 1, 0, nb, m, w, -1.0, L + r1 + i0 * ldl, ldl, B + r1, ldb, 1.0, B + i0, ldb)))
+            return e;
+        if ((e = fl_trsm_llt(s, nb, m, L + i0 + i0 * ldl, ldl, Linv + i * LB * LB, B + i0, ldb, work))) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t fl_trtri_leaves(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Linv) {

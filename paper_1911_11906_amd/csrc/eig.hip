@@ -364,11 +364,25 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     op->has_eig = 0;
     double* L = bL.as<double>();
     double* C = bC.as<double>();
+    // A mass matrix whose pattern is banded (FEM: half-bandwidth ~ the
+    // number of nodes across the mesh in its own numbering) keeps its band in
+    // the factor: factor and triangular solves then run on the q block rows
+    // below each 128 x 128 diagonal block only.
+    int64_t mbw = -1;
+    {
+        int rcb = fl_pattern_bandwidth(op, &mbw);
+        if (rcb) return rcb;
+    }
+    const int64_t qband = mbw >= 0 ? FL_DIV_UP(std::max<int64_t>(mbw, 1), 128) : -1;
+    const bool banded = qband > 0 && (qband + 1) * 128 <= n / 4;
     StageTimer tm(s);
     FL_HIP(ctx, tm.mark(FL_STAGE_POTRF));
     FL_HIP(ctx, hipMemcpyAsync(L, op->M, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
     FL_HIP(ctx, hipMemsetAsync(binfo.p, 0, sizeof(int64_t), s));
-    FL_HIP(ctx, fl_potrf(s, n, L, ld, blinv.as<double>(), binfo.as<int64_t>(), bwork.as<double>()));
+    if (banded)
+        FL_HIP(ctx, fl_potrf_band(s, n, qband, L, ld, blinv.as<double>(), binfo.as<int64_t>(), bwork.as<double>()));
+    else
+        FL_HIP(ctx, fl_potrf(s, n, L, ld, blinv.as<double>(), binfo.as<int64_t>(), bwork.as<double>()));
     int64_t piv = 0;
     FL_HIP(ctx, hipMemcpyAsync(&piv, binfo.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     FL_HIP(ctx, hipStreamSynchronize(s));
@@ -384,10 +398,24 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     // sparse product, and only the lower triangle of C = X Y, skipping X's
     // zero tiles (about half the work of two dense triangular solves);
     // V = X^T Z at the end is one GEMM.  Dense K: two triangular solves.
-    const bool sparse = op->rowptr && op->kval && op->nnz <= (n * n) / 64;
+    const bool sparse = !banded && op->rowptr && op->kval && op->nnz <= (n * n) / 64;
     DevBuf bXt, bY;
     int rc = FL_OK;
-    if (sparse) {
+    if (banded) {
+        // W = L^-1 K, then C = L^-1 W^T (= L^-1 K L^-T, symmetric): two
+        // banded substitutions; the lower triangle is mirrored so that C is
+        // exactly symmetric
+        FL_HIP(ctx, bY.alloc(sizeof(double) * (size_t)n * n));
+        double* Y = bY.as<double>();
+        FL_HIP(ctx, hipMemcpyAsync(C, op->K, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
+        FL_HIP(ctx, fl_trsm_lln_band(s, n, qband, L, ld, blinv.as<double>(), C, ld, n, bwork.as<double>()));
+        FL_HIP(ctx, fl_transpose(s, n, n, C, ld, Y, n));
+        FL_HIP(ctx, fl_trsm_lln_band(s, n, qband, L, ld, blinv.as<double>(), Y, n, n, bwork.as<double>()));
+        FL_HIP(ctx, fl_copy_matrix(s, n, n, Y, n, C, ld));
+        FL_HIP(ctx, fl_mirror_lower(s, n, C, ld));
+        FL_HIP(ctx, hipStreamSynchronize(s));
+        bY.release();
+    } else if (sparse) {
         FL_HIP(ctx, bXt.alloc(sizeof(double) * (size_t)n * n));
         FL_HIP(ctx, bY.alloc(sizeof(double) * (size_t)n * n));
         double* Xt = bXt.as<double>();
@@ -412,7 +440,9 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
         return rc;
     }
     FL_HIP(ctx, tm.mark(FL_STAGE_TRSM));
-    if (sparse) {
+    if (banded) {
+        FL_HIP(ctx, fl_trsm_llt_band(s, n, qband, L, ld, blinv.as<double>(), op->V, ld, n, bwork.as<double>()));
+    } else if (sparse) {
         // V = X^T Z (X^T upper triangular)
         double* Y = bY.as<double>();
         FL_HIP(ctx, fl_dgemm_tri(s, 1, 0, n, n, n, 1.0, L, ld, op->V, ld, 0.0, Y, n, 0, FL_KT_A_UPPER));

@@ -18,6 +18,7 @@
 // exactly zero pivot makes the count for that shift -1.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <queue>
 #include <string>
@@ -208,6 +209,29 @@ std::vector<int32_t> rcm_pinv(int64_t n, const std::vector<int32_t>& rowptr, con
 }
 
 // Numbering of the op's pattern with the smaller bandwidth (cached).
+int prepare_ordering(fl_op* op);
+
+}  // namespace
+
+int fl_pattern_bandwidth(fl_op* op, int64_t* bw) {
+    *bw = -1;
+    if (!op->rowptr || !op->colidx) return FL_OK;
+    if (op->natural_bw < 0) {
+        const int64_t n = op->n;
+        std::vector<int32_t> rowptr(n + 1), colidx(op->nnz);
+        FL_HIP(op->ctx, hipMemcpy(rowptr.data(), op->rowptr, 4 * (n + 1), hipMemcpyDeviceToHost));
+        FL_HIP(op->ctx, hipMemcpy(colidx.data(), op->colidx, 4 * op->nnz, hipMemcpyDeviceToHost));
+        int64_t b = 0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) b = std::max<int64_t>(b, std::abs(i - (int64_t)colidx[p]));
+        op->natural_bw = b;
+    }
+    *bw = op->natural_bw;
+    return FL_OK;
+}
+
+namespace {
+
 int prepare_ordering(fl_op* op) {
     fl_ctx* ctx = op->ctx;
     if (op->inert_pinv) return FL_OK;

@@ -57,6 +57,8 @@ struct fl_op {
     // (new index of each old one; device), and the bandwidth under it
     int32_t* inert_pinv = nullptr;
     int64_t inert_bw = -1;
+    // half-bandwidth of the pattern in its own numbering (-1: not computed)
+    int64_t natural_bw = -1;
     // captured application graphs (fl_apply_graph)
     std::vector<ApplyGraph*> graphs;
     uint64_t graph_clock = 0;
@@ -182,6 +184,17 @@ hipError_t fl_trsm_lln(hipStream_t s, int64_t k, int64_t m, const double* L, int
 hipError_t fl_trsm_llt(hipStream_t s, int64_t k, int64_t m, const double* L, int64_t ldl, const double* Linv,
                        double* B, int64_t ldb, double* work);
 hipError_t fl_trtri_leaves(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Linv);
+// Half-bandwidth max |i - j| of the op's pattern in its own numbering
+// (cached in op->natural_bw; inertia.hip).
+int fl_pattern_bandwidth(fl_op* op, int64_t* bw);
+// Banded mass matrix (q blocks of 128 rows below each diagonal block): the
+// factor, L X = B and L^T X = B on the band only (chol.hip).
+hipError_t fl_potrf_band(hipStream_t s, int64_t n, int64_t q, double* A, int64_t lda, double* Linv, int64_t* info,
+                         double* work);
+hipError_t fl_trsm_lln_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
+                            double* B, int64_t ldb, int64_t m, double* work);
+hipError_t fl_trsm_llt_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
+                            double* B, int64_t ldb, int64_t m, double* work);
 hipError_t fl_trtri_inplace(hipStream_t s, int64_t n, double* L, int64_t ldl, const double* Linv, double* work);
 hipError_t fl_symmetrize(hipStream_t s, int64_t n, double* A, int64_t lda);
 int fl_sygst_device(fl_ctx* ctx, int64_t n, const double* L, int64_t ldl, const double* Linv, double* K,
