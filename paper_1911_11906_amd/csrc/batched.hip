@@ -43,6 +43,7 @@ constexpr double EPS = 2.220446049250313e-16;
 
 struct BProb {
     int64_t n, ld;                                      // ld: of K, M and V
+    int64_t bw;                                         // half-bandwidth of M (n - 1: dense)
     const double* K;
     const double* M;
     double* V;
@@ -193,13 +194,18 @@ __device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n
 
 // Cholesky of the leading n x n of A (lower triangle used and overwritten).
 // Returns 0, or the 1-based index of the first non-positive pivot.
-__device__ __attribute__((noinline)) int wg_potrf(int n, double* A, int64_t lda, Lds& s) {
+// A of half-bandwidth bw (entries with |r - c| > bw zero): the factor keeps
+// the band, so each panel reads only the columns within bw to its left and
+// updates only the rows within bw below it.
+__device__ __attribute__((noinline)) int wg_potrf(int n, int bw, double* A, int64_t lda, Lds& s) {
     const int t = threadIdx.x;
     for (int j0 = 0; j0 < n; j0 += PB) {
         const int jb = min(PB, n - j0);
-        if (j0 > 0)
-            wg_gemm(false, true, n - j0, jb, j0, -1.0, A + j0, lda, A + j0, lda, 1.0, A + j0 + (int64_t)j0 * lda,
-                    lda, s);
+        const int re = min(n, j0 + jb + bw);  // rows of the panel's column block that can be non-zero
+        const int kl = max(0, j0 - bw);       // first column that row block j0 can reach
+        if (j0 > kl)
+            wg_gemm(false, true, re - j0, jb, j0 - kl, -1.0, A + j0 + (int64_t)kl * lda, lda,
+                    A + j0 + (int64_t)kl * lda, lda, 1.0, A + j0 + (int64_t)j0 * lda, lda, s);
         for (int e = t; e < jb * jb; e += BT) {
             const int r = e % jb, c = e / jb;
             s.D[r][c] = A[j0 + r + (int64_t)(j0 + c) * lda];
@@ -231,7 +237,7 @@ __device__ __attribute__((noinline)) int wg_potrf(int n, double* A, int64_t lda,
             if (r >= c) A[j0 + r + (int64_t)(j0 + c) * lda] = s.D[r][c];
         }
         // rows below the block: x L_jj^T = a
-        for (int r = j0 + jb + t; r < n; r += BT) {
+        for (int r = j0 + jb + t; r < re; r += BT) {
             double x[PB];
 #pragma unroll
             for (int c = 0; c < PB; ++c) {
@@ -252,7 +258,9 @@ __device__ __attribute__((noinline)) int wg_potrf(int n, double* A, int64_t lda,
 }
 
 // Solve L X = B in place (L lower, n x n; B n x nrhs).
-__device__ __attribute__((noinline)) void wg_trsm_ln(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
+// L of half-bandwidth bw: the updates below a block reach only the bw rows
+// under it.
+__device__ __attribute__((noinline)) void wg_trsm_ln(int n, int bw, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
     // Two-level blocking: PB-row blocks are solved and update only the rest
     // of their OB-row group (k = PB); each finished group then updates all
@@ -283,12 +291,15 @@ __device__ __attribute__((noinline)) void wg_trsm_ln(int n, int nrhs, const doub
                 }
             }
             gsync();
-            if (i0 + ib < oe)
-                wg_gemm(false, false, oe - i0 - ib, nrhs, ib, -1.0, L + i0 + ib + (int64_t)i0 * ldl, ldl, B + i0, ldb,
+            const int ue = min(oe, i0 + ib + bw);
+            if (i0 + ib < ue)
+                wg_gemm(false, false, ue - i0 - ib, nrhs, ib, -1.0, L + i0 + ib + (int64_t)i0 * ldl, ldl, B + i0, ldb,
                         1.0, B + i0 + ib, ldb, s);
         }
-        if (oe < n)
-            wg_gemm(false, false, n - oe, nrhs, oe - o0, -1.0, L + oe + (int64_t)o0 * ldl, ldl, B + o0, ldb, 1.0,
+        const int ge = min(n, oe + bw);
+        const int gk = max(o0, oe - bw);  // columns of the group that reach below it
+        if (oe < ge)
+            wg_gemm(false, false, ge - oe, nrhs, oe - gk, -1.0, L + oe + (int64_t)gk * ldl, ldl, B + gk, ldb, 1.0,
                     B + oe, ldb, s);
     }
 }
@@ -296,7 +307,7 @@ __device__ __attribute__((noinline)) void wg_trsm_ln(int n, int nrhs, const doub
 // Solve L^T X = B in place (two-level blocking as in wg_trsm_ln, from the
 // last group up: within a group k = PB, the rows above it get one k = OB
 // product).
-__device__ __attribute__((noinline)) void wg_trsm_lt(int n, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
+__device__ __attribute__((noinline)) void wg_trsm_lt(int n, int bw, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
     const int ngrp = (n + OB - 1) / OB;
     for (int gi = ngrp - 1; gi >= 0; --gi) {
@@ -326,11 +337,16 @@ __device__ __attribute__((noinline)) void wg_trsm_lt(int n, int nrhs, const doub
                 }
             }
             gsync();
-            if (i0 > o0)
-                wg_gemm(true, false, i0 - o0, nrhs, ib, -1.0, L + i0 + (int64_t)o0 * ldl, ldl, B + i0, ldb, 1.0,
-                        B + o0, ldb, s);
+            const int us = max(o0, i0 - bw);  // rows above the block that it reaches
+            if (i0 > us)
+                wg_gemm(true, false, i0 - us, nrhs, ib, -1.0, L + i0 + (int64_t)us * ldl, ldl, B + i0, ldb, 1.0,
+                        B + us, ldb, s);
         }
-        if (o0 > 0) wg_gemm(true, false, o0, nrhs, oe - o0, -1.0, L + o0, ldl, B + o0, ldb, 1.0, B, ldb, s);
+        const int gs = max(0, o0 - bw);
+        const int gk = min(oe, o0 + bw);  // rows of the group that reach above it
+        if (o0 > gs)
+            wg_gemm(true, false, o0 - gs, nrhs, gk - o0, -1.0, L + o0 + (int64_t)gs * ldl, ldl, B + o0, ldb, 1.0,
+                    B + gs, ldb, s);
     }
 }
 
@@ -1432,13 +1448,14 @@ __device__ int64_t solve_one(const BProb& p, Lds& s) {
             W[i + (int64_t)j * n] = p.K[i + j * ld];
         }
     gsync();
-    const int piv = wg_potrf(n, L, n, s);
+    const int bw = (int)min(p.bw, p.n - 1);
+    const int piv = wg_potrf(n, bw, L, n, s);
     if (piv) return piv;
-    wg_trsm_ln(n, n, L, n, W, n, s);  // W = L^-1 K
+    wg_trsm_ln(n, bw, n, L, n, W, n, s);  // W = L^-1 K
     for (int j = 0; j < n; ++j)
         for (int i = t; i < n; i += BT) A[i + (int64_t)j * n] = W[j + (int64_t)i * n];
     gsync();
-    wg_trsm_ln(n, n, L, n, A, n, s);  // A = L^-1 K L^-T
+    wg_trsm_ln(n, bw, n, L, n, A, n, s);  // A = L^-1 K L^-T
     for (int j = 0; j < n; ++j)
         for (int i = j + 1 + t; i < n; i += BT) {
             const double v = 0.5 * (A[i + (int64_t)j * n] + A[j + (int64_t)i * n]);
@@ -1454,7 +1471,7 @@ __device__ int64_t solve_one(const BProb& p, Lds& s) {
     gsync();
     if (dc) return -(int64_t)dc;
     wg_ormtr(n, A, n, p.tau, Z, n, W, s);
-    wg_trsm_lt(n, n, L, n, Z, n, s);  // V = L^-T Z
+    wg_trsm_lt(n, bw, n, L, n, Z, n, s);  // V = L^-T Z
     for (int i = t; i < n; i += BT) {
         const double di = s.dd[i];
         int r = 0;
@@ -1539,6 +1556,12 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         BProb& b = hp[i];
         b.n = n;
         b.ld = op->ld;
+        {
+            int64_t bw = -1;
+            int rcb = fl_pattern_bandwidth(op, &bw);
+            if (rcb) return rcb;
+            b.bw = bw >= 0 ? bw : n - 1;  // no pattern: dense
+        }
         b.K = op->K;
         b.M = op->M;
         b.V = op->V;

@@ -21,7 +21,11 @@ constexpr int LT = 1024; // threads of the leaf kernel
 // which uses only row i of X: eight lanes own row i (lane p keeps X_ik for
 // k = p mod 8 in registers) and split each sum, so no workgroup barrier is
 // needed.  L is only read.
-__device__ void invert_lower_rows(const double* L, double* out, int t) {
+// rdiag: 1 / L_jj (LB entries).  The sums run over every k without a
+// condition: at step j the registers hold X_ik only for k in (j, i] and zero
+// elsewhere (entries are set at step k = j only for j <= i), so the other
+// products vanish, and the LDS reads of a step issue back to back.
+__device__ void invert_lower_rows(const double* L, const double* rdiag, double* out, int t) {
     const int i = t >> 3, part = t & 7;  // 1024 threads: 128 rows x 8 lanes
     double X[LB / 8];
 #pragma unroll
@@ -30,13 +34,12 @@ __device__ void invert_lower_rows(const double* L, double* out, int t) {
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < LB / 8; ++q) {
-            const int k = 8 * q + part;
-            if (k > j && k <= i) acc += X[q] * L[k + j * LB];
+            acc += X[q] * L[8 * q + part + j * LB];
         }
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
         acc += __shfl_xor(acc, 4, 64);
-        const double x = (j == i) ? 1.0 / L[j + j * LB] : -acc / L[j + j * LB];
+        const double x = (j == i) ? rdiag[j] : -acc * rdiag[j];
         if (j <= i && part == (j & 7)) {
 #pragma unroll
             for (int q = 0; q < LB / 8; ++q)
@@ -61,6 +64,7 @@ __global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, 
                                                         double* Linv, int64_t* info) {
     __shared__ double S[LB * LB];  // column-major with ld LB (128 KB of the 160 KB LDS)
     __shared__ double y[LB];
+    __shared__ double colj[LB];    // pivot column of the current step (read-only while S is updated)
     const int t = threadIdx.x;
     for (int e = t; e < LB * LB; e += LT) {
         int i = e % LB, j = e / LB;
@@ -81,17 +85,25 @@ __global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, 
             bad = true;
             S[j + j * LB] = deff;
         }
+        // the pivot column goes to its own array: the updates below then
+        // read it without any possible overlap with the entries they write
+        if (t < LB) colj[t] = S[t + j * LB];
+        __syncthreads();
         const double inv = 1.0 / deff;
         // thread t updates row t % LB of the columns j+1+(t / LB), step 8
         // (fixed row, no index division)
         const int i = t & (LB - 1);
         if (i > j && i < nb) {
-            const double sij = S[i + j * LB] * inv;
-            for (int cc = j + 1 + (t >> 7); cc <= i; cc += LT / LB) S[i + cc * LB] -= sij * S[cc + j * LB];
+            const double sij = colj[i] * inv;
+#pragma unroll 4
+            for (int cc = j + 1 + (t >> 7); cc <= i; cc += LT / LB) S[i + cc * LB] -= sij * colj[cc];
         }
         __syncthreads();
     }
-    if (t < LB) y[t] = sqrt(S[t + t * LB]);
+    if (t < LB) {
+        y[t] = sqrt(S[t + t * LB]);
+        colj[t] = 1.0 / y[t];  // reciprocal diagonal of L for the inverse
+    }
     __syncthreads();
     for (int e = t; e < LB * LB; e += LT) {
         int i = e % LB, j = e / LB;
@@ -103,13 +115,14 @@ __global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, 
         int i = e % nb, j = e / nb;
         A[i + (int64_t)j * lda] = (i >= j) ? S[i + j * LB] : 0.0;
     }
-    invert_lower_rows(S, Linv, t);
+    invert_lower_rows(S, colj, Linv, t);
 }
 
 // Inverses of the 128 x 128 diagonal blocks of an existing lower factor L
 // (one workgroup per block).
 __global__ __launch_bounds__(LT) void trtri_leaves_kernel(int64_t n, const double* L, int64_t ldl, double* Linv) {
     __shared__ double S[LB * LB];
+    __shared__ double rd[LB];
     const int t = threadIdx.x;
     const int64_t off = (int64_t)blockIdx.x * LB;
     const int nb = (int)((n - off) < LB ? (n - off) : LB);
@@ -118,7 +131,9 @@ __global__ __launch_bounds__(LT) void trtri_leaves_kernel(int64_t n, const doubl
         S[i + j * LB] = (i < nb && j < nb) ? ((i >= j) ? L[off + i + (off + j) * ldl] : 0.0) : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
-    invert_lower_rows(S, Linv + (int64_t)blockIdx.x * LB * LB, t);
+    if (t < LB) rd[t] = 1.0 / S[t + t * LB];
+    __syncthreads();
+    invert_lower_rows(S, rd, Linv + (int64_t)blockIdx.x * LB * LB, t);
 }
 
 __global__ void symmetrize_kernel(int64_t n, double* A, int64_t lda) {
