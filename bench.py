@@ -183,28 +183,46 @@ def traffic_for(kernel: str):
     return None
 
 
-def eig_roofline_ms(n: int, prec: str, refine_steps: int) -> float:
+def half_bandwidth(mesh) -> int:
+    """max |i - j| over the stored entries of the mesh's pencil (the
+    element couplings of the degrees of freedom, in their own numbering)."""
+    import numpy as np
+    d = np.asarray(mesh.dof_of_node())[np.asarray(mesh.conn)]
+    d = np.where(d >= 0, d, np.nan)
+    return int(np.nanmax(np.nanmax(d, axis=1) - np.nanmin(d, axis=1)))
+
+
+def eig_roofline_ms(n: int, prec: str, refine_steps: int, bw: int = -1) -> float:
     """Stage-wise roofline time of the eigensolve: each stage's algorithmic
     flops at the datasheet peak of its arithmetic (FP64: Cholesky n^3/3,
     standard form n^3, band reduction 4/3 n^3, divide and conquer 4/3 n^3,
     back-substitution n^3; both back-transforms 2 n^3 each, FP32 in mixed
-    mode; refinement 4 n^3 per step in FP64)."""
+    mode; refinement 4 n^3 per step in FP64).  A mass matrix of
+    half-bandwidth bw that the library takes on its band (q = ceil(bw/128),
+    (q + 1) 128 <= n/4) counts the banded algorithms instead: Cholesky
+    n (128 q)^2, and 2 n^2 128 (q + 1) for each of the three block
+    substitutions (two for the standard form, one for the back-substitution)."""
     n3 = float(n) ** 3
-    f64 = (1 / 3 + 1 + 4 / 3 + 4 / 3 + 1) * n3 + 4.0 * n3 * refine_steps
+    q = -(-max(bw, 1) // 128) if bw >= 0 else -1
+    if q > 0 and (q + 1) * 128 <= n // 4:
+        chol_sygst_trsm = n * (128.0 * q) ** 2 + 3 * 2.0 * n * n * 128 * (q + 1)
+    else:
+        chol_sygst_trsm = (1 / 3 + 1 + 1) * n3
+    f64 = chol_sygst_trsm + (4 / 3 + 4 / 3) * n3 + 4.0 * n3 * refine_steps
     bt = 4.0 * n3
     t = f64 / (PEAK_FP64_TFLOPS * 1e12)
     t += bt / ((PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS) * 1e12)
     return t * 1e3
 
 
-def time_eigensolves(op, prec: str, reps: int = 3):
+def time_eigensolves(op, prec: str, reps: int = 3, bw: int = -1):
     import numpy as np
     op.eigensolve(prec)  # warm-up
     infos = [op.eigensolve(prec) for _ in range(reps)]
     ms = float(np.median([i["total_ms"] for i in infos]))
     n = op.n
     return {"s": ms / 1e3, "tflops_nominal": 9.0 * n ** 3 / (ms / 1e3) / 1e12,
-            "roofline_frac": eig_roofline_ms(n, prec, infos[0]["refine_iters"]) / ms,
+            "roofline_frac": eig_roofline_ms(n, prec, infos[0]["refine_iters"], bw) / ms,
             "refine_iters": infos[0]["refine_iters"],
             "stage_ms": {k: float(np.median([i["stage_ms"][k] for i in infos])) for k in infos[0]["stage_ms"]}}
 
@@ -280,11 +298,11 @@ def main():
     if not args.no_extra:
         extra["peaks_measured"] = ctx.measure_peaks()
         # the eigensolve alone: both precisions on both n = 16384 meshes
-        eig = {"q1_square": {p: time_eigensolves(op, p) for p in ("fp64", "mixed")}}
+        eig = {"q1_square": {p: time_eigensolves(op, p, bw=half_bandwidth(mesh)) for p in ("fp64", "mixed")}}
         op.eigensolve(prec)  # leave the timed precision's basis in place
         pm = inputs.p1_polygon_with_holes(16384)
         op3 = Operator.assemble(ctx, pm)
-        eig["p1_polygon"] = {p: time_eigensolves(op3, p) for p in ("fp64", "mixed")}
+        eig["p1_polygon"] = {p: time_eigensolves(op3, p, bw=half_bandwidth(pm)) for p in ("fp64", "mixed")}
         op3.close()
         for mk in eig:
             eig[mk]["mixed_speedup_over_fp64"] = eig[mk]["fp64"]["s"] / eig[mk]["mixed"]["s"]
