@@ -80,6 +80,18 @@ struct Lds {
 // (A plain workgroup barrier on gfx950 waits for LDS traffic only: a store
 // still in flight, or an L1 line fetched before another wave's store, could
 // otherwise be read after it.)
+// Global memory seen as such.  A generic pointer makes every access a flat
+// one; flat accesses may complete out of order with respect to LDS ones, so
+// while any is in flight the compiler can only wait for all loads (and LDS
+// reads) at once, and a prefetch no longer overlaps the work before it.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) int gint;
+
+// Compiler-only barrier at the top of a per-thread loop over right-hand
+// sides: the LDS block it reads is the same in every iteration, and hoisted
+// out of the loop it would take the whole block into registers (and spill).
+__device__ inline void keep_lds_reads_here() { __asm__ volatile("" ::: "memory"); }
+
 __device__ inline void gsync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);
@@ -105,9 +117,12 @@ __device__ double wg_sum(double v, Lds& s) {
 // + 4 r] and the 16 lanes of a row group store consecutive rows.  The next
 // k-slab is loaded into registers (unconditionally, indices clamped into the
 // operands) while the current one is multiplied from LDS.
-__device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int64_t lda,
-                        const double* B, int64_t ldb, double beta, double* C, int64_t ldc, Lds& s) {
+__device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* Ag, int64_t lda,
+                        const double* Bg, int64_t ldb, double beta, double* Cg, int64_t ldc, Lds& s) {
     if (m <= 0 || n <= 0) return;
+    const gdouble* A = (const gdouble*)Ag;
+    const gdouble* B = (const gdouble*)Bg;
+    gdouble* C = (gdouble*)Cg;
     constexpr int NA = TM * TK / BT, NB = TN * TK / BT;
     static_assert(NA * BT == TM * TK && NB * BT == TN * TK && BT == 512, "eight waves, 64 x 128 tiles");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -174,6 +189,19 @@ __device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n
                         acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[tj], fb[ti], acc[ti][tj], 0, 0, 0);
             }
         }
+        // C: the 16 old values of this lane (clamped into C, unconditional)
+        // loaded together before any store, then the valid ones written
+        double cold[2][2][4];
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = min(i0 + wi * 32 + 16 * ti + lc, m - 1);
+                    const int gj = min(j0 + wj * 32 + 16 * tj + lr + 4 * r, n - 1);
+                    cold[ti][tj][r] = (beta == 0.0) ? 0.0 : C[gi + (int64_t)gj * ldc];
+                }
 #pragma unroll
         for (int ti = 0; ti < 2; ++ti) {
             const int gi = i0 + wi * 32 + 16 * ti + lc;
@@ -184,8 +212,7 @@ __device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n
                 for (int r = 0; r < 4; ++r) {
                     const int gj = j0 + wj * 32 + 16 * tj + lr + 4 * r;
                     if (gj >= n) continue;
-                    double* cp = C + gi + (int64_t)gj * ldc;
-                    *cp = (beta == 0.0) ? alpha * acc[ti][tj][r] : alpha * acc[ti][tj][r] + beta * *cp;
+                    C[gi + (int64_t)gj * ldc] = alpha * acc[ti][tj][r] + beta * cold[ti][tj][r];
                 }
         }
     }
@@ -199,6 +226,7 @@ __device__ __attribute__((noinline)) void wg_gemm(bool ta, bool tb, int m, int n
 // updates only the rows within bw below it.
 __device__ __attribute__((noinline)) int wg_potrf(int n, int bw, double* A, int64_t lda, Lds& s) {
     const int t = threadIdx.x;
+    gdouble* gA = (gdouble*)A;
     for (int j0 = 0; j0 < n; j0 += PB) {
         const int jb = min(PB, n - j0);
         const int re = min(n, j0 + jb + bw);  // rows of the panel's column block that can be non-zero
@@ -208,7 +236,7 @@ __device__ __attribute__((noinline)) int wg_potrf(int n, int bw, double* A, int6
                     A + j0 + (int64_t)kl * lda, lda, 1.0, A + j0 + (int64_t)j0 * lda, lda, s);
         for (int e = t; e < jb * jb; e += BT) {
             const int r = e % jb, c = e / jb;
-            s.D[r][c] = A[j0 + r + (int64_t)(j0 + c) * lda];
+            s.D[r][c] = gA[j0 + r + (int64_t)(j0 + c) * lda];
         }
         if (t == 0) s.ival[0] = 0;
         __syncthreads();
@@ -234,23 +262,26 @@ __device__ __attribute__((noinline)) int wg_potrf(int n, int bw, double* A, int6
         if (bad) return bad;
         for (int e = t; e < jb * jb; e += BT) {
             const int r = e % jb, c = e / jb;
-            if (r >= c) A[j0 + r + (int64_t)(j0 + c) * lda] = s.D[r][c];
+            if (r >= c) gA[j0 + r + (int64_t)(j0 + c) * lda] = s.D[r][c];
         }
         // rows below the block: x L_jj^T = a
+        // (the row's jb entries are loaded before the first is used)
         for (int r = j0 + jb + t; r < re; r += BT) {
+            keep_lds_reads_here();
+            gdouble* ar = gA + r + (int64_t)j0 * lda;
             double x[PB];
 #pragma unroll
-            for (int c = 0; c < PB; ++c) {
-                if (c < jb) {
-                    double v = A[r + (int64_t)(j0 + c) * lda];
+            for (int c = 0; c < PB; ++c) x[c] = ar[(int64_t)(c < jb ? c : 0) * lda];
 #pragma unroll
-                    for (int q = 0; q < c; ++q) v -= x[q] * s.D[c][q];
-                    x[c] = v / s.D[c][c];
-                    A[r + (int64_t)(j0 + c) * lda] = x[c];
-                } else {
-                    x[c] = 0.0;
-                }
+            for (int c = 0; c < PB; ++c) {
+                double v = x[c];
+#pragma unroll
+                for (int q = 0; q < c; ++q) v -= x[q] * s.D[c][q];
+                x[c] = (c < jb) ? v / s.D[c][c] : 0.0;
             }
+#pragma unroll
+            for (int c = 0; c < PB; ++c)
+                if (c < jb) ar[(int64_t)c * lda] = x[c];
         }
         gsync();
     }
@@ -262,6 +293,8 @@ __device__ __attribute__((noinline)) int wg_potrf(int n, int bw, double* A, int6
 // under it.
 __device__ __attribute__((noinline)) void wg_trsm_ln(int n, int bw, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
+    const gdouble* gL = (const gdouble*)L;
+    gdouble* gB = (gdouble*)B;
     // Two-level blocking: PB-row blocks are solved and update only the rest
     // of their OB-row group (k = PB); each finished group then updates all
     // rows below it in one product with k = OB, so the trailing rows are
@@ -272,23 +305,26 @@ __device__ __attribute__((noinline)) void wg_trsm_ln(int n, int bw, int nrhs, co
             const int ib = min(PB, oe - i0);
             for (int e = t; e < PB * PB; e += BT) {
                 const int r = e % PB, c = e / PB;
-                s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
+                s.D[r][c] = (r < ib && c <= r) ? gL[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
             }
             __syncthreads();
+            // (the column's ib entries are loaded before the first is used)
             for (int j = t; j < nrhs; j += BT) {
+                keep_lds_reads_here();
+                gdouble* bj = gB + i0 + (int64_t)j * ldb;
                 double x[PB];
 #pragma unroll
-                for (int r = 0; r < PB; ++r) {
-                    if (r < ib) {
-                        double v = B[i0 + r + (int64_t)j * ldb];
+                for (int r = 0; r < PB; ++r) x[r] = bj[r < ib ? r : 0];
 #pragma unroll
-                        for (int q = 0; q < r; ++q) v -= s.D[r][q] * x[q];
-                        x[r] = v / s.D[r][r];
-                        B[i0 + r + (int64_t)j * ldb] = x[r];
-                    } else {
-                        x[r] = 0.0;
-                    }
+                for (int r = 0; r < PB; ++r) {
+                    double v = x[r];
+#pragma unroll
+                    for (int q = 0; q < r; ++q) v -= s.D[r][q] * x[q];
+                    x[r] = (r < ib) ? v / s.D[r][r] : 0.0;
                 }
+#pragma unroll
+                for (int r = 0; r < PB; ++r)
+                    if (r < ib) bj[r] = x[r];
             }
             gsync();
             const int ue = min(oe, i0 + ib + bw);
@@ -309,6 +345,8 @@ __device__ __attribute__((noinline)) void wg_trsm_ln(int n, int bw, int nrhs, co
 // product).
 __device__ __attribute__((noinline)) void wg_trsm_lt(int n, int bw, int nrhs, const double* L, int64_t ldl, double* B, int64_t ldb, Lds& s) {
     const int t = threadIdx.x;
+    const gdouble* gL = (const gdouble*)L;
+    gdouble* gB = (gdouble*)B;
     const int ngrp = (n + OB - 1) / OB;
     for (int gi = ngrp - 1; gi >= 0; --gi) {
         const int o0 = gi * OB, oe = min(n, o0 + OB);
@@ -317,24 +355,27 @@ __device__ __attribute__((noinline)) void wg_trsm_lt(int n, int bw, int nrhs, co
             const int i0 = o0 + bi * PB, ib = min(PB, oe - i0);
             for (int e = t; e < PB * PB; e += BT) {
                 const int r = e % PB, c = e / PB;
-                s.D[r][c] = (r < ib && c <= r) ? L[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
+                s.D[r][c] = (r < ib && c <= r) ? gL[i0 + r + (int64_t)(i0 + c) * ldl] : 0.0;
             }
             __syncthreads();
+            // (the column's ib entries are loaded before the first is used;
+            // D is zero outside its ib x ib block, so x[q >= ib] = 0 drops out)
             for (int j = t; j < nrhs; j += BT) {
+                keep_lds_reads_here();
+                gdouble* bj = gB + i0 + (int64_t)j * ldb;
                 double x[PB];
 #pragma unroll
-                for (int r = PB - 1; r >= 0; --r) {
-                    if (r < ib) {
-                        double v = B[i0 + r + (int64_t)j * ldb];
+                for (int r = 0; r < PB; ++r) x[r] = bj[r < ib ? r : 0];
 #pragma unroll
-                        for (int q = r + 1; q < PB; ++q)
-                            if (q < ib) v -= s.D[q][r] * x[q];
-                        x[r] = v / s.D[r][r];
-                        B[i0 + r + (int64_t)j * ldb] = x[r];
-                    } else {
-                        x[r] = 0.0;
-                    }
+                for (int r = PB - 1; r >= 0; --r) {
+                    double v = x[r];
+#pragma unroll
+                    for (int q = r + 1; q < PB; ++q) v -= s.D[q][r] * x[q];
+                    x[r] = (r < ib) ? v / s.D[r][r] : 0.0;
                 }
+#pragma unroll
+                for (int r = 0; r < PB; ++r)
+                    if (r < ib) bj[r] = x[r];
             }
             gsync();
             const int us = max(o0, i0 - bw);  // rows above the block that it reaches
@@ -357,8 +398,8 @@ __device__ __attribute__((noinline)) void wg_trsm_lt(int n, int bw, int nrhs, co
 // Householder reflector of x = A[g0 : g0 + m, c] (x[0] = alpha at row g0):
 // x[1:] is scaled in place into v[1:] (also copied to the LDS vector v,
 // indexed from row g0).  Returns tau; beta goes to *beta.
-__device__ double wg_house(int n, int64_t g0, int m, double* col, double alpha, double* v, double* beta,
-                           Lds& s) {
+template <class Ptr>
+__device__ double wg_house(int n, int64_t g0, int m, Ptr col, double alpha, double* v, double* beta, Lds& s) {
     const int t = threadIdx.x;
     double loc = 0.0;
 #pragma unroll
@@ -415,26 +456,29 @@ __device__ void wg_make_w(int n, int64_t g0, int m, double tk, const double (&ac
 // s.dd and s.ee.  One pass over the trailing matrix per step: the rank-2
 // update of step k, A22 -= v w^T + w v^T, is fused with the product
 // A22' v' of step k+1 (A22' = A22 without its first row and column).
-// The streamed matrix is addressed as global memory (a generic pointer would
-// make every access a flat one, counted against the LDS counter as well, and
-// the compiler then drains all loads before the first store of a chunk).
-typedef __attribute__((address_space(1))) double gdouble;
+// The streamed matrix is addressed as global memory (gdouble).
 
 // Rows t + q BT (q < RPT) of columns g0 + j0 .. g0 + j0 + SU - 1.  The loads
-// are unconditional, from a row and column clamped into the matrix, so none
-// sits in a branch; entries that are not the caller's (rows it does not own,
-// columns j >= m) are never used.
+// are unconditional within a wave, from a row and column clamped into the
+// matrix; entries that are not the caller's (rows it does not own, columns
+// j >= m) are never used.  A wave whose rows in slot q all lie above the
+// trailing block (rows <= g0) loads nothing there.
 __device__ inline void sytrd_load_chunk(const gdouble* A, int64_t lda, int64_t g0, int j0, int m, int n,
                                         double (&buf)[SU][RPT]) {
     const int t = threadIdx.x;
+    const int wlast = __builtin_amdgcn_readfirstlane(t | 63);  // last row of this wave in slot 0
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
-        const int j = (j0 + u < m) ? j0 + u : m - 1;
-        const gdouble* col = A + (g0 + j) * lda;
+    for (int q = 0; q < RPT; ++q) {
+        if (wlast + q * BT > g0) {
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int g = t + q * BT;
-            buf[u][q] = col[g < n ? g : n - 1];
+            for (int u = 0; u < SU; ++u) {
+                const int j = (j0 + u < m) ? j0 + u : m - 1;
+                const int g = t + q * BT;
+                buf[u][q] = A[(g0 + j) * lda + (g < n ? g : n - 1)];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < SU; ++u) buf[u][q] = 0.0;
         }
     }
 }
@@ -636,9 +680,10 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
 }
 
 // Blocked variant for n >= SYTRD_BLK_MIN: the rank-2 updates of up to NBB
-// consecutive steps stay pending in P = [V | W] (global, n x 2 NBB, ld n,
-// zeros above each vector's first row) and are applied to the trailing
-// matrix in two workgroup products every NBB steps.  A step sees the current
+// consecutive steps stay pending in P = [V | W | V] (global, n x 3 NBB,
+// ld n, zeros above each vector's first row) and are applied to the
+// trailing matrix every NBB steps in one workgroup product with k = 2 NBB,
+// [V W] [W V]^T (the two column ranges of P that start at 0 and at NBB).  A step sees the current
 // matrix through them: its column gets the pending updates before the
 // Householder step, and the product with the new v is formed from the stale
 // matrix (one read-only pass instead of a read-write pass) and corrected by
@@ -650,7 +695,7 @@ constexpr int PU = 8;  // pending pairs read per batch of loads
 // Entries of pending pairs i0 .. i0+PU-1 (clamped to np-1) at this thread's
 // rows (clamped to n-1): all loads issued before any is used, so a batch
 // costs one memory latency instead of PU.
-__device__ inline void pend_rows(const double* PV, const double* PW, int n, int np, int i0,
+__device__ inline void pend_rows(const gdouble* PV, const gdouble* PW, int n, int np, int i0,
                                  double (&pv)[PU][RPT], double (&pw)[PU][RPT]) {
     const int t = threadIdx.x;
 #pragma unroll
@@ -666,17 +711,21 @@ __device__ inline void pend_rows(const double* PV, const double* PW, int n, int 
     }
 }
 
-__device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t lda, double* tau, double* P, Lds& s) {
+__device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* Ag, int64_t lda, double* taug, double* P, Lds& s) {
     const int t = threadIdx.x;
-    double* PV = P;                    // column i: v_i (global rows)
-    double* PW = P + (int64_t)NBB * n; // column i: w_i
+    gdouble* A = (gdouble*)Ag;
+    gdouble* tau = (gdouble*)taug;
+    gdouble* PV = (gdouble*)P;           // column i: v_i (global rows)
+    gdouble* PW = PV + (int64_t)NBB * n; // column i: w_i
     int np = 0;                        // pending pairs
     // append (v, w) of the reflector whose first row is r1 (v, w indexed from r1)
     auto append = [&](int r1, const double* v, const double* w) {
         for (int g = t; g < n; g += BT) {
             const bool in = g >= r1;
-            PV[g + (int64_t)np * n] = in ? v[g - r1] : 0.0;
+            const double vg = in ? v[g - r1] : 0.0;
+            PV[g + (int64_t)np * n] = vg;
             PW[g + (int64_t)np * n] = in ? w[g - r1] : 0.0;
+            PW[g + (int64_t)(NBB + np) * n] = vg;
         }
         ++np;
         gsync();
@@ -685,8 +734,15 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t
     auto flush = [&](int f) {
         if (np > 0 && f < n) {
             const int mm = n - f;
-            wg_gemm(false, true, mm, mm, np, -1.0, PV + f, n, PW + f, n, 1.0, A + f + (int64_t)f * lda, lda, s);
-            wg_gemm(false, true, mm, mm, np, -1.0, PW + f, n, PV + f, n, 1.0, A + f + (int64_t)f * lda, lda, s);
+            double* pv = P + f;
+            double* pw = P + (int64_t)NBB * n + f;
+            double* a = Ag + f + (int64_t)f * lda;
+            if (np == NBB) {
+                wg_gemm(false, true, mm, mm, 2 * NBB, -1.0, pv, n, pw, n, 1.0, a, lda, s);
+            } else {
+                wg_gemm(false, true, mm, mm, np, -1.0, pv, n, pw, n, 1.0, a, lda, s);
+                wg_gemm(false, true, mm, mm, np, -1.0, pw, n, pv, n, 1.0, a, lda, s);
+            }
         }
         np = 0;
     };
@@ -707,7 +763,7 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t
         for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
         for (int j = 1; j < n; ++j) {
             const double vj = s.va[0][j - 1];
-            const double* col = A + (int64_t)j * lda;
+            const gdouble* col = A + (int64_t)j * lda;
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int g = t + q * BT;
@@ -717,7 +773,7 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t
         wg_make_w(n, 1, n - 1, tk, acc, s.va[0], s.wa[0], s);
         append(1, s.va[0], s.wa[0]);
     }
-    const gdouble* gA = (const gdouble*)A;
+    const gdouble* gA = A;
     for (int k = 0; k < n - 3; ++k) {
         const int nxt = (k + 1) & 1;
         const int64_t g0 = k + 1;  // column of reflector k+1, first row/column of A22
@@ -732,7 +788,7 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* A, int64_t
                 r0[NBB + t] = PW[g0 + (int64_t)t * n];
             }
             __syncthreads();
-            double* c0 = A + g0 * lda;
+            gdouble* c0 = A + g0 * lda;
             double a[RPT];
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
@@ -893,6 +949,8 @@ __device__ __attribute__((noinline)) void wg_ormtr(int n, const double* A, int64
     const int t = threadIdx.x;
     const int nref = n - 2;
     if (nref <= 0) return;
+    const gdouble* gA = (const gdouble*)A;
+    const gdouble* gtau = (const gdouble*)tau;
     // Block reflectors of QW = 4 PB reflectors when the n x n work array has
     // room (one pass over Z per 128 reflectors instead of per 32), else PB.
     // T of a wide block: its PB x PB diagonal blocks by the column recurrence
@@ -905,16 +963,28 @@ __device__ __attribute__((noinline)) void wg_ormtr(int n, const double* A, int64
         const int k0 = bi * W, nb = min(W, nref - k0);
         const int rows = n - k0 - 1;  // rows k0+1 .. n-1
         double* Vb = work;                          // rows x nb
+        gdouble* gV = (gdouble*)Vb;
         double* Tm = Vb + (int64_t)rows * W;        // W x W
         double* Gm = Tm + W * W;                    // W x W
         double* Xm = Gm + W * W;                    // W x PB
         double* Wt = Xm + W * PB;                   // nb x n
         double* Wt2 = Wt + (int64_t)W * n;          // nb x n
-        for (int c = 0; c < nb; ++c)
-            for (int rr = t; rr < rows; rr += BT)
-                Vb[rr + (int64_t)c * rows] =
-                    rr < c ? 0.0 : (rr == c ? 1.0 : A[(k0 + 1 + rr) + (int64_t)(k0 + c) * lda]);
-        for (int e = t; e < W * W; e += BT) Tm[e] = 0.0;
+        // V of the block, eight columns' loads in flight before their stores
+        for (int c0 = 0; c0 < nb; c0 += 8)
+            for (int rr = t; rr < rows; rr += BT) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = min(c0 + u, nb - 1);
+                    v[u] = gA[(k0 + 1 + rr) + (int64_t)(k0 + c) * lda];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + u;
+                    if (c < nb) gV[rr + (int64_t)c * rows] = rr < c ? 0.0 : (rr == c ? 1.0 : v[u]);
+                }
+            }
+        for (int e = t; e < W * W; e += BT) ((gdouble*)Tm)[e] = 0.0;
         gsync();
         wg_gemm(true, false, nb, nb, rows, 1.0, Vb, rows, Vb, rows, 0.0, Gm, W, s);
         for (int c0 = 0; c0 < nb; c0 += PB) {
@@ -923,10 +993,10 @@ __device__ __attribute__((noinline)) void wg_ormtr(int n, const double* A, int64
             for (int e = t; e < PB * PB; e += BT) s.D[e % PB][e / PB] = 0.0;
             __syncthreads();
             for (int c = 0; c < sb; ++c) {
-                const double tc = tau[k0 + c0 + c];
+                const double tc = gtau[k0 + c0 + c];
                 double acc = 0.0;
                 if (t < c) {
-                    for (int q = t; q < c; ++q) acc += s.D[t][q] * Gm[(c0 + q) + (int64_t)(c0 + c) * W];
+                    for (int q = t; q < c; ++q) acc += s.D[t][q] * ((const gdouble*)Gm)[(c0 + q) + (int64_t)(c0 + c) * W];
                 }
                 __syncthreads();
                 if (t < c) s.D[t][c] = -tc * acc;
@@ -935,7 +1005,7 @@ __device__ __attribute__((noinline)) void wg_ormtr(int n, const double* A, int64
             }
             for (int e = t; e < PB * PB; e += BT) {
                 const int r = e % PB, c = e / PB;
-                if (r < sb && c < sb) Tm[(c0 + r) + (int64_t)(c0 + c) * W] = s.D[r][c];
+                if (r < sb && c < sb) ((gdouble*)Tm)[(c0 + r) + (int64_t)(c0 + c) * W] = s.D[r][c];
             }
             gsync();
             if (c0 > 0) {
@@ -1200,10 +1270,13 @@ __device__ __attribute__((noinline)) int dc_merge(int o, int N, int n1, double* 
     int* tpos = kcol + NMAX;                       // position of kept column k in type order
     int* rorg = s.rk;                              // pole each root is measured from
     int* dcol = s.ix;                              // deflated columns
-    int* ra = reinterpret_cast<int*>(R + 2 * N);
-    int* rb = ra + N;
-    double* rcs = R;
-    double* rsn = R + N;
+    gdouble* gZ = (gdouble*)Z;
+    gdouble* gX = (gdouble*)X;
+    gdouble* gR = (gdouble*)R;
+    gint* ra = (gint*)(gR + 2 * N);
+    gint* rb = ra + N;
+    gdouble* rcs = gR;
+    gdouble* rsn = gR + N;
     const double beta = s.ee[o + n1 - 1];
     const double sgn = beta >= 0.0 ? 1.0 : -1.0;
     const double rho = 2.0 * fabs(beta);
@@ -1217,7 +1290,7 @@ __device__ __attribute__((noinline)) int dc_merge(int o, int N, int n1, double* 
             const double vj = s.dd[o + j];
             r += (vj < vi || (vj == vi && j < i)) ? 1 : 0;
         }
-        const double zi = (i < n1 ? Z[(o + n1 - 1) + (int64_t)(o + i) * ldz] : sgn * Z[(o + n1) + (int64_t)(o + i) * ldz]) * isq2;
+        const double zi = (i < n1 ? gZ[(o + n1 - 1) + (int64_t)(o + i) * ldz] : sgn * gZ[(o + n1) + (int64_t)(o + i) * ldz]) * isq2;
         ds[r] = vi;
         zs[r] = zi;
         perm[r] = i;
@@ -1307,7 +1380,7 @@ __device__ __attribute__((noinline)) int dc_merge(int o, int N, int n1, double* 
     // (c) deflation rotations on the columns of the merged block, one row per thread
     if (nr > 0) {
         for (int r = t; r < N; r += BT) {
-            double* zr = Z + (o + r);
+            gdouble* zr = gZ + (o + r);
             for (int q = 0; q < nr; ++q) {
                 const int64_t a = o + ra[q], b = o + rb[q];
                 const double c = rcs[q], sn = rsn[q];
@@ -1348,14 +1421,28 @@ __device__ __attribute__((noinline)) int dc_merge(int o, int N, int n1, double* 
     __syncthreads();
     for (int j = t; j < K; j += BT) {
         const double zj = zs[j], dj = dk[j];
-        double* ur = U + tpos[j];
+        gdouble* ur = (gdouble*)U + tpos[j];
         for (int k = 0; k < K; ++k) ur[(int64_t)k * K] = zj / ((dj - dk[rorg[k]]) - ds[k]) * aux[k];
     }
     // (g) kept columns of Q in type order, deflated columns after them
+    // (column k < K of the gathered order is kept column tpos[k], column
+    // k >= K deflated column k - K); MV columns loaded before any is stored
+    constexpr int MV = 8;
     for (int r = t; r < N; r += BT) {
-        const double* zr = Z + (o + r);
-        for (int k = 0; k < K; ++k) X[r + (int64_t)tpos[k] * N] = zr[(int64_t)(o + kcol[k]) * ldz];
-        for (int q = 0; q < N - K; ++q) X[r + (int64_t)(K + q) * N] = zr[(int64_t)(o + dcol[q]) * ldz];
+        const gdouble* zr = gZ + (o + r);
+        for (int k0 = 0; k0 < N; k0 += MV) {
+            double v[MV];
+#pragma unroll
+            for (int u = 0; u < MV; ++u) {
+                const int k = min(k0 + u, N - 1);
+                v[u] = zr[(int64_t)(o + (k < K ? kcol[k] : dcol[k - K])) * ldz];
+            }
+#pragma unroll
+            for (int u = 0; u < MV; ++u) {
+                const int k = k0 + u;
+                if (k < N) gX[r + (int64_t)(k < K ? tpos[k] : k) * N] = v[u];
+            }
+        }
     }
     gsync();
     // (h) Y = Q U, top rows from the type 1|2 columns, bottom rows from type 2|3
@@ -1377,10 +1464,20 @@ __device__ __attribute__((noinline)) int dc_merge(int o, int N, int n1, double* 
     }
     __syncthreads();
     // (j) scatter into Z and s.dd in ascending order
-    for (int c = 0; c < N; ++c) {
-        const int64_t dst = o + perm[c];
-        const double* src = (c < K) ? Y + (int64_t)c * N : X + (int64_t)c * N;
-        for (int r = t; r < N; r += BT) Z[(o + r) + dst * ldz] = src[r];
+    for (int c0 = 0; c0 < N; c0 += MV) {
+        for (int r = t; r < N; r += BT) {
+            double v[MV];
+#pragma unroll
+            for (int u = 0; u < MV; ++u) {
+                const int c = min(c0 + u, N - 1);
+                v[u] = ((c < K) ? (const gdouble*)Y : (const gdouble*)gX)[r + (int64_t)c * N];
+            }
+#pragma unroll
+            for (int u = 0; u < MV; ++u) {
+                const int c = c0 + u;
+                if (c < N) gZ[(o + r) + (int64_t)(o + perm[c]) * ldz] = v[u];
+            }
+        }
     }
     for (int c = t; c < N; c += BT) s.dd[o + perm[c]] = aux[c];
     gsync();
@@ -1437,31 +1534,48 @@ __device__ __attribute__((noinline)) int wg_stedc(int n, double* Z, int64_t ldz,
     return 0;
 }
 
+// f(i, j, src[i + j ls]) for the n x n source (strict: below the diagonal
+// only), the loads of MVC columns issued before their values are handed on,
+// so a copy costs one memory latency per MVC columns, not per column.
+constexpr int MVC = 8;
+template <class F>
+__device__ inline void wg_cols(int n, bool strict, const double* srcg, int64_t ls, F f) {
+    const gdouble* src = (const gdouble*)srcg;
+    const int t = threadIdx.x;
+    for (int j0 = 0; j0 < n; j0 += MVC) {
+        for (int i = (strict ? j0 + 1 : 0) + t; i < n; i += BT) {
+            double v[MVC];
+#pragma unroll
+            for (int u = 0; u < MVC; ++u) v[u] = src[i + (int64_t)min(j0 + u, n - 1) * ls];
+#pragma unroll
+            for (int u = 0; u < MVC; ++u) {
+                const int j = j0 + u;
+                if (j < n && (!strict || i > j)) f(i, j, v[u]);
+            }
+        }
+    }
+}
+
 __device__ int64_t solve_one(const BProb& p, Lds& s) {
     const int t = threadIdx.x;
     const int n = (int)p.n;
     const int64_t ld = p.ld;
     double *L = p.L, *W = p.W, *A = p.A, *Z = p.Z;
-    for (int j = 0; j < n; ++j)
-        for (int i = t; i < n; i += BT) {
-            L[i + (int64_t)j * n] = p.M[i + j * ld];
-            W[i + (int64_t)j * n] = p.K[i + j * ld];
-        }
+    gdouble *gL = (gdouble*)L, *gW = (gdouble*)W, *gA = (gdouble*)A;
+    wg_cols(n, false, p.M, ld, [&](int i, int j, double v) { gL[i + (int64_t)j * n] = v; });
+    wg_cols(n, false, p.K, ld, [&](int i, int j, double v) { gW[i + (int64_t)j * n] = v; });
     gsync();
     const int bw = (int)min(p.bw, p.n - 1);
     const int piv = wg_potrf(n, bw, L, n, s);
     if (piv) return piv;
     wg_trsm_ln(n, bw, n, L, n, W, n, s);  // W = L^-1 K
-    for (int j = 0; j < n; ++j)
-        for (int i = t; i < n; i += BT) A[i + (int64_t)j * n] = W[j + (int64_t)i * n];
+    // A = W^T (reads along columns, so they coalesce; the strided side is
+    // the stores, which nothing waits for)
+    wg_cols(n, false, W, n, [&](int i, int j, double v) { gA[j + (int64_t)i * n] = v; });
     gsync();
     wg_trsm_ln(n, bw, n, L, n, A, n, s);  // A = L^-1 K L^-T
-    for (int j = 0; j < n; ++j)
-        for (int i = j + 1 + t; i < n; i += BT) {
-            const double v = 0.5 * (A[i + (int64_t)j * n] + A[j + (int64_t)i * n]);
-            A[i + (int64_t)j * n] = v;
-            A[j + (int64_t)i * n] = v;
-        }
+    // exactly symmetric: the upper triangle from the lower one
+    wg_cols(n, true, A, n, [&](int i, int j, double v) { gA[j + (int64_t)i * n] = v; });
     gsync();
     if (n >= SYTRD_BLK_MIN)
         wg_sytrd_blk(n, A, n, p.tau, p.U, s);
@@ -1484,10 +1598,8 @@ __device__ int64_t solve_one(const BProb& p, Lds& s) {
         p.logtheta[r] = log(di);
     }
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const int dst = s.rk[j];
-        for (int i = t; i < n; i += BT) p.V[i + (int64_t)dst * ld] = Z[i + (int64_t)j * n];
-    }
+    gdouble* gV = (gdouble*)p.V;
+    wg_cols(n, false, Z, n, [&](int i, int j, double v) { gV[i + (int64_t)s.rk[j] * ld] = v; });
     __syncthreads();
     return 0;
 }
