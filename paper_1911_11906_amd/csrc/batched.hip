@@ -461,15 +461,18 @@ __device__ void wg_make_w(int n, int64_t g0, int m, double tk, const double (&ac
 // Rows t + q BT (q < RPT) of columns g0 + j0 .. g0 + j0 + SU - 1.  The loads
 // are unconditional within a wave, from a row and column clamped into the
 // matrix; entries that are not the caller's (rows it does not own, columns
-// j >= m) are never used.  A wave whose rows in slot q all lie above the
-// trailing block (rows <= g0) loads nothing there.
+// j >= m) are never used.  With SKIP, a wave whose rows in slot q all lie
+// above the trailing block (rows <= g0) loads nothing there and gets zeros
+// (for a caller that only reads the chunk; the unblocked tridiagonalisation
+// stores every loaded row back).
+template <bool SKIP>
 __device__ inline void sytrd_load_chunk(const gdouble* A, int64_t lda, int64_t g0, int j0, int m, int n,
                                         double (&buf)[SU][RPT]) {
     const int t = threadIdx.x;
     const int wlast = __builtin_amdgcn_readfirstlane(t | 63);  // last row of this wave in slot 0
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        if (wlast + q * BT > g0) {
+        if (!SKIP || wlast + q * BT > g0) {
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
                 const int j = (j0 + u < m) ? j0 + u : m - 1;
@@ -625,29 +628,29 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
                 }
             };
             if (t < n) {
-                sytrd_load_chunk(gA, lda, g0, 1, m, n, ca);
+                sytrd_load_chunk<false>(gA, lda, g0, 1, m, n, ca);
                 int j0 = 1;
                 // (the first use of a buffer after the loop's back edge waits
                 // for every load, so the loop body holds two pairs)
                 for (; j0 + 4 * SU <= m; j0 += 4 * SU) {
-                    sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                    sytrd_load_chunk<false>(gA, lda, g0, j0 + SU, m, n, cb);
                     process(ca, j0);
-                    sytrd_load_chunk(gA, lda, g0, j0 + 2 * SU, m, n, ca);
+                    sytrd_load_chunk<false>(gA, lda, g0, j0 + 2 * SU, m, n, ca);
                     process(cb, j0 + SU);
-                    sytrd_load_chunk(gA, lda, g0, j0 + 3 * SU, m, n, cb);
+                    sytrd_load_chunk<false>(gA, lda, g0, j0 + 3 * SU, m, n, cb);
                     process(ca, j0 + 2 * SU);
-                    sytrd_load_chunk(gA, lda, g0, j0 + 4 * SU, m, n, ca);
+                    sytrd_load_chunk<false>(gA, lda, g0, j0 + 4 * SU, m, n, ca);
                     process(cb, j0 + 3 * SU);
                 }
                 if (j0 + 2 * SU <= m) {
-                    sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                    sytrd_load_chunk<false>(gA, lda, g0, j0 + SU, m, n, cb);
                     process(ca, j0);
-                    sytrd_load_chunk(gA, lda, g0, j0 + 2 * SU, m, n, ca);
+                    sytrd_load_chunk<false>(gA, lda, g0, j0 + 2 * SU, m, n, ca);
                     process(cb, j0 + SU);
                     j0 += 2 * SU;
                 }
                 if (j0 < m) {
-                    sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                    sytrd_load_chunk<false>(gA, lda, g0, j0 + SU, m, n, cb);
                     process_tail(ca, j0);
                     if (j0 + SU < m) process_tail(cb, j0 + SU);
                 }
@@ -683,11 +686,12 @@ __device__ __attribute__((noinline)) void wg_sytrd(int n, double* A, int64_t lda
 // consecutive steps stay pending in P = [V | W | V] (global, n x 3 NBB,
 // ld n, zeros above each vector's first row) and are applied to the
 // trailing matrix every NBB steps in one workgroup product with k = 2 NBB,
-// [V W] [W V]^T (the two column ranges of P that start at 0 and at NBB).  A step sees the current
-// matrix through them: its column gets the pending updates before the
-// Householder step, and the product with the new v is formed from the stale
-// matrix (one read-only pass instead of a read-write pass) and corrected by
-// V (W^T v) + W (V^T v).  Same reflectors as wg_sytrd in exact arithmetic.
+// [V W] [W V]^T (the column ranges of P that start at 0 and at NBB).  A
+// step sees the current matrix through them: its column gets the pending
+// updates before the Householder step, and the product with the new v is
+// formed from the stale matrix (one read-only pass instead of a read-write
+// pass) and corrected by V (W^T v) + W (V^T v).  Same reflectors as
+// wg_sytrd in exact arithmetic.
 constexpr int NBB = 32;
 constexpr int SYTRD_BLK_MIN = 256;
 constexpr int PU = 8;  // pending pairs read per batch of loads
@@ -843,16 +847,16 @@ __device__ __attribute__((noinline)) void wg_sytrd_blk(int n, double* Ag, int64_
                     for (int q = 0; q < RPT; ++q) acc[q] = fma(cur[u][q], v2j, acc[q]);
                 }
             };
-            sytrd_load_chunk(gA, lda, g0, 1, m, n, ca);
+            sytrd_load_chunk<true>(gA, lda, g0, 1, m, n, ca);
             int j0 = 1;
             for (; j0 + 2 * SU <= m; j0 += 2 * SU) {
-                sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                sytrd_load_chunk<true>(gA, lda, g0, j0 + SU, m, n, cb);
                 mac(ca, j0);
-                sytrd_load_chunk(gA, lda, g0, j0 + 2 * SU, m, n, ca);
+                sytrd_load_chunk<true>(gA, lda, g0, j0 + 2 * SU, m, n, ca);
                 mac(cb, j0 + SU);
             }
             if (j0 < m) {
-                sytrd_load_chunk(gA, lda, g0, j0 + SU, m, n, cb);
+                sytrd_load_chunk<true>(gA, lda, g0, j0 + SU, m, n, cb);
                 mac(ca, j0);
                 mac(cb, j0 + SU);
             }

@@ -14,6 +14,25 @@ namespace {
 constexpr int LB = 128;  // leaf block
 constexpr int LT = 1024; // threads of the leaf kernel
 
+// v moved across the lanes of a wave by the DPP control CTRL (both halves)
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the eight aligned lanes 8r .. 8r+7: swaps within pairs and within
+// quads, then the mirror within each half row of eight lanes; every lane of
+// the eight gets the same bits (each step adds a and b in either order).
+__device__ inline double sum8(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    return v;
+}
+
 // Inverse X of the lower-triangular LB x LB block L in LDS (column-major, ld
 // LB), written to out (LB x LB, zero above the diagonal).  X L = I gives, row
 // by row from the right, X_ii = 1 / L_ii and
@@ -36,9 +55,7 @@ __device__ void invert_lower_rows(const double* L, const double* rdiag, double* 
         for (int q = 0; q < LB / 8; ++q) {
             acc += X[q] * L[8 * q + part + j * LB];
         }
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
-        acc += __shfl_xor(acc, 4, 64);
+        acc = sum8(acc);
         const double x = (j == i) ? rdiag[j] : -acc * rdiag[j];
         if (j <= i && part == (j & 7)) {
 #pragma unroll
@@ -53,69 +70,77 @@ __device__ void invert_lower_rows(const double* L, const double* rdiag, double* 
     }
 }
 
-// Factor the nb x nb (nb <= 128) diagonal block at A (ld lda) in LDS; write L
-// back (strict upper triangle of the block zeroed) and its inverse (128 x 128,
+// Factor the nb x nb (nb <= 128) diagonal block at A (ld lda); write L back
+// (strict upper triangle of the block zeroed) and its inverse (128 x 128,
 // zero padded) to Linv.  info: first failing global pivot (1-based) if unset.
-// The elimination keeps the columns unscaled (S_ic -= S_ij S_cj / d_j), one
-// barrier per column; L = column j / sqrt(d_j) is formed at the end.  A
-// pivot d_j <= 0 is reported and replaced by 1 (every thread derives the same
-// replacement from either value it may read).
+// The block lives in registers: thread t holds row t % 128 of the columns
+// t / 128 + 8 k (k < 16), so a wave holds one column group and its reads of
+// the pivot column are broadcasts.  Step j: the owner of column j publishes
+// it in LDS (two buffers by parity, so one barrier per step), and every
+// thread updates its entries of the columns c > j, S_ic -= S_ij S_cj / d_j,
+// keeping the columns unscaled; L = column c / sqrt(d_c) is formed at the
+// end.  A pivot d_j <= 0 is reported and replaced by 1 (every thread derives
+// the same replacement from the value it reads).  Padding rows and columns
+// (>= nb) are the identity, which keeps the inverse well defined.
 __global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, int nb, int64_t goff,
                                                         double* Linv, int64_t* info) {
-    __shared__ double S[LB * LB];  // column-major with ld LB (128 KB of the 160 KB LDS)
-    __shared__ double y[LB];
-    __shared__ double colj[LB];    // pivot column of the current step (read-only while S is updated)
+    __shared__ double S[LB * LB];     // L, column-major with ld LB, for the inverse
+    __shared__ double colj[2][LB];    // pivot column of step j in buffer j % 2
+    __shared__ double dg[LB];         // pivots (1 for padding)
+    __shared__ double rd[LB];         // 1 / L_jj
     const int t = threadIdx.x;
-    for (int e = t; e < LB * LB; e += LT) {
-        int i = e % LB, j = e / LB;
-        double v;
-        if (i < nb && j < nb)
-            v = (i >= j) ? A[i + (int64_t)j * lda] : 0.0;
-        else
-            v = (i == j) ? 1.0 : 0.0;  // identity padding keeps the inverse well defined
-        S[i + j * LB] = v;
+    const int i = t & (LB - 1), cg = t >> 7;
+    const int cgu = __builtin_amdgcn_readfirstlane(cg);  // the same on every lane of a wave
+    constexpr int NK = LB / (LT / LB);  // 16 columns per thread
+    double X[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int c = cg + 8 * k;
+        X[k] = (i < nb && c < nb) ? ((i >= c) ? A[i + (int64_t)c * lda] : 0.0) : ((i == c) ? 1.0 : 0.0);
     }
-    __syncthreads();
+    if (t < LB) dg[t] = 1.0;
     bool bad = false;  // thread 0 only
     for (int j = 0; j < nb; ++j) {
-        const double d = S[j + j * LB];
+        double* cj = colj[j & 1];
+        if (cg == (j & 7)) {
+            double v = X[0];
+#pragma unroll
+            for (int k = 1; k < NK; ++k)
+                if (k == (j >> 3)) v = X[k];
+            cj[i] = v;
+        }
+        __syncthreads();
+        const double d = cj[j];
         const double deff = (d > 0.0) ? d : 1.0;
-        if (t == 0 && !(d > 0.0)) {
-            if (!bad && *info == 0) *info = goff + j + 1;
-            bad = true;
-            S[j + j * LB] = deff;
+        if (t == 0) {
+            if (!(d > 0.0) && !bad && *info == 0) *info = goff + j + 1;
+            bad = bad || !(d > 0.0);
+            dg[j] = deff;
         }
-        // the pivot column goes to its own array: the updates below then
-        // read it without any possible overlap with the entries they write
-        if (t < LB) colj[t] = S[t + j * LB];
-        __syncthreads();
-        const double inv = 1.0 / deff;
-        // thread t updates row t % LB of the columns j+1+(t / LB), step 8
-        // (fixed row, no index division)
-        const int i = t & (LB - 1);
-        if (i > j && i < nb) {
-            const double sij = colj[i] * inv;
-#pragma unroll 4
-            for (int cc = j + 1 + (t >> 7); cc <= i; cc += LT / LB) S[i + cc * LB] -= sij * colj[cc];
+        const double sij = cj[i] * (1.0 / deff);
+        // columns c <= j are finished: skipped (c is uniform over the wave)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int c = cgu + 8 * k;
+            if (c > j) X[k] = fma(-sij, cj[c], X[k]);
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (t < LB) {
-        y[t] = sqrt(S[t + t * LB]);
-        colj[t] = 1.0 / y[t];  // reciprocal diagonal of L for the inverse
+        const double y = sqrt(dg[t]);
+        colj[0][t] = y;
+        rd[t] = 1.0 / y;
     }
     __syncthreads();
-    for (int e = t; e < LB * LB; e += LT) {
-        int i = e % LB, j = e / LB;
-        if (i > j) S[e] = S[e] / y[j];
-        else if (i == j) S[e] = y[j];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int c = cg + 8 * k;
+        const double v = (i > c) ? X[k] / colj[0][c] : ((i == c) ? colj[0][c] : 0.0);
+        S[i + c * LB] = v;
+        if (i < nb && c < nb) A[i + (int64_t)c * lda] = v;
     }
     __syncthreads();
-    for (int e = t; e < nb * nb; e += LT) {
-        int i = e % nb, j = e / nb;
-        A[i + (int64_t)j * lda] = (i >= j) ? S[i + j * LB] : 0.0;
-    }
-    invert_lower_rows(S, colj, Linv, t);
+    invert_lower_rows(S, rd, Linv, t);
 }
 
 // Inverses of the 128 x 128 diagonal blocks of an existing lower factor L
@@ -297,17 +322,21 @@ hipError_t fl_potrf_band(hipStream_t s, int64_t n, int64_t q, double* A, int64_t
 
 // L X = B (B: n x m, overwritten by X) for the banded factor: block row i,
 // X_i = L_ii^-1 (B_i - L_i,k X_k), k in [i-q, i).  work: >= 128 m doubles.
+// bwb >= 0: row r of B is zero beyond column r + bwb (B = K of the banded
+// pattern), and so is row r of X (X_r combines rows <= r of B), so block row
+// i is solved on its first i0 + nb + bwb columns only.
 hipError_t fl_trsm_lln_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
-                            double* B, int64_t ldb, int64_t m, double* work) {
+                            double* B, int64_t ldb, int64_t m, double* work, int64_t bwb) {
     if (n <= 0 || m <= 0) return hipSuccess;
     const int64_t nbk = FL_DIV_UP(n, LB);
     hipError_t e;
     for (int64_t i = 0; i < nbk; ++i) {
         const int64_t i0 = i * LB, nb = std::min<int64_t>(LB, n - i0);
         const int64_t k0 = std::max<int64_t>(0, i - q) * LB, w = i0 - k0;
-        if (w > 0 && (e = fl_dgemm(s, 0, 0, nb, m, w, -1.0, L + i0 + k0 * ldl, ldl, B + k0, ldb, 1.0, B + i0, ldb)))
+        const int64_t mi = bwb >= 0 ? std::min<int64_t>(m, i0 + nb + bwb) : m;
+        if (w > 0 && (e = fl_dgemm(s, 0, 0, nb, mi, w, -1.0, L + i0 + k0 * ldl, ldl, B + k0, ldb, 1.0, B + i0, ldb)))
             return e;
-        if ((e = fl_trsm_lln(s, nb, m, L + i0 + i0 * ldl, ldl, Linv + i * LB * LB, B + i0, ldb, work))) return e;
+        if ((e = fl_trsm_lln(s, nb, mi, L + i0 + i0 * ldl, ldl, Linv + i * LB * LB, B + i0, ldb, work))) return e;
     }
     return hipSuccess;
 }

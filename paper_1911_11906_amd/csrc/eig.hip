@@ -403,12 +403,14 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     int rc = FL_OK;
     if (banded) {
         // W = L^-1 K, then C = L^-1 W^T (= L^-1 K L^-T, symmetric): two
-        // banded substitutions; the lower triangle is mirrored so that C is
-        // exactly symmetric
+        // banded substitutions (the first on the columns where W can be
+        // non-zero: K shares M's pattern, so row r of W ends at column
+        // r + bw); the lower triangle is mirrored so that C is exactly
+        // symmetric
         FL_HIP(ctx, bY.alloc(sizeof(double) * (size_t)n * n));
         double* Y = bY.as<double>();
         FL_HIP(ctx, hipMemcpyAsync(C, op->K, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
-        FL_HIP(ctx, fl_trsm_lln_band(s, n, qband, L, ld, blinv.as<double>(), C, ld, n, bwork.as<double>()));
+        FL_HIP(ctx, fl_trsm_lln_band(s, n, qband, L, ld, blinv.as<double>(), C, ld, n, bwork.as<double>(), mbw));
         FL_HIP(ctx, fl_transpose(s, n, n, C, ld, Y, n));
         FL_HIP(ctx, fl_trsm_lln_band(s, n, qband, L, ld, blinv.as<double>(), Y, n, n, bwork.as<double>()));
         FL_HIP(ctx, fl_copy_matrix(s, n, n, Y, n, C, ld));

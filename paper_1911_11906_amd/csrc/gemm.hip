@@ -283,9 +283,14 @@ hipError_t launch(hipStream_t s, const Prob<T>& g, int lower, const SplitWs* ws,
     const int64_t tiles = tm * tn;
     // few output tiles and a long k: split k so that the chip fills up (down
     // to k-slices of 128 for the smallest outputs, e.g. the 64 x 64 Gram
-    // matrices of the band reduction)
-    if (!lower && tiles < 384 && g.k >= 1024) {
-        int64_t S = std::min<int64_t>({FL_DIV_UP(1024, tiles), g.k / 128, 256});
+    // matrices of the band reduction); a handful of tiles with a moderate k
+    // (the block steps of the banded Cholesky: one or two 128 x 128 tiles,
+    // k = 128 .. 512) in slices of 32 (a single tile may be a lower one: the
+    // lower kernel writes whole diagonal tiles as well)
+    const bool few = (!lower || tiles == 1) && tiles <= 16 && g.k >= 128 && g.k < 1024;
+    if ((!lower && tiles < 384 && g.k >= 1024) || few) {
+        int64_t S = few ? std::min<int64_t>(g.k / 32, FL_DIV_UP(512, tiles))
+                        : std::min<int64_t>({FL_DIV_UP(1024, tiles), g.k / 128, 256});
         T* P = split_buffer<T>(s, ws, S, g.m, g.n);
         if (S > 1 && P) {
             int64_t kc = FL_DIV_UP(FL_DIV_UP(g.k, S), GKB) * GKB;

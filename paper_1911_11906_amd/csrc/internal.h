@@ -192,7 +192,7 @@ int fl_pattern_bandwidth(fl_op* op, int64_t* bw);
 hipError_t fl_potrf_band(hipStream_t s, int64_t n, int64_t q, double* A, int64_t lda, double* Linv, int64_t* info,
                          double* work);
 hipError_t fl_trsm_lln_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
-                            double* B, int64_t ldb, int64_t m, double* work);
+                            double* B, int64_t ldb, int64_t m, double* work, int64_t bwb = -1);
 hipError_t fl_trsm_llt_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
                             double* B, int64_t ldb, int64_t m, double* work);
 hipError_t fl_trtri_inplace(hipStream_t s, int64_t n, double* L, int64_t ldl, const double* Linv, double* work);
