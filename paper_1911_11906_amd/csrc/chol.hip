@@ -178,6 +178,142 @@ inline int64_t split_point(int64_t k) {
     return LB * ((leaves + 1) / 2);
 }
 
+
+// ------------------------------------------- banded solves, column strips
+// For many right-hand sides the banded substitution runs as one launch: each
+// workgroup owns a strip of BSW columns of B and walks all block rows in
+// turn, so no workgroup ever waits for another.  Block row i becomes one
+// product X_i = P_i B[lo_i : lo_i + K_i, strip] with a precomputed panel
+//   forward  (L X = B):   P_i = [ -L_ii^-1 L_i,k  |  L_ii^-1 ],  lo_i = k0
+//   backward (L^T X = B): P_i = [ L_ii^-T  |  -L_ii^-T L_k,i^T ], lo_i = i0
+// (k the q block rows on the far side of the diagonal block), which reads
+// the already solved rows and B_i together; X_i overwrites B_i once every
+// wave has read it.
+constexpr int BSW = 64;  // strip width
+constexpr int BSK = 32;  // k-slab staged in LDS
+
+__device__ inline void band_row_range(bool back, int64_t n, int64_t q, int64_t i, int64_t& i0, int64_t& nb,
+                                      int64_t& lo, int64_t& K) {
+    i0 = i * LB;
+    nb = (n - i0) < LB ? (n - i0) : LB;
+    if (!back) {
+        lo = (i > q ? i - q : 0) * LB;
+        K = i0 + nb - lo;
+    } else {
+        lo = i0;
+        const int64_t r1 = i0 + nb, w = (n - r1) < q * LB ? (n - r1) : q * LB;
+        K = nb + w;
+    }
+}
+
+// Diagonal parts of the panels: L_ii^-1 (forward, after the w = i0 - k0
+// columns of the off-diagonal part) or L_ii^-T (backward, first).  One
+// workgroup per block row.
+template <bool BACK>
+__global__ void band_panel_diag_kernel(int64_t n, int64_t q, const double* __restrict__ Linv, double* P) {
+    const int64_t i = blockIdx.x, KP = (q + 1) * LB;
+    int64_t i0, nb, lo, K;
+    band_row_range(BACK, n, q, i, i0, nb, lo, K);
+    const double* Li = Linv + i * LB * LB;
+    double* Pi = P + i * LB * KP;
+    const int64_t off = BACK ? 0 : i0 - lo;
+    for (int e = threadIdx.x; e < LB * LB; e += blockDim.x) {
+        const int r = e % LB, c = e / LB;
+        Pi[r + (off + c) * LB] = BACK ? Li[c + r * LB] : Li[r + c * LB];
+    }
+}
+
+// acc row/column of lane (lr, lc), register r: row 16 ti + lc of the wave's
+// 32 rows, column 16 tj + lr + 4 r (the MFMA's first operand is fed from B).
+template <bool BACK>
+__global__ __launch_bounds__(256) void band_solve_kernel(int64_t n, int64_t q, const double* __restrict__ P,
+                                                         double* B, int64_t ldb, int64_t ncols, int64_t bwb) {
+    __shared__ double As[BSK][LB + 2];   // As[k][r] = P_i(r, kk + k)
+    __shared__ double Bs[BSK][BSW + 2];  // Bs[k][j] = B(lo + kk + k, c0 + j)
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int lr = lane >> 4, lc = lane & 15;
+    const int64_t c0 = (int64_t)blockIdx.x * BSW;
+    const int64_t nbk = FL_DIV_UP(n, LB), KP = (q + 1) * LB;
+    constexpr int NA = BSK * LB / 256, NB = BSK * BSW / 256;  // staged elements per thread
+    for (int64_t st = 0; st < nbk; ++st) {
+        const int64_t i = BACK ? nbk - 1 - st : st;
+        int64_t i0, nb, lo, K;
+        band_row_range(BACK, n, q, i, i0, nb, lo, K);
+        // forward with a banded B: rows r of B and X are zero beyond column
+        // r + bwb, so a block row ending before the strip stays zero
+        if (!BACK && bwb >= 0 && i0 + nb - 1 + bwb < c0) continue;
+        const double* Pi = P + i * LB * KP;
+        d4_t acc[2][4];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = d4_t{0, 0, 0, 0};
+        double ra[NA], rb[NB];
+        // slab kk into registers: loads from clamped indices, masked when staged
+        auto gload = [&](int64_t kk) {
+#pragma unroll
+            for (int u = 0; u < NA; ++u) {
+                const int e = t + 256 * u, r = e % LB, k = e / LB;
+                const int64_t kc = (kk + k < K) ? kk + k : K - 1;
+                ra[u] = Pi[r + kc * LB];
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int e = t + 256 * u, k = e % BSK, j = e / BSK;
+                const int64_t row = lo + ((kk + k < K) ? kk + k : K - 1);
+                const int64_t col = (c0 + j < ncols) ? c0 + j : ncols - 1;
+                rb[u] = B[row + col * ldb];
+            }
+        };
+        gload(0);
+        for (int64_t kk = 0; kk < K; kk += BSK) {
+            __syncthreads();  // the previous slab has been consumed
+#pragma unroll
+            for (int u = 0; u < NA; ++u) {
+                const int e = t + 256 * u, r = e % LB, k = e / LB;
+                As[k][r] = (kk + k < K && r < nb) ? ra[u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int e = t + 256 * u, k = e % BSK, j = e / BSK;
+                Bs[k][j] = (kk + k < K) ? rb[u] : 0.0;
+            }
+            __syncthreads();
+            if (kk + BSK < K) gload(kk + BSK);
+#pragma unroll
+            for (int k4 = 0; k4 < BSK; k4 += 4) {
+                double fa[4], fb[2];
+#pragma unroll
+                for (int y = 0; y < 4; ++y) fa[y] = Bs[k4 + lr][16 * y + lc];
+#pragma unroll
+                for (int x = 0; x < 2; ++x) fb[x] = As[k4 + lr][wave * 32 + 16 * x + lc];
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[y], fb[x], acc[x][y], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read B_i (part of the operand rows)
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int r = wave * 32 + 16 * x + lc;
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t col = c0 + 16 * y + lr + 4 * v;
+                    if (r < nb && col < ncols) B[i0 + r + col * ldb] = acc[x][y][v];
+                }
+        }
+        // the next block row reads these rows through other waves: drain the
+        // stores, barrier, and drop stale vector-L1 lines
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+}
 }  // namespace
 
 int64_t fl_potrf_linv_elems(int64_t n) { return FL_DIV_UP(n, LB) * LB * LB; }
@@ -320,44 +456,6 @@ hipError_t fl_potrf_band(hipStream_t s, int64_t n, int64_t q, double* A, int64_t
     return hipSuccess;
 }
 
-// L X = B (B: n x m, overwritten by X) for the banded factor: block row i,
-// X_i = L_ii^-1 (B_i - L_i,k X_k), k in [i-q, i).  work: >= 128 m doubles.
-// bwb >= 0: row r of B is zero beyond column r + bwb (B = K of the banded
-// pattern), and so is row r of X (X_r combines rows <= r of B), so block row
-// i is solved on its first i0 + nb + bwb columns only.
-hipError_t fl_trsm_lln_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
-                            double* B, int64_t ldb, int64_t m, double* work, int64_t bwb) {
-    if (n <= 0 || m <= 0) return hipSuccess;
-    const int64_t nbk = FL_DIV_UP(n, LB);
-    hipError_t e;
-    for (int64_t i = 0; i < nbk; ++i) {
-        const int64_t i0 = i * LB, nb = std::min<int64_t>(LB, n - i0);
-        const int64_t k0 = std::max<int64_t>(0, i - q) * LB, w = i0 - k0;
-        const int64_t mi = bwb >= 0 ? std::min<int64_t>(m, i0 + nb + bwb) : m;
-        if (w > 0 && (e = fl_dgemm(s, 0, 0, nb, mi, w, -1.0, L + i0 + k0 * ldl, ldl, B + k0, ldb, 1.0, B + i0, ldb)))
-            return e;
-        if ((e = fl_trsm_lln(s, nb, mi, L + i0 + i0 * ldl, ldl, Linv + i * LB * LB, B + i0, ldb, work))) return e;
-    }
-    return hipSuccess;
-}
-
-// L^T X = B (B: n x m, overwritten by X) for the banded factor: block row i
-// from the last, X_i = L_ii^-T (B_i - L_k,i^T X_k), k in (i, i+q].
-hipError_t fl_trsm_llt_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
-                            double* B, int64_t ldb, int64_t m, double* work) {
-    if (n <= 0 || m <= 0) return hipSuccess;
-    const int64_t nbk = FL_DIV_UP(n, LB);
-    hipError_t e;
-    for (int64_t i = nbk - 1; i >= 0; --i) {
-        const int64_t i0 = i * LB, nb = std::min<int64_t>(LB, n - i0);
-        const int64_t r1 = i0 + nb, w = std::min<int64_t>(q * LB, n - r1);  // rows of the blocks below
-        if (w > 0 && (e = fl_dgemm(s, 1, 0, nb, m, w, -1.0, L + r1 + i0 * ldl, ldl, B + r1, ldb, 1.0, B + i0, ldb)))
-            return e;
-        if ((e = fl_trsm_llt(s, nb, m, L + i0 + i0 * ldl, ldl, Linv + i * LB * LB, B + i0, ldb, work))) return e;
-    }
-    return hipSuccess;
-}
-
 hipError_t fl_trtri_leaves(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Linv) {
     if (n <= 0) return hipSuccess;
     trtri_leaves_kernel<<<(unsigned)FL_DIV_UP(n, LB), LT, 0, s>>>(n, L, ldl, Linv);
@@ -368,5 +466,66 @@ hipError_t fl_symmetrize(hipStream_t s, int64_t n, double* A, int64_t lda) {
     if (n <= 1) return hipSuccess;
     dim3 grid((unsigned)FL_DIV_UP(n, 256), (unsigned)(n < 65535 ? n : 65535));
     symmetrize_kernel<<<grid, 256, 0, s>>>(n, A, lda);
+    return hipGetLastError();
+}
+
+int64_t fl_band_panel_elems(int64_t n, int64_t q) { return FL_DIV_UP(n, LB) * LB * (q + 1) * LB; }
+
+// Panels of the strip-parallel banded solves (see band_solve_kernel): P is
+// nbk panels of 128 x (q + 1) 128 (ld 128).  probs: device room for nbk
+// GEMM descriptors.
+hipError_t fl_band_panels(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
+                          double* P, int back, GemmProblem* probs) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nbk = FL_DIV_UP(n, LB), KP = (q + 1) * LB;
+    std::vector<GemmProblem> hp;
+    for (int64_t i = 0; i < nbk; ++i) {
+        const int64_t i0 = i * LB, nb = std::min<int64_t>(LB, n - i0);
+        GemmProblem g{};
+        if (!back) {
+            const int64_t k0 = std::max<int64_t>(0, i - q) * LB, w = i0 - k0;
+            if (w <= 0) continue;
+            // -L_ii^-1 L_i,k: nb x w
+            g.m = nb; g.n = w; g.k = nb;
+            g.A = Linv + i * LB * LB; g.lda = LB;
+            g.B = L + i0 + k0 * ldl; g.ldb = ldl;
+        } else {
+            const int64_t r1 = i0 + nb, w = std::min<int64_t>(q * LB, n - r1);
+            if (w <= 0) continue;
+            // -L_ii^-T L_k,i^T = -(L_ii^-1)^T (L_k,i)^T: nb x w
+            g.m = nb; g.n = w; g.k = nb;
+            g.A = Linv + i * LB * LB; g.lda = LB;
+            g.B = L + r1 + i0 * ldl; g.ldb = ldl;
+        }
+        g.C = P + i * LB * KP + (back ? nb * LB : 0); g.ldc = LB;
+        g.alpha = -1.0; g.beta = 0.0;
+        hp.push_back(g);
+    }
+    hipError_t e;
+    if (!hp.empty()) {
+        if ((e = hipMemcpyAsync(probs, hp.data(), sizeof(GemmProblem) * hp.size(), hipMemcpyHostToDevice, s)))
+            return e;
+        if ((e = fl_dgemm_batched(s, back, back, probs, (int)hp.size(), LB, q * LB))) return e;
+        // the descriptors live in host memory until the copy has been made
+        if ((e = hipStreamSynchronize(s))) return e;
+    }
+    if (back)
+        band_panel_diag_kernel<true><<<(unsigned)nbk, 256, 0, s>>>(n, q, Linv, P);
+    else
+        band_panel_diag_kernel<false><<<(unsigned)nbk, 256, 0, s>>>(n, q, Linv, P);
+    return hipGetLastError();
+}
+
+// L X = B (back = 0) or L^T X = B (back = 1) for the banded factor, B n x m
+// overwritten, from the panels of fl_band_panels.  bwb >= 0 (forward only):
+// row r of B is zero beyond column r + bwb.
+hipError_t fl_band_solve(hipStream_t s, int64_t n, int64_t q, const double* P, double* B, int64_t ldb, int64_t m,
+                         int back, int64_t bwb) {
+    if (n <= 0 || m <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)FL_DIV_UP(m, BSW);
+    if (back)
+        band_solve_kernel<true><<<grid, 256, 0, s>>>(n, q, P, B, ldb, m, -1);
+    else
+        band_solve_kernel<false><<<grid, 256, 0, s>>>(n, q, P, B, ldb, m, bwb);
     return hipGetLastError();
 }

@@ -350,7 +350,7 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     const int band = opts ? opts->band : 0;
     const int leaf = opts ? opts->leaf : 0;
     hipStream_t s = ctx->stream;
-    DevBuf bL, bC, blinv, bwork, binfo;
+    DevBuf bL, bC, blinv, bwork, binfo, bpan, bprob;
     FL_HIP(ctx, bL.alloc(sizeof(double) * ld * n));
     FL_HIP(ctx, bC.alloc(sizeof(double) * ld * n));
     FL_HIP(ctx, blinv.alloc(sizeof(double) * fl_potrf_linv_elems(n)));
@@ -403,16 +403,20 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     int rc = FL_OK;
     if (banded) {
         // W = L^-1 K, then C = L^-1 W^T (= L^-1 K L^-T, symmetric): two
-        // banded substitutions (the first on the columns where W can be
-        // non-zero: K shares M's pattern, so row r of W ends at column
-        // r + bw); the lower triangle is mirrored so that C is exactly
-        // symmetric
+        // banded substitutions, strip-parallel (the first skips the blocks
+        // where W is zero: K shares M's pattern, so row r of W ends at
+        // column r + bw); the lower triangle is mirrored so that C is
+        // exactly symmetric
         FL_HIP(ctx, bY.alloc(sizeof(double) * (size_t)n * n));
         double* Y = bY.as<double>();
+        FL_HIP(ctx, bpan.alloc(sizeof(double) * (size_t)fl_band_panel_elems(n, qband)));
+        FL_HIP(ctx, bprob.alloc(sizeof(GemmProblem) * (size_t)FL_DIV_UP(n, 128)));
+        FL_HIP(ctx, fl_band_panels(s, n, qband, L, ld, blinv.as<double>(), bpan.as<double>(), 0,
+                                   bprob.as<GemmProblem>()));
         FL_HIP(ctx, hipMemcpyAsync(C, op->K, sizeof(double) * ld * n, hipMemcpyDeviceToDevice, s));
-        FL_HIP(ctx, fl_trsm_lln_band(s, n, qband, L, ld, blinv.as<double>(), C, ld, n, bwork.as<double>(), mbw));
+        FL_HIP(ctx, fl_band_solve(s, n, qband, bpan.as<double>(), C, ld, n, 0, mbw));
         FL_HIP(ctx, fl_transpose(s, n, n, C, ld, Y, n));
-        FL_HIP(ctx, fl_trsm_lln_band(s, n, qband, L, ld, blinv.as<double>(), Y, n, n, bwork.as<double>()));
+        FL_HIP(ctx, fl_band_solve(s, n, qband, bpan.as<double>(), Y, n, n, 0, -1));
         FL_HIP(ctx, fl_copy_matrix(s, n, n, Y, n, C, ld));
         FL_HIP(ctx, fl_mirror_lower(s, n, C, ld));
         FL_HIP(ctx, hipStreamSynchronize(s));
@@ -443,7 +447,9 @@ int fl_eigensolve(fl_op* op, int precision, const fl_eig_opts* opts, fl_eig_info
     }
     FL_HIP(ctx, tm.mark(FL_STAGE_TRSM));
     if (banded) {
-        FL_HIP(ctx, fl_trsm_llt_band(s, n, qband, L, ld, blinv.as<double>(), op->V, ld, n, bwork.as<double>()));
+        FL_HIP(ctx, fl_band_panels(s, n, qband, L, ld, blinv.as<double>(), bpan.as<double>(), 1,
+                                   bprob.as<GemmProblem>()));
+        FL_HIP(ctx, fl_band_solve(s, n, qband, bpan.as<double>(), op->V, ld, n, 1, -1));
     } else if (sparse) {
         // V = X^T Z (X^T upper triangular)
         double* Y = bY.as<double>();

@@ -191,10 +191,11 @@ int fl_pattern_bandwidth(fl_op* op, int64_t* bw);
 // factor, L X = B and L^T X = B on the band only (chol.hip).
 hipError_t fl_potrf_band(hipStream_t s, int64_t n, int64_t q, double* A, int64_t lda, double* Linv, int64_t* info,
                          double* work);
-hipError_t fl_trsm_lln_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
-                            double* B, int64_t ldb, int64_t m, double* work, int64_t bwb = -1);
-hipError_t fl_trsm_llt_band(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
-                            double* B, int64_t ldb, int64_t m, double* work);
+int64_t fl_band_panel_elems(int64_t n, int64_t q);
+hipError_t fl_band_panels(hipStream_t s, int64_t n, int64_t q, const double* L, int64_t ldl, const double* Linv,
+                          double* P, int back, GemmProblem* probs);
+hipError_t fl_band_solve(hipStream_t s, int64_t n, int64_t q, const double* P, double* B, int64_t ldb, int64_t m,
+                         int back, int64_t bwb);
 hipError_t fl_trtri_inplace(hipStream_t s, int64_t n, double* L, int64_t ldl, const double* Linv, double* work);
 hipError_t fl_symmetrize(hipStream_t s, int64_t n, double* A, int64_t lda);
 int fl_sygst_device(fl_ctx* ctx, int64_t n, const double* L, int64_t ldl, const double* Linv, double* K,
