@@ -538,7 +538,7 @@ hipError_t q2_apply_t(hipStream_t s, int64_t n, int b, const double* V2, const d
 //   T = [T_a  -T_a (V_a^T V_b) T_b; 0  T_b]
 // built panel by panel, so that each group costs three GEMMs with inner or
 // outer dimension QG b instead of b.  Groups are applied last first.
-constexpr int QG = 4;
+constexpr int QG = 8;
 
 template <class T>
 hipError_t q1_apply_t(hipStream_t s, int64_t n, int b, const T* V1, int64_t ldv, const T* T1, T* Z, int64_t ldz,
