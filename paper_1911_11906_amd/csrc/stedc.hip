@@ -185,121 +185,365 @@ __global__ __launch_bounds__(256) void merge_sort_kernel(const MergeDesc* __rest
     typ[g.o + i] = (i < g.n1) ? 1 : 3;
 }
 
-// Deflation scan: one workgroup per merge; thread 0 walks the sorted poles,
-// the others stage chunks of the sorted arrays through LDS.
-constexpr int DCH = 2048;
-__global__ __launch_bounds__(256) void merge_deflate_kernel(const MergeDesc* __restrict__ md, const double* __restrict__ e,
+// Deflation: one workgroup per merge.  The result is that of one scan over
+// the sorted poles: a pole with rho' |z| <= tol deflates; among the others,
+// a candidate and the next pole whose Givens rotation leaves a residue
+// |(d_j - d_c) c s| <= tol are rotated (the candidate deflates, the next
+// pole carries z = r and becomes the candidate), else the candidate is kept.
+// Only a rotation changes the state that the next test sees, so the scan
+// runs in chunks of DCH sorted poles: (1) flags and the list of
+// non-deflated poles (prefix sums), (2) every consecutive pair tested in
+// parallel with its original values, (3) one thread walks only the pairs
+// that rotate and the chains of tests that follow a rotation, (4) the kept
+// poles, the deflated ones (in scan order) and the counts are written by
+// prefix sums.  The last pole of a chunk is carried into the next one as
+// the candidate.  Every value is computed by the same expressions in the
+// same order as the one-thread scan, so the results are the same bits.
+constexpr int DCH = 2048;          // sorted poles per chunk
+constexpr int DNT = 512;           // threads
+constexpr int DPT = DCH / DNT;     // chunk positions per thread (contiguous)
+
+struct DeflLds {
+    double sd[DCH], sz[DCH];       // chunk poles and z
+    int64_t sp[DCH];               // their columns
+    int L[DCH];                    // chunk position of non-deflated pole u
+    int U[DCH];                    // u of a non-deflated chunk position
+    int F[DCH];                    // u whose pair (u-1, u) rotates when both are original
+    unsigned char fate[DCH];       // 0 kept (original values), 1 kept (modified), 2 deflated by rotation
+    unsigned char hasrot[DCH];     // a rotation deflates u-1 into u
+    double kd[DCH], kz[DCH];       // modified values of a kept pole
+    double rv[DCH];                // value deflated by the rotation at u
+    int64_t rcol[DCH];             // its column
+    int64_t sc[DNT];               // scan scratch
+    double red[DNT];
+    int keptc;                     // the carried candidate was kept at the chunk's start
+};
+
+// rotation test of candidate (cd, cz) against pole (dj, zj)
+__device__ inline bool defl_rotates(double cd, double cz, double dj, double zj, double tol, double& c, double& sn,
+                                    double& r) {
+    // |z| <= 1 and, not deflated, rho' |z| > tol: the squares neither
+    // overflow nor underflow, so no hypot is needed
+    r = sqrt(cz * cz + zj * zj);
+    const double ir = 1.0 / r;
+    c = zj * ir;
+    sn = cz * ir;
+    const double tt = dj - cd;
+    return fabs(tt * c * sn) <= tol;
+}
+
+// exclusive prefix sum of v over the workgroup's threads (in thread order);
+// *total receives the sum
+__device__ inline int64_t defl_scan(int64_t v, DeflLds& s, int64_t* total) {
+    const int t = threadIdx.x;
+    __syncthreads();
+    s.sc[t] = v;
+    __syncthreads();
+    for (int o = 1; o < DNT; o <<= 1) {
+        const int64_t a = (t >= o) ? s.sc[t - o] : 0;
+        __syncthreads();
+        s.sc[t] += a;
+        __syncthreads();
+    }
+    *total = s.sc[DNT - 1];
+    return s.sc[t] - v;
+}
+
+__global__ __launch_bounds__(DNT) void merge_deflate_kernel(const MergeDesc* __restrict__ md, const double* __restrict__ e,
                                                             double* ds, double* zsrt, const int64_t* __restrict__ perm,
                                                             int* typ, double* dk, double* zk, int64_t* kcol,
                                                             double* dval, int64_t* dcol, int64_t* rot_a, int64_t* rot_b,
                                                             double* rot_c, double* rot_s, int64_t* tpos,
                                                             MergeCounts* cnt) {
-    __shared__ double sd[DCH], sz[DCH];
-    __shared__ int64_t sp[DCH];
-    __shared__ double red[256];
+    __shared__ DeflLds s;
     const MergeDesc g = md[blockIdx.x];
     const int t = threadIdx.x;
     const int64_t o = g.o, N = g.N;
     const double rho2 = 2.0 * fabs(e[o + g.n1 - 1]);
     // tolerance: 8 eps max(max|d|, rho' max|z|)
     double mx = 0.0;
-    for (int64_t i = t; i < N; i += 256) mx = fmax(mx, fmax(fabs(ds[o + i]), rho2 * fabs(zsrt[o + i])));
-    red[t] = mx;
+    for (int64_t i = t; i < N; i += DNT) mx = fmax(mx, fmax(fabs(ds[o + i]), rho2 * fabs(zsrt[o + i])));
+    s.red[t] = mx;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) red[t] = fmax(red[t], red[t + w]);
+    for (int w = DNT / 2; w > 0; w >>= 1) {
+        if (t < w) s.red[t] = fmax(s.red[t], s.red[t + w]);
         __syncthreads();
     }
-    const double tol = 8.0 * EPS * red[0];
-    // scan state (thread 0)
+    const double tol = 8.0 * EPS * s.red[0];
+    // running totals (every thread) and the carried candidate (thread 0)
     int64_t K = 0, nd = 0, nr = 0;
-    int64_t cand = -1, ccol = -1;
-    double cd = 0.0, cz = 0.0;  // candidate's current pole and z
+    bool have = false;
+    int64_t ccol = -1;
+    double cd = 0.0, cz = 0.0;
     for (int64_t base = 0; base < N; base += DCH) {
+        const int lim = (N - base) < DCH ? (int)(N - base) : DCH;
         __syncthreads();
-        for (int q = t; q < DCH; q += 256)
-            if (base + q < N) {
-                sd[q] = ds[o + base + q];
-                sz[q] = zsrt[o + base + q];
-                sp[q] = perm[o + base + q];
+        for (int q = t; q < lim; q += DNT) {
+            s.sd[q] = ds[o + base + q];
+            s.sz[q] = zsrt[o + base + q];
+            s.sp[q] = perm[o + base + q];
+        }
+        __syncthreads();
+        // (1) non-deflated poles of the chunk, in order
+        int cntnd = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int q = t * DPT + j;
+            cntnd += (q < lim && rho2 * fabs(s.sz[q]) > tol) ? 1 : 0;
+        }
+        int64_t Mc64;
+        int u = (int)defl_scan(cntnd, s, &Mc64);
+        const int Mc = (int)Mc64;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int q = t * DPT + j;
+            if (q < lim && rho2 * fabs(s.sz[q]) > tol) {
+                s.L[u] = q;
+                s.U[q] = u;
+                ++u;
             }
+        }
         __syncthreads();
-        if (t == 0) {
-            int64_t lim = (N - base) < DCH ? (N - base) : DCH;
-            for (int64_t q = 0; q < lim; ++q) {
-                const int64_t jj = base + q;
-                const double dj = sd[q], zj = sz[q];
-                const int64_t col = sp[q];
-                if (rho2 * fabs(zj) <= tol) {
-                    dval[o + nd] = dj;
-                    dcol[o + nd] = col;
-                    ++nd;
-                    continue;
+        // (2) pairs (u-1, u) that rotate with original values
+        int cntf = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int v = t * DPT + j;
+            if (v < Mc) {
+                s.fate[v] = 0;
+                s.hasrot[v] = 0;
+            }
+            if (v >= 1 && v < Mc) {
+                double c, sn, r;
+                const int qa = s.L[v - 1], qb = s.L[v];
+                cntf += defl_rotates(s.sd[qa], s.sz[qa], s.sd[qb], s.sz[qb], tol, c, sn, r) ? 1 : 0;
+            }
+        }
+        int64_t Fc64;
+        int f = (int)defl_scan(cntf, s, &Fc64);
+        const int Fc = (int)Fc64;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int v = t * DPT + j;
+            if (v >= 1 && v < Mc) {
+                double c, sn, r;
+                const int qa = s.L[v - 1], qb = s.L[v];
+                if (defl_rotates(s.sd[qa], s.sz[qa], s.sd[qb], s.sz[qb], tol, c, sn, r)) s.F[f++] = v;
+            }
+        }
+        __syncthreads();
+        // (3) the rotations and the chains after them (one thread)
+        if (t == 0) s.keptc = 0;
+        if (t == 0 && Mc > 0) {
+            int settled = -1;      // every u <= settled has its test (u-1, u) decided
+            bool endmod = false;   // a chain reached the chunk's last pole
+            double endd = 0.0, endz = 0.0;
+            // rotation deflating the pole before uu (column colp, state dp, zp)
+            // into uu, then the tests that see uu's modified state
+            auto rotate_from = [&](int uu, int64_t colp, double dp, double zp) {
+                const int qb = s.L[uu];
+                const double dj = s.sd[qb], zj = s.sz[qb];
+                const int64_t col = s.sp[qb];
+                double c, sn, r;
+                defl_rotates(dp, zp, dj, zj, tol, c, sn, r);
+                rot_a[o + nr] = colp;
+                rot_b[o + nr] = col;
+                rot_c[o + nr] = c;
+                rot_s[o + nr] = sn;
+                ++nr;
+                if (typ[o + colp] != typ[o + col]) {
+                    typ[o + colp] = 2;
+                    typ[o + col] = 2;
                 }
-                if (cand < 0) {
-                    cand = jj;
-                    ccol = col;
-                    cd = dj;
-                    cz = zj;
-                    continue;
-                }
-                // |z| <= 1 and, not deflated, rho' |z| > tol: the squares
-                // neither overflow nor underflow, so no hypot is needed
-                const double r = sqrt(cz * cz + zj * zj);
-                const double ir = 1.0 / r;
-                const double c = zj * ir, s = cz * ir;
-                const double tt = dj - cd;
-                const int64_t cp = ccol;
-                if (fabs(tt * c * s) <= tol) {
-                    // rotate columns (cp, col): the candidate deflates, the new pole carries z = r
-                    rot_a[o + nr] = cp;
-                    rot_b[o + nr] = col;
-                    rot_c[o + nr] = c;
-                    rot_s[o + nr] = s;
+                s.hasrot[uu] = 1;
+                s.rv[uu] = c * c * dp + sn * sn * dj;
+                s.rcol[uu] = colp;
+                double mdv = sn * sn * dp + c * c * dj, mzv = r;
+                int v = uu + 1;
+                for (; v < Mc; ++v) {
+                    const int qv = s.L[v];
+                    const double dv = s.sd[qv], zv = s.sz[qv];
+                    const int64_t colv = s.sp[qv];
+                    const int64_t colm = s.sp[s.L[v - 1]];
+                    double c2, s2, r2;
+                    if (!defl_rotates(mdv, mzv, dv, zv, tol, c2, s2, r2)) break;
+                    rot_a[o + nr] = colm;
+                    rot_b[o + nr] = colv;
+                    rot_c[o + nr] = c2;
+                    rot_s[o + nr] = s2;
                     ++nr;
-                    if (typ[o + cp] != typ[o + col]) {
-                        typ[o + cp] = 2;
-                        typ[o + col] = 2;
+                    if (typ[o + colm] != typ[o + colv]) {
+                        typ[o + colm] = 2;
+                        typ[o + colv] = 2;
                     }
-                    dval[o + nd] = c * c * cd + s * s * dj;
-                    dcol[o + nd] = cp;
-                    ++nd;
-                    cand = jj;
-                    ccol = col;
-                    cd = s * s * cd + c * c * dj;
-                    cz = r;
+                    s.fate[v - 1] = 2;
+                    s.hasrot[v] = 1;
+                    s.rv[v] = c2 * c2 * mdv + s2 * s2 * dv;
+                    s.rcol[v] = colm;
+                    mdv = s2 * s2 * mdv + c2 * c2 * dv;
+                    mzv = r2;
+                }
+                if (v < Mc) {
+                    // the test at v keeps pole v-1 with its modified state;
+                    // pole v is original again
+                    s.fate[v - 1] = 1;
+                    s.kd[v - 1] = mdv;
+                    s.kz[v - 1] = mzv;
+                    settled = v;
+                } else {
+                    endmod = true;
+                    endd = mdv;
+                    endz = mzv;
+                    settled = Mc - 1;
+                }
+            };
+            // the candidate carried from the previous chunk against u = 0
+            if (have) {
+                const int q0 = s.L[0];
+                double c, sn, r;
+                if (defl_rotates(cd, cz, s.sd[q0], s.sz[q0], tol, c, sn, r)) {
+                    rotate_from(0, ccol, cd, cz);
                 } else {
                     dk[o + K] = cd;
                     zk[o + K] = cz;
-                    kcol[o + K] = cp;
-                    ++K;
-                    cand = jj;
-                    ccol = col;
-                    cd = dj;
-                    cz = zj;
+                    kcol[o + K] = ccol;
+                    s.keptc = 1;
                 }
             }
+            for (int fi = 0; fi < Fc; ++fi) {
+                const int uu = s.F[fi];
+                if (uu <= settled) continue;
+                // pole uu-1 is original: no chain has reached it
+                const int qa = s.L[uu - 1];
+                s.fate[uu - 1] = 2;
+                rotate_from(uu, s.sp[qa], s.sd[qa], s.sz[qa]);
+            }
+            // the chunk's last pole becomes the carried candidate
+            const int ql = s.L[Mc - 1];
+            ccol = s.sp[ql];
+            cd = endmod ? endd : s.sd[ql];
+            cz = endmod ? endz : s.sz[ql];
+            have = true;
+        }
+        __syncthreads();
+        K += s.keptc;
+        // (4) kept poles u < Mc - 1 (the last one is carried)
+        int cntk = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int v = t * DPT + j;
+            cntk += (v < Mc - 1 && s.fate[v] != 2) ? 1 : 0;
+        }
+        int64_t Kc;
+        int64_t kpos = K + defl_scan(cntk, s, &Kc);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int v = t * DPT + j;
+            if (v < Mc - 1 && s.fate[v] != 2) {
+                const int q = s.L[v];
+                const bool m1 = s.fate[v] == 1;
+                dk[o + kpos] = m1 ? s.kd[v] : s.sd[q];
+                zk[o + kpos] = m1 ? s.kz[v] : s.sz[q];
+                kcol[o + kpos] = s.sp[q];
+                ++kpos;
+            }
+        }
+        K += Kc;
+        // deflated poles in scan order: a pole deflated by its own z, or the
+        // candidate deflated by the rotation into this pole
+        int cntd = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int q = t * DPT + j;
+            if (q < lim) cntd += (!(rho2 * fabs(s.sz[q]) > tol) || s.hasrot[s.U[q]]) ? 1 : 0;
+        }
+        int64_t Dc;
+        int64_t dpos = nd + defl_scan(cntd, s, &Dc);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int q = t * DPT + j;
+            if (q >= lim) continue;
+            if (!(rho2 * fabs(s.sz[q]) > tol)) {
+                dval[o + dpos] = s.sd[q];
+                dcol[o + dpos] = s.sp[q];
+                ++dpos;
+            } else if (s.hasrot[s.U[q]]) {
+                const int v = s.U[q];
+                dval[o + dpos] = s.rv[v];
+                dcol[o + dpos] = s.rcol[v];
+                ++dpos;
+            }
+        }
+        nd += Dc;
+        if (t == 0) s.sc[0] = nr;
+        __syncthreads();
+        nr = s.sc[0];
+    }
+    // the last candidate is kept
+    if (t == 0 && have) {
+        dk[o + K] = cd;
+        zk[o + K] = cz;
+        kcol[o + K] = ccol;
+    }
+    __syncthreads();
+    if (t == 0) s.sc[0] = have ? 1 : 0;
+    __syncthreads();
+    K += s.sc[0];
+    // the rotations' type changes and the kept columns are read back by
+    // other threads: drain, barrier, drop stale vector-L1 lines
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // kept columns by type (1 top only, 2 both, 3 bottom only) and each
+    // one's position in type order: three counts packed in one prefix sum
+    int64_t c1 = 0, c2 = 0, c3 = 0;
+    {
+        int64_t acc = 0;
+        for (int64_t k0 = 0; k0 < K; k0 += DCH) {
+            int64_t pk = 0;
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                const int64_t k = k0 + t * DPT + j;
+                if (k < K) {
+                    const int ty = typ[o + kcol[o + k]];
+                    pk += (int64_t)1 << (21 * (ty - 1));
+                }
+            }
+            int64_t tot;
+            defl_scan(pk, s, &tot);
+            acc += tot;
+        }
+        c1 = acc & 0x1FFFFF;
+        c2 = (acc >> 21) & 0x1FFFFF;
+        c3 = (acc >> 42) & 0x1FFFFF;
+        int64_t run = 0;  // packed counts before the current chunk
+        for (int64_t k0 = 0; k0 < K; k0 += DCH) {
+            int64_t pk = 0;
+            int tys[DPT];
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                const int64_t k = k0 + t * DPT + j;
+                tys[j] = (k < K) ? typ[o + kcol[o + k]] : 0;
+                if (k < K) pk += (int64_t)1 << (21 * (tys[j] - 1));
+            }
+            int64_t tot;
+            int64_t before = run + defl_scan(pk, s, &tot);
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                const int64_t k = k0 + t * DPT + j;
+                if (k < K) {
+                    const int ty = tys[j];
+                    const int64_t p1 = before & 0x1FFFFF, p2 = (before >> 21) & 0x1FFFFF,
+                                  p3 = (before >> 42) & 0x1FFFFF;
+                    tpos[o + k] = (ty == 1) ? p1 : (ty == 2) ? c1 + p2 : c1 + c2 + p3;
+                    before += (int64_t)1 << (21 * (ty - 1));
+                }
+            }
+            run += tot;
         }
     }
     if (t == 0) {
-        if (cand >= 0) {
-            dk[o + K] = cd;
-            zk[o + K] = cz;
-            kcol[o + K] = ccol;
-            ++K;
-        }
-        int64_t c1 = 0, c2 = 0, c3 = 0;
-        for (int64_t k = 0; k < K; ++k) {
-            int ty = typ[o + kcol[o + k]];
-            c1 += ty == 1;
-            c2 += ty == 2;
-            c3 += ty == 3;
-        }
-        int64_t p1 = 0, p2 = c1, p3 = c1 + c2;
-        for (int64_t k = 0; k < K; ++k) {
-            int ty = typ[o + kcol[o + k]];
-            tpos[o + k] = (ty == 1) ? p1++ : (ty == 2) ? p2++ : p3++;
-        }
         MergeCounts mc;
         mc.K = K;
         mc.ndefl = nd;
@@ -767,7 +1011,7 @@ int fl_stedc_device(fl_ctx* ctx, int64_t n, double* d, const double* e, double* 
         const unsigned bx = (unsigned)FL_DIV_UP(Nmax, 256);
         merge_sort_kernel<<<dim3(bx, nm), 256, 0, s>>>(md, d, Z, ldw, e, ds, zsrt, perm, typ);
         FL_HIP(ctx, hipGetLastError());
-        merge_deflate_kernel<<<nm, 256, 0, s>>>(md, e, ds, zsrt, perm, typ, dk, zk, kcol, dval, dcol, ra, rb, rc, rs,
+        merge_deflate_kernel<<<nm, DNT, 0, s>>>(md, e, ds, zsrt, perm, typ, dk, zk, kcol, dval, dcol, ra, rb, rc, rs,
                                                 tpos, cnt);
         FL_HIP(ctx, hipGetLastError());
         merge_rotate_kernel<<<dim3(bx, nm), 256, 0, s>>>(md, cnt, ra, rb, rc, rs, Z, ldw);
