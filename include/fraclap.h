@@ -175,6 +175,19 @@ int fl_eigensolve(fl_op *op, int precision, const fl_eig_opts *opts, fl_eig_info
  * problem (the others are still solved).  Workspace: about 4 n^2 doubles per
  * problem, allocated and released by the call.  Synchronous. */
 int fl_eigensolve_batched(fl_ctx *ctx, int64_t count, fl_op *const *ops, int precision, fl_eig_info *infos);
+/* The same solve in two halves, so that the caller can queue other work
+ * (on other streams) while the launch runs: fl_eigensolve_batched_begin
+ * checks the arguments as above, allocates the workspace and queues the
+ * launch on the context's stream, then returns; *out (host) receives the
+ * handle of the launch in flight, or NULL when count == 0.  The operators
+ * must not be used or destroyed until fl_eigensolve_batched_wait(handle,
+ * infos) has returned: it waits for the launch, fills infos (as above; may
+ * be NULL), releases the workspace and the handle (in every case, errors
+ * included) and returns the status fl_eigensolve_batched would return.
+ * The synchronous call is begin followed by wait. */
+typedef struct fl_batch fl_batch;
+int fl_eigensolve_batched_begin(fl_ctx *ctx, int64_t count, fl_op *const *ops, int precision, fl_batch **out);
+int fl_eigensolve_batched_wait(fl_batch *batch, fl_eig_info *infos);
 /* Copy theta (n) and V (n x n, ld ldv; V may be NULL) out. */
 int fl_eigenpairs(const fl_op *op, double *theta, double *V, int64_t ldv, int on_device);
 /* Install eigenpairs computed elsewhere (resume, or testing the apply path

@@ -27,7 +27,8 @@ FL_GV_AUTO, FL_GV_SQUARE16, FL_GV_SQUARE32, FL_GV_THIN = 0, 1, 2, 3
 EXPORTS = [
     "fl_ctx_create", "fl_ctx_set_stream", "fl_ctx_destroy", "fl_last_error",
     "fl_assemble", "fl_assemble_sparse", "fl_op_from_dense", "fl_op_n", "fl_op_matrices", "fl_op_destroy",
-    "fl_eigensolve", "fl_eigensolve_batched", "fl_eigenpairs", "fl_op_set_eigenpairs",
+    "fl_eigensolve", "fl_eigensolve_batched", "fl_eigensolve_batched_begin", "fl_eigensolve_batched_wait",
+    "fl_eigenpairs", "fl_op_set_eigenpairs",
     "fl_op_save", "fl_op_load", "fl_op_info", "fl_inertia_count", "fl_eigensolve_interval",
     "fl_apply_fractional", "fl_apply_fractional_noalloc", "fl_grad_apply", "fl_apply_graph", "fl_apply_diffusion", "fl_grad_diffusion",
     "fl_gemm_tune", "fl_gemm_tuning_set", "fl_gemm_tuning_count", "fl_gemm_tuning_get", "fl_gemm_tuning_clear",
@@ -105,6 +106,8 @@ def load(path: str = SO_PATH):
         "fl_op_destroy": ([P], None),
         "fl_eigensolve": ([P, i32, ctypes.POINTER(FlEigOpts), ctypes.POINTER(FlEigInfo)], i32),
         "fl_eigensolve_batched": ([P, i64, P, i32, P], i32),
+        "fl_eigensolve_batched_begin": ([P, i64, P, i32, P], i32),
+        "fl_eigensolve_batched_wait": ([P, P], i32),
         "fl_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_op_set_eigenpairs": ([P, P, P, i64, i32], i32),
         "fl_inertia_count": ([P, i64, P, P, ctypes.POINTER(i64)], i32),

@@ -168,6 +168,21 @@ class Context:
             raise FraclapError(rc, self.lib.fl_last_error(self.ptr).decode())
         return out
 
+    def eigensolve_batched_begin(self, ops, precision: str = "fp64") -> "BatchedSolve":
+        """Queue the batched solve of `ops` on the current stream and return
+        at once; `wait()` on the result waits for it and returns the
+        per-problem info dicts.  The operators are not to be used until
+        then."""
+        ops = list(ops)
+        prec = {"fp64": _lib.FL_FP64, "mixed": _lib.FL_MIXED}[precision]
+        arr = (P * max(len(ops), 1))(*[o.ptr for o in ops])
+        h = P()
+        self._sync_stream()
+        rc = self.lib.fl_eigensolve_batched_begin(self.ptr, len(ops), ctypes.cast(arr, P), prec, ctypes.byref(h))
+        if rc != 0:
+            raise FraclapError(rc, self.lib.fl_last_error(self.ptr).decode())
+        return BatchedSolve(self, ops, h)
+
     # ---------------------------------------------------------- stage calls
     def dgemm(self, A, B, C=None, ta=False, tb=False, alpha=1.0, beta=0.0):
         A, B = colmajor(A, self.device), colmajor(B, self.device)
@@ -228,6 +243,26 @@ class Context:
         self._sync_stream()
         self.check(self.lib.fl_dsyevd(self.ptr, n, _ptr(A), _ld(A), band, _ptr(w), _ptr(Z), _ld(Z)))
         return w, Z
+
+
+class BatchedSolve:
+    """A batched solve in flight (from Context.eigensolve_batched_begin)."""
+
+    def __init__(self, ctx: "Context", ops, handle):
+        self.ctx, self.ops, self.h = ctx, ops, handle
+
+    def wait(self):
+        infos = (FlEigInfo * max(len(self.ops), 1))()
+        h, self.h = self.h, None
+        if h is None:
+            raise FraclapError(_lib.FL_ESTATE, "batched solve already waited for")
+        rc = self.ctx.lib.fl_eigensolve_batched_wait(h, ctypes.cast(infos, P))
+        out = [infos[i].as_dict() for i in range(len(self.ops))]
+        for o, d in zip(self.ops, out):
+            o.info = d
+        if rc != 0:
+            raise FraclapError(rc, self.ctx.lib.fl_last_error(self.ctx.ptr).decode())
+        return out
 
 
 class Operator:

@@ -18,6 +18,7 @@
 // LDS).  No workgroup waits on another: the launch ends when the counter
 // passes the last problem.
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -1626,9 +1627,24 @@ __global__ __launch_bounds__(BT) void batched_eig_kernel(const BProb* __restrict
 
 }  // namespace
 
-extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* ops, int precision,
-                                     fl_eig_info* infos) {
+// A launch in flight: its workspace and the problems it writes.
+struct fl_batch {
+    fl_ctx* ctx = nullptr;
+    hipStream_t s = nullptr;
+    std::vector<fl_op*> ops;
+    DevBuf bws, bprobs, border, bnext, bstat;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~fl_batch() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+extern "C" int fl_eigensolve_batched_begin(fl_ctx* ctx, int64_t count, fl_op* const* ops, int precision,
+                                           fl_batch** out) {
     if (!ctx) return FL_EINVAL;
+    if (!out) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: bad arguments");
+    *out = nullptr;
     if (count < 0 || (count > 0 && !ops)) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: bad arguments");
     if (precision != FL_FP64)
         return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: the batched solver runs in FP64 only");
@@ -1646,7 +1662,12 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
             if (ops[j] == op) return fl_fail(ctx, FL_EINVAL, "fl_eigensolve_batched: an operator appears twice");
     }
     FL_HIP(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
+    auto bt = std::make_unique<fl_batch>();
+    fl_batch& B = *bt;
+    B.ctx = ctx;
+    B.s = ctx->stream;
+    B.ops.assign(ops, ops + count);
+    hipStream_t s = B.s;
     // workspace: L, W, A, Z and tau per problem, 256-byte aligned
     std::vector<int64_t> off(count);
     int64_t tot = 0;
@@ -1657,8 +1678,7 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         off[i] = tot;
         tot += al(n * n) * 5 + al(wsz) + al(4 * n) + al(n);
     }
-    DevBuf bws, bprobs, border, bnext, bstat;
-    FL_HIP(ctx, bws.alloc(sizeof(double) * tot));
+    FL_HIP(ctx, B.bws.alloc(sizeof(double) * tot));
     std::vector<BProb> hp(count);
     for (int64_t i = 0; i < count; ++i) {
         fl_op* op = ops[i];
@@ -1667,7 +1687,7 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         if (!op->logtheta) FL_HIP(ctx, hipMalloc(&op->logtheta, sizeof(double) * n));
         if (!op->V) FL_HIP(ctx, hipMalloc(&op->V, sizeof(double) * op->ld * n));
         op->has_eig = 0;
-        double* w = bws.as<double>() + off[i];
+        double* w = B.bws.as<double>() + off[i];
         const int64_t wsz = ormtr_wsz(n);
         BProb& b = hp[i];
         b.n = n;
@@ -1695,56 +1715,65 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ops[a]->n > ops[b]->n; });
-    FL_HIP(ctx, bprobs.alloc(sizeof(BProb) * count));
-    FL_HIP(ctx, border.alloc(sizeof(int) * count));
-    FL_HIP(ctx, bnext.alloc(sizeof(unsigned)));
-    FL_HIP(ctx, bstat.alloc(sizeof(int64_t) * count));
-    FL_HIP(ctx, hipMemcpyAsync(bprobs.p, hp.data(), sizeof(BProb) * count, hipMemcpyHostToDevice, s));
-    FL_HIP(ctx, hipMemcpyAsync(border.p, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-    FL_HIP(ctx, hipMemsetAsync(bnext.p, 0, sizeof(unsigned), s));
-    FL_HIP(ctx, hipMemsetAsync(bstat.p, 0, sizeof(int64_t) * count, s));
+    FL_HIP(ctx, B.bprobs.alloc(sizeof(BProb) * count));
+    FL_HIP(ctx, B.border.alloc(sizeof(int) * count));
+    FL_HIP(ctx, B.bnext.alloc(sizeof(unsigned)));
+    FL_HIP(ctx, B.bstat.alloc(sizeof(int64_t) * count));
+    // (pageable sources: the copies complete before these calls return)
+    FL_HIP(ctx, hipMemcpyAsync(B.bprobs.p, hp.data(), sizeof(BProb) * count, hipMemcpyHostToDevice, s));
+    FL_HIP(ctx, hipMemcpyAsync(B.border.p, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    FL_HIP(ctx, hipMemsetAsync(B.bnext.p, 0, sizeof(unsigned), s));
+    FL_HIP(ctx, hipMemsetAsync(B.bstat.p, 0, sizeof(int64_t) * count, s));
     int cus = 256;
     {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
     }
     const unsigned grid = (unsigned)std::min<int64_t>(count, 2 * (int64_t)cus);
-    hipEvent_t e0, e1;
-    FL_HIP(ctx, hipEventCreate(&e0));
-    FL_HIP(ctx, hipEventCreate(&e1));
-    FL_HIP(ctx, hipEventRecord(e0, s));
+    FL_HIP(ctx, hipEventCreate(&B.e0));
+    FL_HIP(ctx, hipEventCreate(&B.e1));
+    FL_HIP(ctx, hipEventRecord(B.e0, s));
     {
         KScope ks("batched_eig", s);
-        batched_eig_kernel<<<grid, BT, 0, s>>>(bprobs.as<BProb>(), border.as<int>(), (int)count, bnext.as<unsigned>(),
-                                               bstat.as<int64_t>());
+        batched_eig_kernel<<<grid, BT, 0, s>>>(B.bprobs.as<BProb>(), B.border.as<int>(), (int)count,
+                                               B.bnext.as<unsigned>(), B.bstat.as<int64_t>());
     }
-    hipError_t le = hipGetLastError();
-    FL_HIP(ctx, hipEventRecord(e1, s));
+    FL_HIP(ctx, hipGetLastError());
+    FL_HIP(ctx, hipEventRecord(B.e1, s));
+    *out = bt.release();
+    return FL_OK;
+}
+
+extern "C" int fl_eigensolve_batched_wait(fl_batch* b, fl_eig_info* infos) {
+    if (!b) return FL_OK;
+    std::unique_ptr<fl_batch> own(b);
+    fl_ctx* ctx = b->ctx;
+    FL_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t count = (int64_t)b->ops.size();
+    FL_HIP(ctx, hipEventSynchronize(b->e1));
     std::vector<int64_t> st(count);
-    FL_HIP(ctx, hipMemcpyAsync(st.data(), bstat.p, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
-    FL_HIP(ctx, hipStreamSynchronize(s));
+    FL_HIP(ctx, hipMemcpyAsync(st.data(), b->bstat.p, sizeof(int64_t) * count, hipMemcpyDeviceToHost, b->s));
+    FL_HIP(ctx, hipStreamSynchronize(b->s));
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    FL_HIP(ctx, le);
+    (void)hipEventElapsedTime(&ms, b->e0, b->e1);
     int rc = FL_OK;
     for (int64_t i = 0; i < count; ++i) {
+        fl_op* op = b->ops[i];
         int code = FL_OK;
         if (st[i] > 0) code = FL_ENOTSPD;
         if (st[i] < 0) code = FL_ENOCONV;
         if (code == FL_OK) {
-            ops[i]->has_eig = 1;
-            ops[i]->eig_precision = FL_FP64;
-            ops[i]->refine_iters = 0;
-            ops[i]->refine_resid = 0.0;
+            op->has_eig = 1;
+            op->eig_precision = FL_FP64;
+            op->refine_iters = 0;
+            op->refine_resid = 0.0;
         }
         if (infos) {
             infos[i] = fl_eig_info{};
             infos[i].status = code;
             infos[i].index = st[i] > 0 ? st[i] : (st[i] < 0 ? -st[i] : 0);
             infos[i].total_ms = ms;
-            const double n = (double)ops[i]->n;
+            const double n = (double)op->n;
             infos[i].flops_nominal = 9.0 * n * n * n;
         }
         if (code != FL_OK && rc == FL_OK) {
@@ -1757,4 +1786,13 @@ extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* o
         }
     }
     return rc;
+}
+
+extern "C" int fl_eigensolve_batched(fl_ctx* ctx, int64_t count, fl_op* const* ops, int precision,
+                                     fl_eig_info* infos) {
+    if (!ctx) return FL_EINVAL;
+    fl_batch* b = nullptr;
+    const int rc = fl_eigensolve_batched_begin(ctx, count, ops, precision, &b);
+    if (rc != FL_OK) return rc;
+    return fl_eigensolve_batched_wait(b, infos);
 }

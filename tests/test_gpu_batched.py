@@ -95,6 +95,34 @@ def test_batched_matches_single_solve(ctx):
     assert ((ta - tb).abs() / tb).max().item() <= 1e-12
 
 
+def test_batched_begin_wait_matches_sync(ctx):
+    """The asynchronous pair (launch queued on a side stream, other work on
+    the main stream meanwhile, then wait) gives bitwise the synchronous
+    call's eigenpairs; an empty batch gives an empty result."""
+    from paper_1911_11906_amd.api import Operator
+    meshes = inputs.batched_problem_meshes(24, tag=9)
+    meshes = [m for m in meshes if m.n_dof <= 400][:12]
+    note("batched begin/wait, n", [m.n_dof for m in meshes])
+    a = [Operator.assemble(ctx, m) for m in meshes]
+    b = [Operator.assemble(ctx, m) for m in meshes]
+    ia = ctx.eigensolve_batched(a)
+    side = torch.cuda.Stream()
+    X = torch.randn(2048, 2048, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        pending = ctx.eigensolve_batched_begin(b)
+    Y = X @ X  # work on the main stream while the launch runs
+    ib = pending.wait()
+    torch.cuda.synchronize()
+    assert torch.isfinite(Y).all()
+    assert [i["status"] for i in ia] == [i["status"] for i in ib] == [0] * len(meshes)
+    for oa, ob in zip(a, b):
+        ta, Va = oa.eigenpairs()
+        tb, Vb = ob.eigenpairs()
+        assert torch.equal(ta, tb) and torch.equal(Va, Vb)
+    assert ctx.eigensolve_batched_begin([]).wait() == []
+
+
 def test_batched_error_paths(ctx):
     from paper_1911_11906_amd._lib import FL_EINVAL, FL_ENOTSPD, FraclapError
     from paper_1911_11906_amd.api import Operator
