@@ -36,11 +36,12 @@ constexpr int DCL = 32;                    // largest leaf of the divide and con
 constexpr int SU = 8;                      // columns per chunk in the tridiagonalisation's update
 constexpr double EPS = 2.220446049250313e-16;
 
-// The workgroup routines below are kept as separate (noinline) functions:
-// fully inlined into the one persistent kernel, the register pressure (256
-// VGPRs plus spills) produced wrong results in the blocked triangular solve
-// at n > 32, while the same code called as functions, or in a small kernel,
-// is exact.
+// The workgroup routines below are separate (noinline) functions: fully
+// inlined into the persistent kernel they run no faster (same launch time on
+// the 256-problem batch) and the code is several times larger.  (An earlier
+// version, with generic pointers for global memory, gave wrong triangular
+// solves at n > 32 when fully inlined; the current code, global accesses
+// through address-space-1 pointers, passes every batched check either way.)
 
 struct BProb {
     int64_t n, ld;                                      // ld: of K, M and V
