@@ -3,9 +3,11 @@
 // back (V = L^-T Z), all in FP64.
 //
 // Recursive blocking on 128-aligned splits: every leaf is a 128 x 128
-// diagonal block, factored in LDS by one workgroup that also inverts it in
-// place.  Off-diagonal work is GEMM (matrix cores); a triangular solve at a
-// leaf is a GEMM with the stored leaf inverse.
+// diagonal block, factored by one workgroup (the block in registers) that
+// also inverts it.  Off-diagonal work is GEMM (matrix cores); a triangular
+// solve at a leaf is a GEMM with the stored leaf inverse.  A banded M keeps
+// its band: left-looking block steps over the band, and solves with many
+// right-hand sides as one strip-parallel launch (the end of this file).
 #include <algorithm>
 #include "internal.h"
 
