@@ -189,6 +189,7 @@ def half_bandwidth(mesh) -> int:
     import numpy as np
     d = np.asarray(mesh.dof_of_node())[np.asarray(mesh.conn)]
     d = np.where(d >= 0, d, np.nan)
+    d = d[~np.all(np.isnan(d), axis=1)]   # elements with every node constrained
     return int(np.nanmax(np.nanmax(d, axis=1) - np.nanmin(d, axis=1)))
 
 
