@@ -220,14 +220,24 @@ __global__ __launch_bounds__(256) void q2_apply_kernel(int64_t n, int b, int64_t
 // LDS to match it) and, up to a permutation inside each 16-row tile, the
 // output layout of Z -= V (T W).  After a block the upper half of the window
 // is final for the group and goes to memory; the lower half becomes the
-// upper half of the next block.  V of the next block (read straight from
-// the bulge-chasing output) and its T factor are fetched into registers
-// while the current block computes.
+// upper half of the next block.  V of the next block (a contiguous 64 x 64
+// chunk written beside its T factor) and the T factor are fetched into
+// registers while the current block computes.
 constexpr int FB = 64;       // band width of this path
 constexpr int FR = 2 * FB;   // frame rows
 constexpr int LDF = FB + 4;  // LDS stride of the V frame (spreads banks for both read patterns)
 
 __host__ __device__ inline int64_t q2_block_base(int64_t gi, int64_t n0) { return gi * n0 - gi * (gi - 1) / 2; }
+
+// Workgroup barrier that orders LDS only.  Every entry of Z is loaded and
+// stored by one and the same lane (its column fixes the wave, its row modulo
+// 16 the lane), so the waves share nothing through global memory and need
+// not wait for their stores to land: those drain while the next block runs.
+__device__ inline void q2_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Frame-row offset, inside a 16-row tile, of MFMA output index p when lane
 // (lr, lc) register r holds row 4 lr + r.
@@ -238,11 +248,15 @@ template <> __device__ inline int q2_sigma<float>(int p) { return p; }          
 // Forward T factor of every block (g = 64 gi, j): T upper triangular with
 // H(g, j) ... H(g+63, j) = I - V T V^T.  T[t][jj] = -tau_jj sum_k T[t][k] G[k][jj]
 // over t <= k < jj, with G = V^T V.  Output column-major 64 x 64 per block,
-// blocks of group gi from q2_block_base(gi, n0).
+// blocks of group gi from q2_block_base(gi, n0).  The block's reflectors go
+// to VB in the same order, 64 x 64 per block (VB[64 s + i]: entry i of
+// reflector s, zero where the reflector or the entry does not exist), so
+// that the application reads one contiguous, unmasked chunk per block.
 template <class OT>
 __global__ __launch_bounds__(256) void q2_tfactor_kernel(int64_t n, int64_t maxt, int64_t n0,
                                                          const double* __restrict__ V2,
-                                                         const double* __restrict__ tau2, OT* __restrict__ TB) {
+                                                         const double* __restrict__ tau2, OT* __restrict__ TB,
+                                                         OT* __restrict__ VB) {
     const int64_t gi = blockIdx.y, j = blockIdx.x;
     if (j >= n0 - gi) return;
     constexpr int LC = FB + 1;
@@ -260,6 +274,10 @@ __global__ __launch_bounds__(256) void q2_tfactor_kernel(int64_t n, int64_t maxt
         if (lane == 0) tv[s] = ex ? tau2[sw * maxt + j] : 0.0;
     }
     __syncthreads();
+    {
+        OT* vb = VB + (q2_block_base(gi, n0) + j) * (int64_t)(FB * FB);
+        for (int s = wave; s < FB; s += 4) vb[s * FB + lane] = (OT)Vc[s * LC + lane];
+    }
     // G[k][jj] (k < jj): rows s.t. both reflectors are nonzero; thread -> (jj, k mod 4)
     {
         const int jj = lane, q = wave;
@@ -335,52 +353,55 @@ __device__ inline void q2_store4(T* zc, int64_t row0, int64_t n, bool cok, const
 }
 
 template <class T, bool VEC>
-__global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t maxt, int64_t n0,
-                                                         const double* __restrict__ V2, const T* __restrict__ TB,
-                                                         T* __restrict__ Z, int64_t ldz, int64_t ncols) {
+__global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t n0, const T* __restrict__ VB,
+                                                         const T* __restrict__ TB, T* __restrict__ Z, int64_t ldz,
+                                                         int64_t ncols) {
     typedef fl_tile::Mfma<T> MM;
     typedef typename MM::acc acc_t;
-    __shared__ __attribute__((aligned(16))) T Vf[FR * LDF];  // Vf[k*LDF + s] = V[k][s], frame row k
-    __shared__ __attribute__((aligned(16))) T Ts[FB * FB];   // Ts[i + k*FB] = T[i][k]
+    // FP32: every group of four A operands of one lane (r = 0..3) is one
+    // 16-byte LDS read, conflict-free over each 16 lanes: V twice (row-major
+    // Vf for Z -= V W2, reflector-major VW for W = V^T Z) and T transposed.
+    // FP64 keeps single-value reads from Vf and a column-major T.
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr int LDW = FR + 4;                // VW stride (frame rows + 4)
+    constexpr int LDT = F32 ? FB + 4 : FB;     // Ts stride
+    __shared__ __attribute__((aligned(16))) T Vf[FR * LDF];                // Vf[k*LDF + s] = V[k][s], frame row k
+    __shared__ __attribute__((aligned(16))) T VW[F32 ? FB * LDW : 1];     // VW[s*LDW + k] = V[k][s]
+    __shared__ __attribute__((aligned(16))) T Ts[FB * LDT];               // F32: Ts[i*LDT + k], else Ts[i + k*FB] = T[i][k]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int lr = lane >> 4, lc = lane & 15;
     const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + lc;
     const bool cok = col < ncols;
     T* zc = Z + (cok ? col : 0) * ldz;
-    const int64_t nsw = n - 2;
     for (int e = t; e < FR * LDF; e += 256) Vf[e] = T(0);  // off-staircase entries stay zero
+    if constexpr (F32)
+        for (int e = t; e < FB * LDW; e += 256) VW[e] = T(0);
 
-    double pv[16];  // raw reflector entries; masked and converted when staged
-    unsigned pmask = 0;
-    T pt[16];
-    // block (g, j): reflector s = wave + 4 q, entry i = lane -> frame row s + 1 + i.
-    // The loads are unconditional (absent entries read V2[0]); the mask is
-    // applied when the values are staged after the block's products.
+    T pv[16], pt[16];
+    // block (g, j): element t + 256 q of its V chunk is entry i = lane of
+    // reflector s = wave + 4 q, at frame row s + 1 + i.
     auto fetch = [&](int64_t gi, int64_t j) {
-        const int64_t g = gi * FB;
-        pmask = 0;
+        const int64_t off = (q2_block_base(gi, n0) + j) * (int64_t)(FB * FB);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int s = wave + 4 * q;
-            const int64_t sw = g + s;
-            const bool ex = sw < nsw && j < 1 + (n - 3 - sw) / FB;
-            const int64_t r0 = g + 1 + j * FB + s;
-            const bool ok = ex && lane < n - r0;
-            pv[q] = V2[ok ? (sw * maxt + j) * FB + lane : 0];
-            pmask |= (ok ? 1u : 0u) << q;
-        }
-        const T* tb = TB + (q2_block_base(gi, n0) + j) * (int64_t)(FB * FB);
+        for (int q = 0; q < 16; ++q) pv[q] = VB[off + t + 256 * q];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) pt[q] = tb[t + 256 * q];
+        for (int q = 0; q < 16; ++q) pt[q] = TB[off + t + 256 * q];
     };
     auto stage = [&]() {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int s = wave + 4 * q;
-            Vf[(s + 1 + lane) * LDF + s] = ((pmask >> q) & 1u) ? (T)pv[q] : T(0);
+            Vf[(s + 1 + lane) * LDF + s] = pv[q];
+            if constexpr (F32) VW[s * LDW + s + 1 + lane] = pv[q];
         }
 #pragma unroll
-        for (int q = 0; q < 16; ++q) Ts[t + 256 * q] = pt[q];
+        for (int q = 0; q < 16; ++q) {
+            const int e = t + 256 * q;
+            if constexpr (F32)
+                Ts[(e & (FB - 1)) * LDT + e / FB] = pt[q];
+            else
+                Ts[e] = pt[q];
+        }
     };
 
     const int lrow = 4 * lr;
@@ -403,63 +424,103 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t maxt
 #pragma unroll
         for (int wt = 0; wt < 4; ++wt) w[wt] = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < 5; ++d)
+        for (int d = 0; d < 5; ++d) {
+            T a[4][4];  // a[wt][r]
+#pragma unroll
+            for (int wt = 0; wt < 4; ++wt) {
+                const int rt = wt + d;
+                if constexpr (F32) {
+                    const float4 v = *reinterpret_cast<const float4*>(&VW[(16 * wt + lc) * LDW + 16 * rt + lrow]);
+                    a[wt][0] = v.x; a[wt][1] = v.y; a[wt][2] = v.z; a[wt][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[wt][r] = Vf[(16 * rt + lrow + r) * LDF + 16 * wt + lc];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int wt = 0; wt < 4; ++wt) {
                     const int rt = wt + d;
-                    const T a = Vf[(16 * rt + lrow + r) * LDF + 16 * wt + lc];
                     const T bz = rt < 4 ? zt[rt & 3][r] : zb[rt & 3][r];
-                    w[wt] = MM::mma(a, bz, w[wt]);
+                    w[wt] = MM::mma(a[wt][r], bz, w[wt]);
                 }
+        }
         // W2 = T W (T upper triangular)
 #pragma unroll
         for (int wt = 0; wt < 4; ++wt) w2[wt] = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
+        for (int d = 0; d < 4; ++d) {
+            T a[4][4];  // a[wt2][r]
+#pragma unroll
+            for (int wt2 = 0; wt2 + d < 4; ++wt2) {
+                const int wt = wt2 + d;
+                if constexpr (F32) {
+                    const float4 v = *reinterpret_cast<const float4*>(&Ts[(16 * wt2 + lc) * LDT + 16 * wt + lrow]);
+                    a[wt2][0] = v.x; a[wt2][1] = v.y; a[wt2][2] = v.z; a[wt2][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[wt2][r] = Ts[(16 * wt2 + lc) + (16 * wt + MM::row(lr, r)) * FB];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int wt2 = 0; wt2 < 4; ++wt2) {
-                    const int wt = wt2 + d;
-                    if (wt < 4) {
-                        const T a = Ts[(16 * wt2 + lc) + (16 * wt + MM::row(lr, r)) * FB];
-                        w2[wt2] = MM::mma(a, w[wt][r], w2[wt2]);
-                    }
-                }
+                for (int wt2 = 0; wt2 + d < 4; ++wt2) w2[wt2] = MM::mma(a[wt2][r], w[wt2 + d][r], w2[wt2]);
+        }
 #pragma unroll
         for (int wt = 0; wt < 4; ++wt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) w2[wt][r] = -w2[wt][r];
         // Z -= V W2
 #pragma unroll
-        for (int d = 0; d < 5; ++d)
+        for (int d = 0; d < 5; ++d) {
+            T a[4][4];  // a[wt][r]
+#pragma unroll
+            for (int wt = 0; wt < 4; ++wt) {
+                const int rt = wt + d;
+                if constexpr (F32) {
+                    const float4 v = *reinterpret_cast<const float4*>(&Vf[(16 * rt + vsig) * LDF + 16 * wt + lrow]);
+                    a[wt][0] = v.x; a[wt][1] = v.y; a[wt][2] = v.z; a[wt][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[wt][r] = Vf[(16 * rt + vsig) * LDF + 16 * wt + MM::row(lr, r)];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int wt = 0; wt < 4; ++wt) {
                     const int rt = wt + d;
-                    const T a = Vf[(16 * rt + vsig) * LDF + 16 * wt + MM::row(lr, r)];
                     if (rt < 4)
-                        zt[rt & 3] = MM::mma(a, w2[wt][r], zt[rt & 3]);
+                        zt[rt & 3] = MM::mma(a[wt][r], w2[wt][r], zt[rt & 3]);
                     else
-                        zb[rt & 3] = MM::mma(a, w2[wt][r], zb[rt & 3]);
+                        zb[rt & 3] = MM::mma(a[wt][r], w2[wt][r], zb[rt & 3]);
                 }
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC, TAIL>(zc, F + 16 * rt + lrow, n, cok, zt[rt]);
+        }
         if (more) {
             // keep the prefetched rows out of the products: without this
             // ordering point the compiler may move the copy into zb (and the
-            // wait for those loads) in among the matrix instructions
-            T last = zb[3][3];
+            // wait for those loads) in among the matrix instructions.  It
+            // sits before the stores below, so that the wait for the loads
+            // cannot turn into a wait for the stores as well, and it takes
+            // the last product of every tile, so that it cannot be scheduled
+            // (with its wait) before the final product of any of them.
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) asm volatile("" : "+v"(zn[rt][r]) : "v"(last));
-            __syncthreads();  // every wave is done with this block's V and T
+                for (int r = 0; r < 4; ++r)
+                    asm volatile("" : "+v"(zn[rt][r])
+                                 : "v"(zt[0][3]), "v"(zt[1][3]), "v"(zt[2][3]), "v"(zt[3][3]),
+                                   "v"(zb[0][3]), "v"(zb[1][3]), "v"(zb[2][3]), "v"(zb[3][3]));
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) q2_store4<T, VEC, TAIL>(zc, F + 16 * rt + lrow, n, cok, zt[rt]);
+        asm volatile("" ::: "memory");  // issue the stores here, before the staging keeps zt live
+        if (more) {
+            q2_lds_barrier();  // every wave is done with this block's V and T
             stage();
-            __syncthreads();
+            q2_lds_barrier();
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
                 zt[rt] = zb[rt];
@@ -474,14 +535,18 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t maxt
     for (int64_t gi = n0 - 1; gi >= 0; --gi) {
         const int64_t g = gi * FB, nt = n0 - gi;
         fetch(gi, 0);
-        __syncthreads();  // the previous group's last block is done with the LDS
+        q2_lds_barrier();  // the previous group's last block is done with the LDS
         stage();
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
             q2_load4<T, VEC, true>(zc, g + 16 * rt + lrow, n, zt[rt]);
             q2_load4<T, VEC, true>(zc, g + FB + 16 * rt + lrow, n, zb[rt]);
         }
-        __syncthreads();
+        // wait for the window loads here: a wait for them carried into the
+        // blocks would, in every block, stall the products until that
+        // block's prefetch has landed
+        __builtin_amdgcn_s_waitcnt(0);
+        q2_lds_barrier();
         // blocks whose window and prefetched rows lie inside the matrix
         const int64_t nfull = n - g >= 3 * FB ? (n - g - 3 * FB) / FB + 1 : 0;
         int64_t j = 0;
@@ -502,16 +567,17 @@ hipError_t q2_apply_t(hipStream_t s, int64_t n, int b, const double* V2, const d
     const int64_t nsw = n - 2;
     if (b == FB) {
         const int64_t n0 = 1 + (n - 3) / FB;  // groups, and tasks of the first sweep of group 0
-        q2_tfactor_kernel<T><<<dim3((unsigned)n0, (unsigned)n0), 256, 0, s>>>(n, maxt, n0, V2, tau2, work);
+        T* VB = work + q2_block_base(n0, n0) * FB * FB;
+        q2_tfactor_kernel<T><<<dim3((unsigned)n0, (unsigned)n0), 256, 0, s>>>(n, maxt, n0, V2, tau2, work, VB);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const bool vec = (reinterpret_cast<uintptr_t>(Z) % 16 == 0) && ((ldz * (int64_t)sizeof(T)) % 16 == 0);
         const unsigned grid = (unsigned)FL_DIV_UP(ncols, 64);
         KScope ks("q2_apply", s);
         if (vec)
-            q2_apply64_kernel<T, true><<<grid, 256, 0, s>>>(n, maxt, n0, V2, work, Z, ldz, ncols);
+            q2_apply64_kernel<T, true><<<grid, 256, 0, s>>>(n, n0, VB, work, Z, ldz, ncols);
         else
-            q2_apply64_kernel<T, false><<<grid, 256, 0, s>>>(n, maxt, n0, V2, work, Z, ldz, ncols);
+            q2_apply64_kernel<T, false><<<grid, 256, 0, s>>>(n, n0, VB, work, Z, ldz, ncols);
         return hipGetLastError();
     }
     T* VB = work;
@@ -596,7 +662,7 @@ hipError_t q1_apply_t(hipStream_t s, int64_t n, int b, const T* V1, int64_t ldv,
 int64_t fl_q2_t_elems(int64_t n, int b, int64_t maxt) {
     if (b == FB && n >= 3) {
         const int64_t n0 = 1 + (n - 3) / FB;
-        return q2_block_base(n0, n0) * FB * FB + 4;  // T factors of every block
+        return 2 * q2_block_base(n0, n0) * FB * FB + 4;  // T factors and reflectors of every block
     }
     return maxt * (VBLK + TBLK) + 4;
 }
