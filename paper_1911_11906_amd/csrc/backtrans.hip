@@ -358,22 +358,29 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t n0, 
                                                          int64_t ncols) {
     typedef fl_tile::Mfma<T> MM;
     typedef typename MM::acc acc_t;
-    // FP32: every group of four A operands of one lane (r = 0..3) is one
-    // 16-byte LDS read, conflict-free over each 16 lanes: V twice (row-major
-    // Vf for Z -= V W2, reflector-major VW for W = V^T Z) and T transposed.
-    // FP64 keeps single-value reads from Vf and a column-major T.
+    // The four A operands of one lane in one 16 x 16 tile pair (r = 0..3)
+    // are contiguous in LDS, read as 16-byte groups that are conflict-free
+    // over each 16 lanes.  FP32: V twice (row-major Vf for Z -= V W2,
+    // reflector-major VW for W = V^T Z) and T transposed.  FP64 (whose MFMA
+    // output row of lane (lr, r) is lr + 4 r, not 4 lr + r): row-major Vf and
+    // transposed T with the columns of every 16-wide tile permuted by
+    // pcol, so that logical column lr + 4 r sits at 4 lr + r; W = V^T Z
+    // reads single values (row stride 132 words: at most two lanes per
+    // bank).
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int LDW = FR + 4;                // VW stride (frame rows + 4)
-    constexpr int LDT = F32 ? FB + 4 : FB;     // Ts stride
-    __shared__ __attribute__((aligned(16))) T Vf[FR * LDF];                // Vf[k*LDF + s] = V[k][s], frame row k
+    constexpr int LDV = F32 ? LDF : FB + 2;    // Vf stride
+    constexpr int LDT = FB + (F32 ? 4 : 2);    // Ts stride
+    __shared__ __attribute__((aligned(16))) T Vf[FR * LDV];                // Vf[k*LDV + pcol(s)] = V[k][s], frame row k
     __shared__ __attribute__((aligned(16))) T VW[F32 ? FB * LDW : 1];     // VW[s*LDW + k] = V[k][s]
-    __shared__ __attribute__((aligned(16))) T Ts[FB * LDT];               // F32: Ts[i*LDT + k], else Ts[i + k*FB] = T[i][k]
+    __shared__ __attribute__((aligned(16))) T Ts[FB * LDT];               // Ts[i*LDT + pcol(k)] = T[i][k]
+    auto pcol = [](int c) { return F32 ? c : (c & ~15) | (4 * (c & 3) + ((c >> 2) & 3)); };
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int lr = lane >> 4, lc = lane & 15;
     const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + lc;
     const bool cok = col < ncols;
     T* zc = Z + (cok ? col : 0) * ldz;
-    for (int e = t; e < FR * LDF; e += 256) Vf[e] = T(0);  // off-staircase entries stay zero
+    for (int e = t; e < FR * LDV; e += 256) Vf[e] = T(0);  // off-staircase entries stay zero
     if constexpr (F32)
         for (int e = t; e < FB * LDW; e += 256) VW[e] = T(0);
 
@@ -391,16 +398,13 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t n0, 
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int s = wave + 4 * q;
-            Vf[(s + 1 + lane) * LDF + s] = pv[q];
+            Vf[(s + 1 + lane) * LDV + pcol(s)] = pv[q];
             if constexpr (F32) VW[s * LDW + s + 1 + lane] = pv[q];
         }
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = t + 256 * q;
-            if constexpr (F32)
-                Ts[(e & (FB - 1)) * LDT + e / FB] = pt[q];
-            else
-                Ts[e] = pt[q];
+            Ts[(e & (FB - 1)) * LDT + pcol(e / FB)] = pt[q];
         }
     };
 
@@ -434,7 +438,7 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t n0, 
                     a[wt][0] = v.x; a[wt][1] = v.y; a[wt][2] = v.z; a[wt][3] = v.w;
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) a[wt][r] = Vf[(16 * rt + lrow + r) * LDF + 16 * wt + lc];
+                    for (int r = 0; r < 4; ++r) a[wt][r] = Vf[(16 * rt + lrow + r) * LDV + 16 * wt + pcol(lc)];
                 }
             }
 #pragma unroll
@@ -455,12 +459,14 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t n0, 
 #pragma unroll
             for (int wt2 = 0; wt2 + d < 4; ++wt2) {
                 const int wt = wt2 + d;
+                const T* src = &Ts[(16 * wt2 + lc) * LDT + 16 * wt + lrow];  // column pcol(16 wt + row(lr, r))
                 if constexpr (F32) {
-                    const float4 v = *reinterpret_cast<const float4*>(&Ts[(16 * wt2 + lc) * LDT + 16 * wt + lrow]);
+                    const float4 v = *reinterpret_cast<const float4*>(src);
                     a[wt2][0] = v.x; a[wt2][1] = v.y; a[wt2][2] = v.z; a[wt2][3] = v.w;
                 } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) a[wt2][r] = Ts[(16 * wt2 + lc) + (16 * wt + MM::row(lr, r)) * FB];
+                    const double2 v0 = *reinterpret_cast<const double2*>(src);
+                    const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+                    a[wt2][0] = v0.x; a[wt2][1] = v0.y; a[wt2][2] = v1.x; a[wt2][3] = v1.y;
                 }
             }
 #pragma unroll
@@ -479,12 +485,14 @@ __global__ __launch_bounds__(256) void q2_apply64_kernel(int64_t n, int64_t n0, 
 #pragma unroll
             for (int wt = 0; wt < 4; ++wt) {
                 const int rt = wt + d;
+                const T* src = &Vf[(16 * rt + vsig) * LDV + 16 * wt + lrow];  // column pcol(16 wt + row(lr, r))
                 if constexpr (F32) {
-                    const float4 v = *reinterpret_cast<const float4*>(&Vf[(16 * rt + vsig) * LDF + 16 * wt + lrow]);
+                    const float4 v = *reinterpret_cast<const float4*>(src);
                     a[wt][0] = v.x; a[wt][1] = v.y; a[wt][2] = v.z; a[wt][3] = v.w;
                 } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) a[wt][r] = Vf[(16 * rt + vsig) * LDF + 16 * wt + MM::row(lr, r)];
+                    const double2 v0 = *reinterpret_cast<const double2*>(src);
+                    const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+                    a[wt][0] = v0.x; a[wt][1] = v0.y; a[wt][2] = v1.x; a[wt][3] = v1.y;
                 }
             }
 #pragma unroll
