@@ -206,6 +206,24 @@ def test_eigensolve_banded_mass_q1(ctx, oracle_mod, precision):
     op.close()
 
 
+def test_eigensolve_mixed_odd_order_q1(ctx, oracle_mod):
+    """Q1 23 x 21 (n = 483, odd): the FP32 eigenvector columns are not
+    16-byte aligned, so the Q2 application takes its element-wise row loads
+    and stores, and the last block reflectors and the last 64-column group
+    are ragged; the exact discrete spectrum, V^T M V = I and the residuals."""
+    note("eigensolve mixed q1 23x21")
+    from paper_1911_11906_amd.api import Operator
+    mesh = inputs.q1_rectangle(23, 21)
+    assert mesh.n_dof % 2 == 1
+    op = Operator.assemble(ctx, mesh)
+    op.eigensolve("mixed")
+    th, V = op.eigenpairs()
+    th, V = to_np(th), to_np(V)
+    K, M = oracle_mod.assemble(mesh)
+    check_pencil(K, M, th, V, Q1Rectangle(23, 21).eigenvalues(), 1e-12, 1e-11)
+    op.close()
+
+
 def test_eigensolve_banded_mass_p1(ctx, oracle_mod):
     """P1 polygon with holes (n = 2000): banded mass path against the
     library eigensolver step on the oracle's pencil."""
