@@ -75,74 +75,136 @@ __device__ void invert_lower_rows(const double* L, const double* rdiag, double* 
 // Factor the nb x nb (nb <= 128) diagonal block at A (ld lda); write L back
 // (strict upper triangle of the block zeroed) and its inverse (128 x 128,
 // zero padded) to Linv.  info: first failing global pivot (1-based) if unset.
-// The block lives in registers: thread t holds row t % 128 of the columns
-// t / 128 + 8 k (k < 16), so a wave holds one column group and its reads of
-// the pivot column are broadcasts.  Step j: the owner of column j publishes
-// it in LDS (two buffers by parity, so one barrier per step), and every
-// thread updates its entries of the columns c > j, S_ic -= S_ij S_cj / d_j,
-// keeping the columns unscaled; L = column c / sqrt(d_c) is formed at the
-// end.  A pivot d_j <= 0 is reported and replaced by 1 (every thread derives
-// the same replacement from the value it reads).  Padding rows and columns
-// (>= nb) are the identity, which keeps the inverse well defined.
-__global__ __launch_bounds__(LT) void potrf_leaf_kernel(double* A, int64_t lda, int nb, int64_t goff,
-                                                        double* Linv, int64_t* info) {
-    __shared__ double S[LB * LB];     // L, column-major with ld LB, for the inverse
-    __shared__ double colj[2][LB];    // pivot column of step j in buffer j % 2
-    __shared__ double dg[LB];         // pivots (1 for padding)
-    __shared__ double rd[LB];         // 1 / L_jj
+// 256 threads; thread t holds the 8 x 8 register block (rows 8 (t mod 16)..,
+// columns 8 (t / 16)..), so a step reads 16 values from LDS per thread
+// (32 KB per step for the workgroup, where one value per entry held would
+// read 128 KB) for 64 multiply-adds.  Step j: the owners of column j publish
+// it in LDS (two buffers by parity, one barrier per step) and every block
+// with columns c > j updates S_ic -= S_ij S_cj / d_j, keeping the columns
+// unscaled; L = column c / sqrt(d_c) is formed at the end.  A pivot d_j <= 0
+// is reported and replaced by 1 (every thread derives the same replacement
+// from the value it reads).  Padding rows and columns (>= nb) are the
+// identity, which keeps the inverse well defined.  The inverse solves
+// L X = I by rows in the same layout: row i of X is final once rows < i are
+// (X_i = (e_i - sum_{k<i} L_ik X_k) / L_ii); it is published and every block
+// below subtracts L_mi X_i from its rows m > i.
+constexpr int LT2 = 256;  // threads of the leaf kernel
+__global__ __launch_bounds__(LT2) void potrf_leaf_kernel(double* A, int64_t lda, int nb, int64_t goff,
+                                                         double* Linv, int64_t* info) {
+    __shared__ __attribute__((aligned(16))) double S[LB * LB];  // L, column-major with ld LB
+    __shared__ __attribute__((aligned(16))) double pv[2][LB];   // published column (factor) or row (inverse), by parity
+    __shared__ double dg[LB];                                   // pivots (1 for padding)
+    __shared__ double rd[LB];                                   // 1 / L_jj
     const int t = threadIdx.x;
-    const int i = t & (LB - 1), cg = t >> 7;
-    const int cgu = __builtin_amdgcn_readfirstlane(cg);  // the same on every lane of a wave
-    constexpr int NK = LB / (LT / LB);  // 16 columns per thread
-    double X[NK];
+    const int br = t & 15, bc = t >> 4;  // row block, column block
+    const int i0 = 8 * br, c0 = 8 * bc;
+    double X[8][8];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        const int c = cg + 8 * k;
-        X[k] = (i < nb && c < nb) ? ((i >= c) ? A[i + (int64_t)c * lda] : 0.0) : ((i == c) ? 1.0 : 0.0);
-    }
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int i = i0 + r, c = c0 + cc;
+            X[r][cc] = (i < nb && c < nb) ? ((i >= c) ? A[i + (int64_t)c * lda] : 0.0) : ((i == c) ? 1.0 : 0.0);
+        }
     if (t < LB) dg[t] = 1.0;
     bool bad = false;  // thread 0 only
-    for (int j = 0; j < nb; ++j) {
-        double* cj = colj[j & 1];
-        if (cg == (j & 7)) {
-            double v = X[0];
+    // 8 consecutive doubles of pv starting at a multiple of 8
+    auto read8 = [&](const double* p, double (&v)[8]) {
 #pragma unroll
-            for (int k = 1; k < NK; ++k)
-                if (k == (j >> 3)) v = X[k];
-            cj[i] = v;
+        for (int h = 0; h < 4; ++h) {
+            const double2 w = *reinterpret_cast<const double2*>(p + 2 * h);
+            v[2 * h] = w.x;
+            v[2 * h + 1] = w.y;
         }
-        __syncthreads();
-        const double d = cj[j];
-        const double deff = (d > 0.0) ? d : 1.0;
-        if (t == 0) {
-            if (!(d > 0.0) && !bad && *info == 0) *info = goff + j + 1;
-            bad = bad || !(d > 0.0);
-            dg[j] = deff;
-        }
-        const double sij = cj[i] * (1.0 / deff);
-        // columns c <= j are finished: skipped (c is uniform over the wave)
+    };
+    for (int jb = 0; jb < LB / 8; ++jb) {
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const int c = cgu + 8 * k;
-            if (c > j) X[k] = fma(-sij, cj[c], X[k]);
+        for (int jj = 0; jj < 8; ++jj) {
+            const int j = 8 * jb + jj;
+            if (j >= nb) break;  // uniform
+            double* cj = pv[j & 1];
+            if (bc == jb) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) cj[i0 + r] = X[r][jj];
+            }
+            __syncthreads();
+            const double d = cj[j];
+            const double deff = (d > 0.0) ? d : 1.0;
+            if (t == 0) {
+                if (!(d > 0.0) && !bad && *info == 0) *info = goff + j + 1;
+                bad = bad || !(d > 0.0);
+                dg[j] = deff;
+            }
+            // blocks left of or at column j (except j's own later columns) are finished
+            if (bc >= jb && br >= bc) {
+                double prow[8], pcol[8];
+                read8(cj + i0, prow);
+                read8(cj + c0, pcol);
+                const double rinv = 1.0 / deff;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const double sij = prow[r] * rinv;
+#pragma unroll
+                    for (int cc = 0; cc < 8; ++cc)
+                        if (bc > jb || cc > jj) X[r][cc] = fma(-sij, pcol[cc], X[r][cc]);
+                }
+            }
         }
     }
     __syncthreads();
     if (t < LB) {
         const double y = sqrt(dg[t]);
-        colj[0][t] = y;
+        pv[0][t] = y;
         rd[t] = 1.0 / y;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        const int c = cg + 8 * k;
-        const double v = (i > c) ? X[k] / colj[0][c] : ((i == c) ? colj[0][c] : 0.0);
-        S[i + c * LB] = v;
-        if (i < nb && c < nb) A[i + (int64_t)c * lda] = v;
-    }
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int i = i0 + r, c = c0 + cc;
+            const double v = (i > c) ? X[r][cc] / pv[0][c] : ((i == c) ? pv[0][c] : 0.0);
+            S[i + c * LB] = v;
+            if (i < nb && c < nb) A[i + (int64_t)c * lda] = v;
+            X[r][cc] = (i == c) ? 1.0 : 0.0;  // the inverse's right-hand side I
+        }
     __syncthreads();
-    invert_lower_rows(S, rd, Linv, t);
+    // rows of X = L^-1, ascending; X holds the partial right-hand sides
+    for (int ib = 0; ib < LB / 8; ++ib) {
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii) {
+            const int i = 8 * ib + ii;
+            double* xi = pv[i & 1];
+            if (br == ib) {
+                const double s = rd[i];
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc) {
+                    X[ii][cc] *= s;
+                    xi[c0 + cc] = X[ii][cc];
+                }
+            }
+            __syncthreads();
+            // rows m > i of blocks on or below the diagonal: X_m -= L_mi X_i
+            if (br >= ib && br >= bc && c0 <= i) {
+                double lcol[8], xrow[8];
+                read8(S + i * LB + i0, lcol);
+                read8(xi + c0, xrow);
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (br > ib || r > ii) {
+#pragma unroll
+                        for (int cc = 0; cc < 8; ++cc) X[r][cc] = fma(-lcol[r], xrow[cc], X[r][cc]);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int i = i0 + r, c = c0 + cc;
+            Linv[i + c * LB] = (c <= i) ? X[r][cc] : 0.0;
+        }
 }
 
 // Inverses of the 128 x 128 diagonal blocks of an existing lower factor L
@@ -324,7 +386,7 @@ int64_t fl_trsm_work_elems(int64_t n, int64_t other) { (void)n; return (int64_t)
 hipError_t fl_potrf(hipStream_t s, int64_t n, double* A, int64_t lda, double* Linv, int64_t* info, double* work) {
     if (n <= 0) return hipSuccess;
     if (n <= LB) {
-        potrf_leaf_kernel<<<1, LT, 0, s>>>(A, lda, (int)n, 0, Linv, info);
+        potrf_leaf_kernel<<<1, LT2, 0, s>>>(A, lda, (int)n, 0, Linv, info);
         return hipGetLastError();
     }
     // The global pivot offset of each leaf is needed in the status; recurse
@@ -333,7 +395,7 @@ hipError_t fl_potrf(hipStream_t s, int64_t n, double* A, int64_t lda, double* Li
         static hipError_t run(hipStream_t s, int64_t n, double* A, int64_t lda, double* Linv, int64_t* info,
                               double* work, int64_t goff) {
             if (n <= LB) {
-                potrf_leaf_kernel<<<1, LT, 0, s>>>(A, lda, (int)n, goff, Linv, info);
+                potrf_leaf_kernel<<<1, LT2, 0, s>>>(A, lda, (int)n, goff, Linv, info);
                 return hipGetLastError();
             }
             int64_t n1 = split_point(n), n2 = n - n1;
@@ -446,7 +508,7 @@ hipError_t fl_potrf_band(hipStream_t s, int64_t n, int64_t q, double* A, int64_t
         if (w > 0 && (e = fl_dgemm(s, 0, 1, nb, nb, w, -1.0, A + j0 + k0 * lda, lda, A + j0 + k0 * lda, lda, 1.0, Ajj,
                                    lda, 1)))
             return e;
-        potrf_leaf_kernel<<<1, LT, 0, s>>>(Ajj, lda, (int)nb, j0, Linv + j * LB * LB, info);
+        potrf_leaf_kernel<<<1, LT2, 0, s>>>(Ajj, lda, (int)nb, j0, Linv + j * LB * LB, info);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t r1 = j0 + nb, mr = std::min<int64_t>(q * LB, n - r1);  // rows of the blocks below
         if (mr <= 0) continue;
